@@ -1,0 +1,126 @@
+/*
+ * helmz -- complex-double Krylov solves of sparse Helmholtz systems on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations are those of Cheik Ahamed & Magoules, "Accelerated solution
+ * of Helmholtz equation with Iterative Krylov Methods on GPU": complex
+ * sparse matrix-vector product on CSR storage (Sections 3.2 and 6), the
+ * complex BLAS-1 operations dot product, norm and axpy (Section 5), and the
+ * preconditioned BiCGStab solve of A x = b with zero initial guess, a
+ * residual tolerance and an iteration limit (Section 7).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Complex numbers are (re, im) pairs with no padding: the paper's complex
+ *    structure (Section 4), the same layout as torch.complex128 /
+ *    torch.complex64.  hz_c128 arrays must be 16-byte aligned, hz_c64 arrays
+ *    8-byte aligned.
+ *  - CSR is 0-based: row i occupies [row_ptr[i], row_ptr[i+1]) of col_idx
+ *    and vals (the paper's 1-based IA/JA/AA).  row_ptr has n+1 int32
+ *    entries with row_ptr[0] = 0 and row_ptr[n] = nnz; 0 <= col_idx < n.
+ *    Unless HZ_VALIDATE is passed, malformed CSR is undefined behaviour.
+ *  - Every array pointer is a DEVICE pointer owned by the caller.  The
+ *    library never frees or retains them.  Work is enqueued on `stream`
+ *    (a hipStream_t; NULL means the default stream).
+ *  - Return value: HZ_OK (0), a positive solver status, or a negative error.
+ *    No call aborts or throws.  hz_strerror() names every code.
+ *  - A handle holds per-device scratch (reduction partials, device scalars,
+ *    pinned host words); calls that share a handle must be issued from one
+ *    host thread at a time.  A handle is bound to the device that was
+ *    current when it was created.
+ */
+#ifndef HELMZ_H
+#define HELMZ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { double re, im; } hz_c128;
+typedef struct { float re, im; } hz_c64;
+typedef struct hz_handle hz_handle;
+typedef void *hz_stream; /* hipStream_t */
+
+/* status and error codes */
+enum {
+    HZ_OK = 0,
+    HZ_NOT_CONVERGED = 1, /* maxiter reached; x holds the last iterate      */
+    HZ_BREAKDOWN = 2,     /* rho, <rhat,v>, <t,t> or omega became exactly 0 */
+    HZ_NONFINITE = 3,     /* a NaN/Inf scalar appeared                      */
+    HZ_ERR_INVALID = -1,  /* bad argument or malformed CSR (validated)      */
+    HZ_ERR_HIP = -2,      /* a HIP runtime call failed                      */
+    HZ_ERR_WORKSPACE = -3 /* workspace missing, misaligned or too small     */
+};
+
+/* solver flags (bitwise or) */
+#define HZ_PRECOND_NONE 0x0
+#define HZ_PRECOND_JACOBI 0x1 /* right preconditioner M = diag(A)          */
+#define HZ_X0_ZERO 0x4        /* ignore x on entry, start from 0 (paper)   */
+#define HZ_VALIDATE 0x8       /* check CSR structure on the device first   */
+
+typedef struct {
+    int status;              /* HZ_OK / HZ_NOT_CONVERGED / HZ_BREAKDOWN / HZ_NONFINITE */
+    int iterations;          /* BiCGStab iterations (inner total for mixed) */
+    int outer_steps;         /* refinement corrections (mixed only)         */
+    int reserved;
+    double relres_recursive; /* last ||r||/||b|| of the recursive residual  */
+    double relres_true;      /* ||b - A x|| / ||b||, recomputed in FP64     */
+} hz_solve_info;
+
+/* Handle with scratch for the standalone reductions and the solvers.
+ * Allocates device memory once; returns HZ_ERR_HIP if that fails. */
+int hz_handle_create(hz_handle **handle);
+int hz_handle_destroy(hz_handle *handle);
+
+/* Text for any return code of this library (never NULL). */
+const char *hz_strerror(int code);
+
+/*
+ * y = A x, complex128 CSR sparse matrix-vector product (Sections 3.2, 6).
+ * x and y hold n entries and must not overlap.  n = 0 is a no-op.
+ */
+int csr_zspmv(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+              const hz_c128 *vals, const hz_c128 *x, hz_c128 *y);
+
+/* Same product with complex64 values, vectors and arithmetic. */
+int csr_cspmv(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+              const hz_c64 *vals, const hz_c64 *x, hz_c64 *y);
+
+/*
+ * *out = sum_i conj(x_i) y_i (Section 5, dot product; the first argument is
+ * conjugated).  out is a device pointer; nothing is synchronised.  The sum
+ * order is fixed for a given n, so repeated calls are bitwise identical.
+ */
+int zdotc(hz_handle *handle, hz_stream stream, int n, const hz_c128 *x, const hz_c128 *y, hz_c128 *out);
+
+/* *out = ||x||_2 = sqrt(sum |x_i|^2) (Section 5, norm), device pointer. */
+int dznrm2(hz_handle *handle, hz_stream stream, int n, const hz_c128 *x, double *out);
+
+/* y <- alpha x + y (Section 5, complex axpy); alpha by value. */
+int zaxpy(hz_handle *handle, hz_stream stream, int n, hz_c128 alpha, const hz_c128 *x, hz_c128 *y);
+
+/* Device workspace (bytes) that zbicgstab_solve needs for this n, nnz, flags. */
+size_t zbicgstab_workspace_bytes(int n, int nnz, int flags);
+
+/*
+ * Solve A x = b by preconditioned BiCGStab (Section 7: the paper's
+ * P-BiCGSTAB), complex128.  Right preconditioner M = I or M = diag(A)
+ * (HZ_PRECOND_JACOBI).  The shadow residual is the initial residual;
+ * convergence is ||r|| / ||b|| <= rtol on the recursive residual, tested
+ * after the half step (s) and after the full step (r).  x is in/out: the
+ * initial guess on entry (zero if HZ_X0_ZERO), the solution on return.
+ * ws is a device buffer of at least zbicgstab_workspace_bytes(n, nnz,
+ * flags) bytes, 256-byte aligned, owned by the caller.  The call
+ * synchronises `stream` and fills *info (host memory).  Returns the solver
+ * status (also in info->status) or a negative error.
+ */
+int zbicgstab_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+                    const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol, int maxiter, int flags, void *ws,
+                    size_t ws_bytes, hz_solve_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELMZ_H */

@@ -1,0 +1,26 @@
+"""helmz: complex-double BiCGStab for sparse Helmholtz systems on MI355X.
+
+The compute path is the C-ABI library ``libhelmz.so`` (hand-written HIP for
+gfx950, declared in ``include/helmz.h``); this package is its Python binding.
+"""
+
+from .binding import (  # noqa: F401
+    BREAKDOWN,
+    NONFINITE,
+    NOT_CONVERGED,
+    OK,
+    PRECOND_JACOBI,
+    PRECOND_NONE,
+    VALIDATE,
+    X0_ZERO,
+    csr_cspmv,
+    csr_zspmv,
+    dznrm2,
+    handle,
+    workspace,
+    zaxpy,
+    zbicgstab_solve,
+    zbicgstab_workspace_bytes,
+    zdotc,
+)
+from ._lib import HelmzError, lib_path, load  # noqa: F401

@@ -1,0 +1,88 @@
+"""ctypes loader for ``libhelmz.so``.
+
+The library is required: there is no CPU fallback.  If it is missing it is
+built once from the in-tree sources with hipcc; if that fails, import-time
+use raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+from . import build as _build
+
+_lock = threading.Lock()
+_lib = None
+
+
+class HzInfo(C.Structure):
+    _fields_ = [
+        ("status", C.c_int),
+        ("iterations", C.c_int),
+        ("outer_steps", C.c_int),
+        ("reserved", C.c_int),
+        ("relres_recursive", C.c_double),
+        ("relres_true", C.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {
+            "status": self.status,
+            "iterations": self.iterations,
+            "outer_steps": self.outer_steps,
+            "relres_recursive": self.relres_recursive,
+            "relres_true": self.relres_true,
+        }
+
+
+class HzC128(C.Structure):
+    _fields_ = [("re", C.c_double), ("im", C.c_double)]
+
+
+# name -> (restype, argtypes); mirrors include/helmz.h
+P, I, D, SZ = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+SIGNATURES = {
+    "hz_handle_create": (I, [C.POINTER(C.c_void_p)]),
+    "hz_handle_destroy": (I, [P]),
+    "hz_strerror": (C.c_char_p, [I]),
+    "csr_zspmv": (I, [P, P, I, I, P, P, P, P, P]),
+    "csr_cspmv": (I, [P, P, I, I, P, P, P, P, P]),
+    "zdotc": (I, [P, P, I, P, P, P]),
+    "dznrm2": (I, [P, P, I, P, P]),
+    "zaxpy": (I, [P, P, I, HzC128, P, P]),
+    "zbicgstab_workspace_bytes": (SZ, [I, I, I]),
+    "zbicgstab_solve": (I, [P, P, I, I, P, P, P, P, P, D, I, I, P, SZ, C.POINTER(HzInfo)]),
+}
+
+
+def lib_path() -> str:
+    return _build.LIB
+
+
+def load() -> C.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_build.LIB):
+                _build.build()
+            L = C.CDLL(_build.LIB)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return load().hz_strerror(int(code)).decode()
+
+
+class HelmzError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        super().__init__(f"{fn} failed: {code} ({strerror(code)})")
+        self.code = code

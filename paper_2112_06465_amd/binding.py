@@ -1,0 +1,194 @@
+"""Python binding of the helmz C-ABI: torch tensors in, the same calls out.
+
+Each function checks dtypes/devices/contiguity, passes ``data_ptr()`` and the
+current HIP stream to the library, and returns torch tensors.  No arithmetic
+of the method happens here; every step runs in the library's kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import threading
+
+import torch
+
+from ._lib import HelmzError, HzC128, HzInfo, load
+
+OK, NOT_CONVERGED, BREAKDOWN, NONFINITE = 0, 1, 2, 3
+PRECOND_NONE, PRECOND_JACOBI, X0_ZERO, VALIDATE = 0x0, 0x1, 0x4, 0x8
+
+_handles: dict[int, int] = {}
+_hlock = threading.Lock()
+
+
+def handle(device: torch.device | int | None = None) -> int:
+    """Per-device library handle, created on first use with that device current."""
+    if device is None:
+        idx = torch.cuda.current_device()
+    else:
+        d = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        idx = d.index if d.index is not None else torch.cuda.current_device()
+    with _hlock:
+        h = _handles.get(idx)
+        if h is None:
+            with torch.cuda.device(idx):
+                hp = C.c_void_p()
+                rc = load().hz_handle_create(C.byref(hp))
+                if rc != 0:
+                    raise HelmzError("hz_handle_create", rc)
+                h = hp.value
+                _handles[idx] = h
+    return h
+
+
+def _stream(dev: torch.device) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _need(t: torch.Tensor, name: str, dtype, dev=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if dev is not None and t.device != dev:
+        raise ValueError(f"{name} is on {t.device}, expected {dev}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _check(fn: str, rc: int, ok=(0,)):
+    if rc not in ok:
+        raise HelmzError(fn, rc)
+    return rc
+
+
+def _csr(row_ptr, col_idx, vals, vdtype):
+    dev = vals.device
+    _need(row_ptr, "row_ptr", torch.int32, dev)
+    _need(col_idx, "col_idx", torch.int32, dev)
+    _need(vals, "vals", vdtype, dev)
+    n = row_ptr.numel() - 1
+    nnz = col_idx.numel()
+    if n < 0 or vals.numel() != nnz:
+        raise ValueError("inconsistent CSR sizes")
+    return dev, n, nnz
+
+
+def csr_zspmv(row_ptr, col_idx, vals, x, y=None):
+    """y = A x, complex128 CSR (csr_zspmv)."""
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    _need(x, "x", torch.complex128, dev)
+    if x.numel() != n:
+        raise ValueError("x has the wrong length")
+    if y is None:
+        y = torch.empty(n, dtype=torch.complex128, device=dev)
+    _need(y, "y", torch.complex128, dev)
+    rc = load().csr_zspmv(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(), vals.data_ptr(),
+                          x.data_ptr(), y.data_ptr())
+    _check("csr_zspmv", rc)
+    return y
+
+
+def csr_cspmv(row_ptr, col_idx, vals, x, y=None):
+    """y = A x, complex64 CSR (csr_cspmv)."""
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex64)
+    _need(x, "x", torch.complex64, dev)
+    if x.numel() != n:
+        raise ValueError("x has the wrong length")
+    if y is None:
+        y = torch.empty(n, dtype=torch.complex64, device=dev)
+    _need(y, "y", torch.complex64, dev)
+    rc = load().csr_cspmv(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(), vals.data_ptr(),
+                          x.data_ptr(), y.data_ptr())
+    _check("csr_cspmv", rc)
+    return y
+
+
+def zdotc(x, y, out=None):
+    """sum conj(x_i) y_i as a 0-d complex128 GPU tensor (zdotc)."""
+    dev = x.device
+    _need(x, "x", torch.complex128, dev)
+    _need(y, "y", torch.complex128, dev)
+    if x.numel() != y.numel():
+        raise ValueError("length mismatch")
+    if out is None:
+        out = torch.empty((), dtype=torch.complex128, device=dev)
+    _need(out, "out", torch.complex128, dev)
+    rc = load().zdotc(handle(dev), _stream(dev), x.numel(), x.data_ptr(), y.data_ptr(), out.data_ptr())
+    _check("zdotc", rc)
+    return out
+
+
+def dznrm2(x, out=None):
+    """||x||_2 as a 0-d float64 GPU tensor (dznrm2)."""
+    dev = x.device
+    _need(x, "x", torch.complex128, dev)
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=dev)
+    _need(out, "out", torch.float64, dev)
+    rc = load().dznrm2(handle(dev), _stream(dev), x.numel(), x.data_ptr(), out.data_ptr())
+    _check("dznrm2", rc)
+    return out
+
+
+def zaxpy(alpha: complex, x, y):
+    """y <- alpha x + y in place (zaxpy); returns y."""
+    dev = y.device
+    _need(x, "x", torch.complex128, dev)
+    _need(y, "y", torch.complex128, dev)
+    if x.numel() != y.numel():
+        raise ValueError("length mismatch")
+    a = complex(alpha)
+    rc = load().zaxpy(handle(dev), _stream(dev), y.numel(), HzC128(a.real, a.imag), x.data_ptr(), y.data_ptr())
+    _check("zaxpy", rc)
+    return y
+
+
+def zbicgstab_workspace_bytes(n: int, nnz: int, flags: int = 0) -> int:
+    return int(load().zbicgstab_workspace_bytes(int(n), int(nnz), int(flags)))
+
+
+def workspace(n: int, nnz: int, flags: int, device) -> torch.Tensor:
+    """A caller-owned workspace tensor of the size the solver needs (256-byte aligned)."""
+    nbytes = zbicgstab_workspace_bytes(n, nnz, flags)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    return ws
+
+
+def _aligned_ptr(ws: torch.Tensor, nbytes: int) -> tuple[int, int]:
+    p = ws.data_ptr()
+    off = (-p) % 256
+    if ws.numel() - off < nbytes:
+        raise ValueError("workspace too small")
+    return p + off, ws.numel() - off
+
+
+def zbicgstab_solve(row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxiter=20000, flags=PRECOND_NONE | X0_ZERO, ws=None):
+    """Solve A x = b by (preconditioned) BiCGStab on the GPU (zbicgstab_solve).
+
+    Returns (x, info).  ``x`` is updated in place when given (its entry value
+    is the initial guess unless X0_ZERO is in ``flags``).  Solver statuses
+    other than OK are reported in info, not raised; argument and runtime
+    errors raise HelmzError.
+    """
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    _need(b, "b", torch.complex128, dev)
+    if b.numel() != n:
+        raise ValueError("b has the wrong length")
+    if x is None:
+        x = torch.zeros(n, dtype=torch.complex128, device=dev)
+        flags |= X0_ZERO
+    _need(x, "x", torch.complex128, dev)
+    need = zbicgstab_workspace_bytes(n, nnz, flags)
+    if ws is None:
+        ws = workspace(n, nnz, flags, dev)
+    _need(ws, "ws", torch.uint8, dev)
+    wp, wbytes = _aligned_ptr(ws, need)
+    info = HzInfo()
+    rc = load().zbicgstab_solve(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                                vals.data_ptr(), b.data_ptr(), x.data_ptr(), float(rtol), int(maxiter), int(flags), wp,
+                                wbytes, C.byref(info))
+    _check("zbicgstab_solve", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
+    return x, info.as_dict()

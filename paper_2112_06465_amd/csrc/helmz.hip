@@ -1,0 +1,433 @@
+// Host side of the helmz C-ABI: argument checks, workspace carving, launch
+// geometry and the BiCGStab driver.  All arithmetic runs in the kernels of
+// hz_kernels.hpp; the host only sequences launches and polls a done flag.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "helmz.h"
+#include "hz_kernels.hpp"
+
+using hz::cx;
+using hz::Geom;
+using hz::kBlock;
+using hz::kMaxGrid;
+using hz::kMaxParts;
+using hz::SolverScal;
+
+struct hz_handle {
+    int device;
+    double* part;          // kMaxParts * kMaxGrid partials for standalone reductions
+    int* dflag;            // device word for CSR validation
+    int* hflag;            // pinned host word
+    SolverScal* hsc;       // pinned host copy of the solver scalars
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; }
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+#define HZ_HIP(call)                                  \
+    do {                                              \
+        if ((call) != hipSuccess) return HZ_ERR_HIP;  \
+    } while (0)
+
+// Lanes per row for the vector-CSR kernel: the smallest power of two not
+// below the mean row length, in [2, 64].  HZ_SPMV_LANES overrides (tuning).
+int pick_lanes(int n, int64_t nnz) {
+    if (const char* env = std::getenv("HZ_SPMV_LANES")) {
+        int v = std::atoi(env);
+        if (v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64) return v;
+    }
+    const double mean = n > 0 ? double(nnz) / double(n) : 1.0;
+    int L = 2;
+    while (L < 64 && L < mean) L *= 2;
+    return L;
+}
+
+// Contiguous chunks of rows per block (see hz_kernels.hpp): G blocks, a
+// multiple of 8 when there are at least 8, each chunk a multiple of `step`.
+Geom geom_for(int n, int step) {
+    const int64_t steps = (int64_t(n) + step - 1) / step;
+    int64_t G = steps < kMaxGrid ? steps : kMaxGrid;
+    if (G < 1) G = 1;
+    if (G >= hz::kXcd) G -= G % hz::kXcd;
+    const int64_t per = (steps + G - 1) / G;
+    return Geom{int(G), int(per * step)};
+}
+
+inline dim3 grid1(int64_t n) { return dim3(unsigned((n + kBlock - 1) / kBlock)); }
+
+template <typename T, int EPI>
+void launch_spmv(int L, const hz::SpmvArgs<T>& a, hipStream_t s) {
+    const dim3 g(a.geo.G), b(kBlock);
+    switch (L) {
+        case 2: hipLaunchKernelGGL((hz::k_spmv<T, 2, EPI>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((hz::k_spmv<T, 4, EPI>), g, b, 0, s, a); break;
+        case 8: hipLaunchKernelGGL((hz::k_spmv<T, 8, EPI>), g, b, 0, s, a); break;
+        case 16: hipLaunchKernelGGL((hz::k_spmv<T, 16, EPI>), g, b, 0, s, a); break;
+        case 32: hipLaunchKernelGGL((hz::k_spmv<T, 32, EPI>), g, b, 0, s, a); break;
+        default: hipLaunchKernelGGL((hz::k_spmv<T, 64, EPI>), g, b, 0, s, a); break;
+    }
+}
+
+template <typename T>
+hz::SpmvArgs<T> spmv_args(int n, Geom geo, const int* rp, const int* ci, const cx<T>* v, const cx<T>* x, cx<T>* y,
+                          const cx<T>* w, double* part, const SolverScal* sc) {
+    hz::SpmvArgs<T> a;
+    a.n = n;
+    a.geo = geo;
+    a.row_ptr = rp;
+    a.col_idx = ci;
+    a.vals = v;
+    a.x = x;
+    a.y = y;
+    a.w = w;
+    a.part = part;
+    a.sc = sc;
+    return a;
+}
+
+template <typename T>
+hz::VecArgs<T> vec_args(int n, Geom geo, const cx<T>* a_, const cx<T>* b_, const cx<T>* c_, cx<T>* o1, cx<T>* o2,
+                        const cx<T>* w, double* part, SolverScal* sc) {
+    hz::VecArgs<T> a;
+    a.n = n;
+    a.geo = geo;
+    a.a = a_;
+    a.b = b_;
+    a.c = c_;
+    a.o1 = o1;
+    a.o2 = o2;
+    a.w = w;
+    a.part = part;
+    a.sc = sc;
+    return a;
+}
+
+// Device CSR structure check; synchronises the stream.
+int validate_csr(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci) {
+    HZ_HIP(hipMemsetAsync(h->dflag, 0, sizeof(int), s));
+    hipLaunchKernelGGL(hz::k_validate, grid1(int64_t(n) + 1), dim3(kBlock), 0, s, n, nnz, rp, ci, h->dflag);
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipMemcpyAsync(h->hflag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    return *h->hflag ? HZ_ERR_INVALID : HZ_OK;
+}
+
+int check_csr_args(int n, int nnz, const int* rp, const int* ci, const void* vals) {
+    if (n < 0 || nnz < 0) return HZ_ERR_INVALID;
+    if (n > 0 && rp == nullptr) return HZ_ERR_INVALID;
+    if (nnz > 0 && (ci == nullptr || vals == nullptr)) return HZ_ERR_INVALID;
+    if (misaligned(rp, 4) || misaligned(ci, 4)) return HZ_ERR_INVALID;
+    return HZ_OK;
+}
+
+// ------------------------------------------------------------------ solver workspace
+
+struct SolveWs {
+    SolverScal* sc;
+    double* part;
+    void* vec[6];  // r, rhat, p, v, s, t
+    void* dinv;
+    void* ahat;
+};
+
+template <typename T>
+size_t ws_layout(int n, int64_t nnz, bool jacobi, char* base, SolveWs* out) {
+    const size_t vb = align_up(sizeof(cx<T>) * size_t(n > 0 ? n : 1));
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    SolveWs w{};
+    w.sc = static_cast<SolverScal*>(take(sizeof(SolverScal)));
+    w.part = static_cast<double*>(take(sizeof(double) * kMaxParts * kMaxGrid));
+    for (auto& v : w.vec) v = take(vb);
+    w.dinv = jacobi ? take(vb) : nullptr;
+    w.ahat = jacobi ? take(sizeof(cx<T>) * size_t(nnz > 0 ? nnz : 1)) : nullptr;
+    if (out) *out = w;
+    return off;
+}
+
+// The iteration loop of BiCGStab on the (possibly column-scaled) matrix
+// `av`.  On entry r, rhat and the scalars are initialised (k_fin_init ran).
+// Launches at most maxiter iterations, polling sc->done every `poll`
+// iterations.  x holds the iterate (the scaled one, y, under Jacobi).
+template <typename T>
+int iterate(hz_handle* h, hipStream_t s, int n, int L, Geom geo, const int* rp, const int* ci, const cx<T>* av,
+            cx<T>* x, const SolveWs& w, int maxiter) {
+    cx<T>* r = static_cast<cx<T>*>(w.vec[0]);
+    cx<T>* rh = static_cast<cx<T>*>(w.vec[1]);
+    cx<T>* p = static_cast<cx<T>*>(w.vec[2]);
+    cx<T>* v = static_cast<cx<T>*>(w.vec[3]);
+    cx<T>* sv = static_cast<cx<T>*>(w.vec[4]);
+    cx<T>* t = static_cast<cx<T>*>(w.vec[5]);
+    SolverScal* sc = w.sc;
+    double* part = w.part;
+    const dim3 G(geo.G), B(kBlock), one(1);
+
+    const auto pupd = vec_args<T>(n, geo, r, nullptr, v, p, nullptr, nullptr, nullptr, sc);
+    const auto sp1 = spmv_args<T>(n, geo, rp, ci, av, p, v, rh, part, sc);
+    const auto supd = vec_args<T>(n, geo, r, v, nullptr, sv, nullptr, nullptr, part, sc);
+    const auto sp2 = spmv_args<T>(n, geo, rp, ci, av, sv, t, nullptr, part, sc);
+    const auto xr = vec_args<T>(n, geo, p, sv, t, x, r, rh, part, sc);
+
+    int launched = 0, poll = 8;
+    while (launched < maxiter) {
+        const int m = (maxiter - launched) < poll ? (maxiter - launched) : poll;
+        for (int k = 0; k < m; ++k) {
+            hipLaunchKernelGGL(hz::k_pupd<T>, G, B, 0, s, pupd);
+            launch_spmv<T, hz::EPI_DOT_W>(L, sp1, s);
+            hipLaunchKernelGGL(hz::k_fin_alpha, one, B, 0, s, part, geo.G, sc);
+            hipLaunchKernelGGL(hz::k_supd<T>, G, B, 0, s, supd);
+            hipLaunchKernelGGL(hz::k_fin_half, one, B, 0, s, part, geo.G, sc);
+            launch_spmv<T, hz::EPI_TS>(L, sp2, s);
+            hipLaunchKernelGGL(hz::k_fin_omega, one, B, 0, s, part, geo.G, sc);
+            hipLaunchKernelGGL(hz::k_xr<T>, G, B, 0, s, xr);
+            hipLaunchKernelGGL(hz::k_fin_rho, one, B, 0, s, part, geo.G, sc);
+        }
+        HZ_HIP(hipGetLastError());
+        launched += m;
+        HZ_HIP(hipMemcpyAsync(h->hflag, &sc->done, sizeof(int), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipStreamSynchronize(s));
+        if (*h->hflag) break;
+        if (poll < 64) poll *= 2;
+    }
+    return HZ_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C-ABI
+
+extern "C" {
+
+const char* hz_strerror(int code) {
+    switch (code) {
+        case HZ_OK: return "ok";
+        case HZ_NOT_CONVERGED: return "not converged: iteration limit reached";
+        case HZ_BREAKDOWN: return "breakdown: a BiCGStab denominator became exactly zero";
+        case HZ_NONFINITE: return "non-finite scalar (NaN or Inf) in the iteration";
+        case HZ_ERR_INVALID: return "invalid argument or malformed CSR";
+        case HZ_ERR_HIP: return "HIP runtime error";
+        case HZ_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+        default: return "unknown helmz status";
+    }
+}
+
+int hz_handle_create(hz_handle** out) {
+    if (out == nullptr) return HZ_ERR_INVALID;
+    *out = nullptr;
+    hz_handle* h = new (std::nothrow) hz_handle();
+    if (h == nullptr) return HZ_ERR_HIP;
+    if (hipGetDevice(&h->device) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&h->part), sizeof(double) * kMaxParts * kMaxGrid) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&h->dflag), sizeof(int)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h->hflag), sizeof(int), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h->hsc), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess) {
+        hz_handle_destroy(h);
+        return HZ_ERR_HIP;
+    }
+    *out = h;
+    return HZ_OK;
+}
+
+int hz_handle_destroy(hz_handle* h) {
+    if (h == nullptr) return HZ_OK;
+    if (h->part) (void)hipFree(h->part);
+    if (h->dflag) (void)hipFree(h->dflag);
+    if (h->hflag) (void)hipHostFree(h->hflag);
+    if (h->hsc) (void)hipHostFree(h->hsc);
+    delete h;
+    return HZ_OK;
+}
+
+static int spmv_common_checks(hz_handle* h, int n, int nnz, const int* rp, const int* ci, const void* vals,
+                              const void* x, void* y, size_t esz) {
+    if (h == nullptr) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (n > 0 && (x == nullptr || y == nullptr)) return HZ_ERR_INVALID;
+    if (misaligned(x, esz) || misaligned(y, esz) || misaligned(vals, esz)) return HZ_ERR_INVALID;
+    if (n > 0 && overlap(x, esz * size_t(n), y, esz * size_t(n))) return HZ_ERR_INVALID;
+    return HZ_OK;
+}
+
+int csr_zspmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c128* vals,
+              const hz_c128* x, hz_c128* y) {
+    int rc = spmv_common_checks(h, n, nnz, rp, ci, vals, x, y, sizeof(hz_c128));
+    if (rc || n == 0) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int L = pick_lanes(n, nnz);
+    const Geom geo = geom_for(n, kBlock / L);
+    auto a = spmv_args<double>(n, geo, rp, ci, reinterpret_cast<const double2*>(vals),
+                               reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nullptr, nullptr,
+                               nullptr);
+    launch_spmv<double, hz::EPI_NONE>(L, a, s);
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+int csr_cspmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c64* vals,
+              const hz_c64* x, hz_c64* y) {
+    int rc = spmv_common_checks(h, n, nnz, rp, ci, vals, x, y, sizeof(hz_c64));
+    if (rc || n == 0) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int L = pick_lanes(n, nnz);
+    const Geom geo = geom_for(n, kBlock / L);
+    auto a = spmv_args<float>(n, geo, rp, ci, reinterpret_cast<const float2*>(vals), reinterpret_cast<const float2*>(x),
+                              reinterpret_cast<float2*>(y), nullptr, nullptr, nullptr);
+    launch_spmv<float, hz::EPI_NONE>(L, a, s);
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+int zdotc(hz_handle* h, hz_stream stream, int n, const hz_c128* x, const hz_c128* y, hz_c128* out) {
+    if (h == nullptr || n < 0 || out == nullptr) return HZ_ERR_INVALID;
+    if (n > 0 && (x == nullptr || y == nullptr)) return HZ_ERR_INVALID;
+    if (misaligned(x, 16) || misaligned(y, 16) || misaligned(out, 16)) return HZ_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Geom geo = geom_for(n > 0 ? n : 1, kBlock);
+    hipLaunchKernelGGL(hz::k_dot_part<0>, dim3(geo.G), dim3(kBlock), 0, s, n, geo,
+                       reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(y), h->part);
+    hipLaunchKernelGGL(hz::k_dot_fin<0>, dim3(1), dim3(kBlock), 0, s, h->part, geo.G, static_cast<void*>(out));
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+int dznrm2(hz_handle* h, hz_stream stream, int n, const hz_c128* x, double* out) {
+    if (h == nullptr || n < 0 || out == nullptr) return HZ_ERR_INVALID;
+    if (n > 0 && x == nullptr) return HZ_ERR_INVALID;
+    if (misaligned(x, 16) || misaligned(out, 8)) return HZ_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Geom geo = geom_for(n > 0 ? n : 1, kBlock);
+    hipLaunchKernelGGL(hz::k_dot_part<1>, dim3(geo.G), dim3(kBlock), 0, s, n, geo,
+                       reinterpret_cast<const double2*>(x), nullptr, h->part);
+    hipLaunchKernelGGL(hz::k_dot_fin<1>, dim3(1), dim3(kBlock), 0, s, h->part, geo.G, static_cast<void*>(out));
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+int zaxpy(hz_handle* h, hz_stream stream, int n, hz_c128 alpha, const hz_c128* x, hz_c128* y) {
+    if (h == nullptr || n < 0) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (x == nullptr || y == nullptr || misaligned(x, 16) || misaligned(y, 16)) return HZ_ERR_INVALID;
+    if (x != y && overlap(x, 16 * size_t(n), y, 16 * size_t(n))) return HZ_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double2 a;
+    a.x = alpha.re;
+    a.y = alpha.im;
+    int64_t blocks = (int64_t(n) + kBlock - 1) / kBlock;
+    if (blocks > 8 * kMaxGrid) blocks = 8 * kMaxGrid;
+    hipLaunchKernelGGL(hz::k_zaxpy, dim3(unsigned(blocks)), dim3(kBlock), 0, s, int64_t(n), a,
+                       reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+size_t zbicgstab_workspace_bytes(int n, int nnz, int flags) {
+    if (n < 0 || nnz < 0) return 0;
+    return ws_layout<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr);
+}
+
+int zbicgstab_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c128* vals,
+                    const hz_c128* b, hz_c128* x, double rtol, int maxiter, int flags, void* ws, size_t ws_bytes,
+                    hz_solve_info* info) {
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (h == nullptr || info == nullptr) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (!(rtol >= 0.0) || maxiter < 0) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
+        return HZ_ERR_INVALID;
+    if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
+    const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
+    SolveWs w;
+    const size_t need = ws_layout<double>(n, nnz, jacobi, static_cast<char*>(ws), &w);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (flags & HZ_VALIDATE) {
+        rc = validate_csr(h, s, n, nnz, rp, ci);
+        if (rc) return rc;
+    }
+    const int L = pick_lanes(n, nnz);
+    const Geom geo = geom_for(n, kBlock / L);
+    const double2* A = reinterpret_cast<const double2*>(vals);
+    const double2* bd = reinterpret_cast<const double2*>(b);
+    double2* xd = reinterpret_cast<double2*>(x);
+    double2* r = static_cast<double2*>(w.vec[0]);
+    double2* rh = static_cast<double2*>(w.vec[1]);
+    double2* t = static_cast<double2*>(w.vec[5]);
+    double2* dinv = static_cast<double2*>(w.dinv);
+
+    SolverScal* hs = h->hsc;
+    std::memset(hs, 0, sizeof(*hs));
+    hs->rtol = rtol;
+    hs->maxiter = maxiter;
+    HZ_HIP(hipMemcpyAsync(w.sc, hs, sizeof(SolverScal), hipMemcpyHostToDevice, s));
+
+    const double2* Aop = A;
+    if (jacobi) {
+        hipLaunchKernelGGL(hz::k_jacobi_diag<double>, grid1(n), dim3(kBlock), 0, s, n, rp, ci, A, dinv, w.sc);
+        double2* ah = static_cast<double2*>(w.ahat);
+        if (nnz > 0)
+            hipLaunchKernelGGL(hz::k_colscale<double>, grid1(nnz), dim3(kBlock), 0, s, int64_t(nnz), ci, A,
+                               static_cast<const double2*>(dinv), ah);
+        Aop = ah;
+    }
+    // initial iterate (y = D x0 under Jacobi) and residual
+    const double2* rsrc = bd;
+    if (flags & HZ_X0_ZERO) {
+        HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
+    } else {
+        if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, dinv, xd, 1);
+        launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, Aop, xd, r, bd, w.part, nullptr), s);
+        rsrc = r;
+    }
+    hipLaunchKernelGGL(hz::k_init<double>, dim3(geo.G), dim3(kBlock), 0, s,
+                       vec_args<double>(n, geo, bd, rsrc, nullptr, r, rh, nullptr, w.part, w.sc));
+    hipLaunchKernelGGL(hz::k_fin_init, dim3(1), dim3(kBlock), 0, s, w.part, geo.G, w.sc);
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipMemcpyAsync(hs, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    if (hs->bad_diag) return HZ_ERR_INVALID;
+
+    if (!hs->done) {
+        rc = iterate<double>(h, s, n, L, geo, rp, ci, Aop, xd, w, maxiter);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(hz::k_zero_if<double>, grid1(n), dim3(kBlock), 0, s, n, w.sc, xd);
+    if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, dinv, xd, 0);
+    // true residual with the caller's matrix
+    launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, t, bd, w.part, nullptr), s);
+    hipLaunchKernelGGL(hz::k_fin_true, dim3(1), dim3(kBlock), 0, s, w.part, geo.G, w.sc);
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipMemcpyAsync(hs, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    info->status = hs->status;
+    info->iterations = hs->iter;
+    info->outer_steps = 0;
+    info->relres_recursive = hs->relres;
+    info->relres_true = hs->relres_true;
+    return hs->status;
+}
+
+}  // extern "C"
