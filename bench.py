@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the Helmholtz BiCGStab hot path on one MI355X.
+
+One step = the whole hot path on the cylinder workload (P1 Kuhn-tet FEM,
+radius 1, length 4, h = 0.04, k = 20: n = 209,777, nnz = 3,048,433):
+  1. R standalone complex128 SpMVs (csr_zspmv), each after a cache flush
+     and bracketed by HIP events on the launch stream;
+  2. one zdotc and one zaxpy on the n-vectors;
+  3. one Jacobi-BiCGStab solve of A x = b to ||r||/||b|| <= 1e-8.
+
+``value`` = algorithmic HBM bytes of every kernel of the step / step time
+(GB/s).  The algorithmic byte model (each array element moved once):
+  SpMV                 20 nnz + 36 n + 4
+  zdotc / zaxpy        32 n / 48 n
+  BiCGStab iteration   40 nnz + 312 n   (five fused kernels, Jacobi folded)
+  solve set-up/finish  76 nnz + 168 n   (diagonal, column scaling, init,
+                                          un-scaling, true residual)
+``roofline`` reports the standalone zSpMV kernel against the 8 TB/s HBM
+peak; its duration is the HIP-event average over the timed region.
+``cpu_baseline`` times the plain C oracle on a bounded sample of the same
+work, single-threaded, on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --calib-copy       (plain copy for counter scaling)
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SPMV_KERNEL = "hz::k_spmv<double, 16, 0>"
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def spmv_bytes(n, nnz):
+    return 20 * nnz + 36 * n + 4
+
+
+def solve_bytes(n, nnz, iterations):
+    return iterations * (40 * nnz + 312 * n) + 76 * nnz + 168 * n
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("hz_kernels.hpp", "helmz.hip"):
+        with open(os.path.join(ROOT, "paper_2112_06465_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(n, nnz):
+    """HBM bytes per SpMV launch from the committed counter summary, if current."""
+    path = os.path.join(PROFILES, "zspmv_cylinder_pmc.md")
+    try:
+        txt = open(path).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"kernel source hash:\s*`?([0-9a-f]{16})", txt)
+    m_bytes = re.search(r"HBM bytes per launch \(scaled\):\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def cpu_baseline(A, b, x_spmv, budget_iters=300):
+    """Time the oracle (single thread) on a bounded sample of the step's work."""
+    import oracle as O
+
+    n, nnz = A.n, A.nnz
+    t0 = time.perf_counter()
+    for _ in range(3):
+        O.zspmv(A, x_spmv)
+    O.zdotc(x_spmv, b)
+    O.zaxpy(0.7 - 0.3j, x_spmv, b)
+    _, info = O.zbicgstab(A, b, tol=1e-8, maxiter=budget_iters, jacobi=True)
+    dt = time.perf_counter() - t0
+    it = info["iterations"]
+    # oracle time per iteration and bytes of the same model
+    nbytes = 3 * spmv_bytes(n, nnz) + 32 * n + 48 * n + it * (40 * nnz + 312 * n) + 76 * nnz + 168 * n
+    return {
+        "value": nbytes / dt / 1e9,
+        "unit": "GB/s",
+        "cores": O.threads_used(),
+        "kind": "oracle",
+        "sample": f"cylinder n={n} nnz={nnz}: 3 zSpMV + zdotc + zaxpy + {it} Jacobi-BiCGStab iterations "
+        f"(bounded; the full solve needs ~1e3 iterations), single thread, {dt:.1f} s on '{O.cpu_model()}'",
+        "seconds": dt,
+    }
+
+
+def calib_copy():
+    import torch
+
+    nbytes = 512 * 2**20
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes": nbytes, "launches": 5}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--spmv-reps", type=int, default=10)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the solve is not sharded).",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.calib_copy:
+        calib_copy()
+        return
+
+    import torch
+
+    import paper_2112_06465_amd as hz
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    A, b_np, info = W.config_cylinder()
+    n, nnz = A.n, A.nnz
+    rng = np.random.default_rng(0)
+    x_np = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col_idx).to(dev)
+    vals = torch.from_numpy(A.vals).to(dev)
+    b = torch.from_numpy(b_np).to(dev)
+    xv = torch.from_numpy(x_np).to(dev)
+    yv = torch.empty_like(xv)
+    zv = xv.clone()
+    xs = torch.zeros_like(b)
+    flags = hz.PRECOND_JACOBI | hz.X0_ZERO
+    ws = hz.workspace(n, nnz, flags, dev)
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)  # 1 GiB > 256 MiB MALL
+    dotout = torch.empty((), dtype=torch.complex128, device=dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.spmv_reps)]
+
+    def step(record):
+        spmv_ms = []
+        for r in range(args.spmv_reps):
+            flush.zero_()
+            e0, e1 = ev[r]
+            e0.record()
+            hz.csr_zspmv(rp, ci, vals, xv, yv)
+            e1.record()
+        hz.zdotc(xv, yv, out=dotout)
+        hz.zaxpy(0.7 - 0.3j, xv, zv)
+        _, sinfo = hz.zbicgstab_solve(rp, ci, vals, b, x=xs, rtol=args.tol, maxiter=20000, flags=flags, ws=ws)
+        if record:
+            torch.cuda.synchronize()
+            spmv_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+        return sinfo, spmv_ms
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+
+    step_ms, spmv_all, infos = [], [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sinfo, spmv_ms = step(True)
+        torch.cuda.synchronize()
+        step_ms.append((time.perf_counter() - t0) * 1e3)
+        spmv_all += spmv_ms
+        infos.append(sinfo)
+    total_s = time.perf_counter() - t_start
+
+    its = [i["iterations"] for i in infos]
+    step_bytes = [
+        args.spmv_reps * spmv_bytes(n, nnz) + 32 * n + 48 * n + solve_bytes(n, nnz, it) for it in its
+    ]
+    value = sum(step_bytes) / total_s / 1e9
+    spmv_avg_s = float(np.mean(spmv_all)) / 1e3
+    spmv_gbs = spmv_bytes(n, nnz) / spmv_avg_s / 1e9
+    traffic = read_traffic(n, nnz)
+
+    # correctness of the last solve, checked on the host with the oracle
+    import oracle as O
+
+    x_host = xs.cpu().numpy()
+    true_rr = float(np.linalg.norm(b_np - O.zspmv(A, x_host)) / np.linalg.norm(b_np))
+
+    out = {
+        "metric": "zSpMV HBM GB/s (% of peak); BiCGStab time-to-1e-10, mixed vs FP64, 1 MI355X",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(total_s * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded P1 FEM cylinder, point source + noise RHS)",
+        "config": {
+            "workload": f"cylinder P1 FEM h=0.04 k=20 impedance boundary (n={n}, nnz={nnz}): "
+            f"{args.spmv_reps} flushed zSpMV + zdotc + zaxpy + Jacobi-BiCGStab to {args.tol:g}",
+            "n": n,
+            "nnz": nnz,
+            "value_definition": "algorithmic HBM bytes of all kernels in a step / wall time of the steps",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": SPMV_KERNEL,
+            "achieved": round(spmv_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": spmv_bytes(n, nnz),
+            "avg_launch_us": round(spmv_avg_s * 1e6, 3),
+            "cache": "flushed (1 GiB write) before every launch",
+        },
+        "solve": {
+            "iterations": its[-1],
+            "status": infos[-1]["status"],
+            "relres_recursive": infos[-1]["relres_recursive"],
+            "relres_true_gpu": infos[-1]["relres_true"],
+            "relres_true_oracle_spmv": true_rr,
+            "step_ms": [round(s, 3) for s in step_ms],
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, b_np, x_np)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

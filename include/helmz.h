@@ -120,6 +120,28 @@ int zbicgstab_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const i
                     const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol, int maxiter, int flags, void *ws,
                     size_t ws_bytes, hz_solve_info *info);
 
+/* Device workspace (bytes) that zbicgstab_solve_mixed needs. */
+size_t zbicgstab_mixed_workspace_bytes(int n, int nnz, int flags);
+
+/*
+ * Solve A x = b to ||b - A x|| / ||b|| <= rtol by iterative refinement with
+ * a complex64 inner BiCGStab.  The paper's library provides single as well
+ * as double precision (Section 1); this entry point combines them: the
+ * residual r = b - A x, the correction x <- x + ||r|| d, the norms and the
+ * stopping test are complex128, while each correction solves A d = r/||r||
+ * to inner_rtol with the values of A (column-scaled by D^{-1} under
+ * HZ_PRECOND_JACOBI) rounded to complex64 and complex64 vectors and SpMV
+ * (Krylov scalars and reductions in FP64).  At most max_outer corrections,
+ * each of at most maxiter inner iterations.  info->iterations is the total
+ * of inner iterations, info->outer_steps the number of corrections, and
+ * info->relres_true the final FP64 residual.  Workspace, stream, x and
+ * status conventions as for zbicgstab_solve.
+ */
+int zbicgstab_solve_mixed(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr,
+                          const int *col_idx, const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol,
+                          double inner_rtol, int maxiter, int max_outer, int flags, void *ws, size_t ws_bytes,
+                          hz_solve_info *info);
+
 #ifdef __cplusplus
 }
 #endif

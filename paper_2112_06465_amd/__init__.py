@@ -19,7 +19,10 @@ from .binding import (  # noqa: F401
     handle,
     workspace,
     zaxpy,
+    mixed_workspace,
+    zbicgstab_mixed_workspace_bytes,
     zbicgstab_solve,
+    zbicgstab_solve_mixed,
     zbicgstab_workspace_bytes,
     zdotc,
 )

@@ -54,6 +54,8 @@ SIGNATURES = {
     "zaxpy": (I, [P, P, I, HzC128, P, P]),
     "zbicgstab_workspace_bytes": (SZ, [I, I, I]),
     "zbicgstab_solve": (I, [P, P, I, I, P, P, P, P, P, D, I, I, P, SZ, C.POINTER(HzInfo)]),
+    "zbicgstab_mixed_workspace_bytes": (SZ, [I, I, I]),
+    "zbicgstab_solve_mixed": (I, [P, P, I, I, P, P, P, P, P, D, D, I, I, I, P, SZ, C.POINTER(HzInfo)]),
 }
 
 

@@ -192,3 +192,46 @@ def zbicgstab_solve(row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxiter=20000,
                                 wbytes, C.byref(info))
     _check("zbicgstab_solve", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
     return x, info.as_dict()
+
+
+def zbicgstab_mixed_workspace_bytes(n: int, nnz: int, flags: int = 0) -> int:
+    return int(load().zbicgstab_mixed_workspace_bytes(int(n), int(nnz), int(flags)))
+
+
+def mixed_workspace(n: int, nnz: int, flags: int, device) -> torch.Tensor:
+    return torch.empty(zbicgstab_mixed_workspace_bytes(n, nnz, flags) + 256, dtype=torch.uint8, device=device)
+
+
+def zbicgstab_solve_mixed(
+    row_ptr,
+    col_idx,
+    vals,
+    b,
+    x=None,
+    rtol=1e-10,
+    inner_rtol=1e-4,
+    maxiter=20000,
+    max_outer=50,
+    flags=PRECOND_NONE | X0_ZERO,
+    ws=None,
+):
+    """Complex64-inner BiCGStab with complex128 refinement (zbicgstab_solve_mixed).  Returns (x, info)."""
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    _need(b, "b", torch.complex128, dev)
+    if b.numel() != n:
+        raise ValueError("b has the wrong length")
+    if x is None:
+        x = torch.zeros(n, dtype=torch.complex128, device=dev)
+        flags |= X0_ZERO
+    _need(x, "x", torch.complex128, dev)
+    need = zbicgstab_mixed_workspace_bytes(n, nnz, flags)
+    if ws is None:
+        ws = mixed_workspace(n, nnz, flags, dev)
+    _need(ws, "ws", torch.uint8, dev)
+    wp, wbytes = _aligned_ptr(ws, need)
+    info = HzInfo()
+    rc = load().zbicgstab_solve_mixed(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                                      vals.data_ptr(), b.data_ptr(), x.data_ptr(), float(rtol), float(inner_rtol),
+                                      int(maxiter), int(max_outer), int(flags), wp, wbytes, C.byref(info))
+    _check("zbicgstab_solve_mixed", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
+    return x, info.as_dict()

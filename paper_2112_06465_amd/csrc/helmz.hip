@@ -24,6 +24,7 @@ struct hz_handle {
     int* dflag;            // device word for CSR validation
     int* hflag;            // pinned host word
     SolverScal* hsc;       // pinned host copy of the solver scalars
+    SolverScal* hsc2;      // pinned host copy of the refinement's outer scalars
 };
 
 namespace {
@@ -212,6 +213,40 @@ int iterate(hz_handle* h, hipStream_t s, int n, int L, Geom geo, const int* rp, 
     return HZ_OK;
 }
 
+
+// Mixed refinement workspace: outer scalars, the complex64 solver's own
+// workspace (vectors, partials, scalars, D^{-1}, demoted matrix), the FP64
+// residual and the complex64 right-hand side and correction.
+struct MixedWs {
+    SolverScal* outer;
+    SolveWs in;
+    double2* r64;
+    float2* b32;
+    float2* d32;
+};
+
+size_t mixed_layout(int n, int64_t nnz, bool jacobi, char* base, MixedWs* out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const size_t nn = size_t(n > 0 ? n : 1);
+    MixedWs m{};
+    m.outer = static_cast<SolverScal*>(take(sizeof(SolverScal)));
+    m.in.sc = static_cast<SolverScal*>(take(sizeof(SolverScal)));
+    m.in.part = static_cast<double*>(take(sizeof(double) * kMaxParts * kMaxGrid));
+    for (auto& v : m.in.vec) v = take(sizeof(float2) * nn);
+    m.in.dinv = jacobi ? take(sizeof(float2) * nn) : nullptr;
+    m.in.ahat = take(sizeof(float2) * size_t(nnz > 0 ? nnz : 1));
+    m.r64 = static_cast<double2*>(take(sizeof(double2) * nn));
+    m.b32 = static_cast<float2*>(take(sizeof(float2) * nn));
+    m.d32 = static_cast<float2*>(take(sizeof(float2) * nn));
+    if (out) *out = m;
+    return off;
+}
+
 }  // namespace
 
 // ====================================================================== C-ABI
@@ -240,7 +275,8 @@ int hz_handle_create(hz_handle** out) {
         hipMalloc(reinterpret_cast<void**>(&h->part), sizeof(double) * kMaxParts * kMaxGrid) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&h->dflag), sizeof(int)) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&h->hflag), sizeof(int), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&h->hsc), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(reinterpret_cast<void**>(&h->hsc), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h->hsc2), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess) {
         hz_handle_destroy(h);
         return HZ_ERR_HIP;
     }
@@ -254,6 +290,7 @@ int hz_handle_destroy(hz_handle* h) {
     if (h->dflag) (void)hipFree(h->dflag);
     if (h->hflag) (void)hipHostFree(h->hflag);
     if (h->hsc) (void)hipHostFree(h->hsc);
+    if (h->hsc2) (void)hipHostFree(h->hsc2);
     delete h;
     return HZ_OK;
 }
@@ -379,10 +416,7 @@ int zbicgstab_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* r
     double2* dinv = static_cast<double2*>(w.dinv);
 
     SolverScal* hs = h->hsc;
-    std::memset(hs, 0, sizeof(*hs));
-    hs->rtol = rtol;
-    hs->maxiter = maxiter;
-    HZ_HIP(hipMemcpyAsync(w.sc, hs, sizeof(SolverScal), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(hz::k_sc_init, dim3(1), dim3(64), 0, s, w.sc, rtol, maxiter);
 
     const double2* Aop = A;
     if (jacobi) {
@@ -428,6 +462,111 @@ int zbicgstab_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* r
     info->relres_recursive = hs->relres;
     info->relres_true = hs->relres_true;
     return hs->status;
+}
+
+
+size_t zbicgstab_mixed_workspace_bytes(int n, int nnz, int flags) {
+    if (n < 0 || nnz < 0) return 0;
+    return mixed_layout(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr);
+}
+
+int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci,
+                          const hz_c128* vals, const hz_c128* b, hz_c128* x, double rtol, double inner_rtol,
+                          int maxiter, int max_outer, int flags, void* ws, size_t ws_bytes, hz_solve_info* info) {
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (h == nullptr || info == nullptr) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (!(rtol >= 0.0) || !(inner_rtol > 0.0) || maxiter < 0 || max_outer < 0) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
+        return HZ_ERR_INVALID;
+    if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
+    const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
+    MixedWs m;
+    const size_t need = mixed_layout(n, nnz, jacobi, static_cast<char*>(ws), &m);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (flags & HZ_VALIDATE) {
+        rc = validate_csr(h, s, n, nnz, rp, ci);
+        if (rc) return rc;
+    }
+    const int L = pick_lanes(n, nnz);
+    const Geom geo = geom_for(n, kBlock / L);
+    const double2* A = reinterpret_cast<const double2*>(vals);
+    const double2* bd = reinterpret_cast<const double2*>(b);
+    double2* xd = reinterpret_cast<double2*>(x);
+    float2* r32 = static_cast<float2*>(m.in.vec[0]);
+    float2* rh32 = static_cast<float2*>(m.in.vec[1]);
+    const dim3 one(1), B(kBlock);
+
+    hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, m.outer, rtol, max_outer);
+    hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, m.in.sc, inner_rtol, maxiter);
+    // complex64 copy of the (column-scaled) matrix; r64 holds the FP64 D^{-1} meanwhile
+    const double2* dinv64 = nullptr;
+    if (jacobi) {
+        hipLaunchKernelGGL(hz::k_jacobi_diag<double>, grid1(n), B, 0, s, n, rp, ci, A, m.r64, m.outer);
+        hipLaunchKernelGGL(hz::k_demote_vec, grid1(n), B, 0, s, n, static_cast<const double2*>(m.r64),
+                           static_cast<float2*>(m.in.dinv));
+        dinv64 = m.r64;
+    }
+    if (nnz > 0)
+        hipLaunchKernelGGL(hz::k_demote_vals, grid1(nnz), B, 0, s, int64_t(nnz), ci, A, dinv64,
+                           static_cast<float2*>(m.in.ahat));
+    if (flags & HZ_X0_ZERO) HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
+    hipLaunchKernelGGL(hz::k_dot_part<1>, dim3(geo.G), B, 0, s, n, geo, bd, nullptr, m.in.part);
+    hipLaunchKernelGGL(hz::k_fin_bnorm, one, B, 0, s, m.in.part, geo.G, m.outer);
+    HZ_HIP(hipGetLastError());
+    SolverScal* ho = h->hsc2;
+    SolverScal* hi = h->hsc;
+    HZ_HIP(hipMemcpyAsync(ho, m.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    if (ho->bad_diag) return HZ_ERR_INVALID;
+
+    const float2* dinv32 = jacobi ? static_cast<const float2*>(m.in.dinv) : nullptr;
+    int inner_total = 0, outer = 0;
+    for (;; ++outer) {
+        // r = b - A x in FP64, and the outer decision
+        launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, m.r64, bd, m.in.part, nullptr),
+                                           s);
+        hipLaunchKernelGGL(hz::k_fin_outer, one, B, 0, s, m.in.part, geo.G, m.outer, outer, max_outer);
+        HZ_HIP(hipGetLastError());
+        HZ_HIP(hipMemcpyAsync(ho, m.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipStreamSynchronize(s));
+        if (ho->done) break;
+        // inner complex64 solve of A d = r / ||r|| from d = 0
+        hipLaunchKernelGGL(hz::k_demote_scaled, grid1(n), B, 0, s, n, static_cast<const double2*>(m.r64), m.outer,
+                           m.b32);
+        HZ_HIP(hipMemsetAsync(m.d32, 0, 8 * size_t(n), s));
+        hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, m.in.sc, inner_rtol, maxiter);
+        hipLaunchKernelGGL(hz::k_init<float>, dim3(geo.G), B, 0, s,
+                           vec_args<float>(n, geo, m.b32, m.b32, nullptr, r32, rh32, nullptr, m.in.part, m.in.sc));
+        hipLaunchKernelGGL(hz::k_fin_init, one, B, 0, s, m.in.part, geo.G, m.in.sc);
+        HZ_HIP(hipGetLastError());
+        rc = iterate<float>(h, s, n, L, geo, rp, ci, static_cast<const float2*>(m.in.ahat), m.d32, m.in, maxiter);
+        if (rc) return rc;
+        HZ_HIP(hipMemcpyAsync(hi, m.in.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipStreamSynchronize(s));
+        inner_total += hi->iter;
+        if (hi->status == HZ_NONFINITE) {
+            info->status = HZ_NONFINITE;
+            info->iterations = inner_total;
+            info->outer_steps = outer + 1;
+            return HZ_NONFINITE;
+        }
+        hipLaunchKernelGGL(hz::k_promote_add, grid1(n), B, 0, s, n, static_cast<const float2*>(m.d32), dinv32,
+                           static_cast<const SolverScal*>(m.outer), xd);
+    }
+    hipLaunchKernelGGL(hz::k_zero_if<double>, grid1(n), B, 0, s, n, static_cast<const SolverScal*>(m.outer), xd);
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipStreamSynchronize(s));
+    info->status = ho->status;
+    info->iterations = inner_total;
+    info->outer_steps = outer;
+    info->relres_recursive = ho->relres;
+    info->relres_true = ho->relres_true;
+    return ho->status;
 }
 
 }  // extern "C"

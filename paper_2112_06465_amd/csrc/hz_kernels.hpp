@@ -191,9 +191,20 @@ struct alignas(256) SolverScal {
     int first;   // iteration 1: p = r
     int zero_x;  // ||b|| = 0: the solution is x = 0
     int bad_diag;  // Jacobi requested with a zero diagonal entry
+    double outer_rn;  // refinement: ||b - A x|| of the current outer step
 };
 
 enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = 2, ST_NONFINITE = 3 };
+
+// Reset a scalar block before a solve (one thread).
+__global__ void k_sc_init(SolverScal* sc, double rtol, int maxiter) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    SolverScal z = {};
+    z.rtol = rtol;
+    z.maxiter = maxiter;
+    z.status = 1;
+    *sc = z;
+}
 
 __device__ __forceinline__ void finish(SolverScal* sc, int status, int iterations) {
     sc->status = status;
@@ -636,6 +647,82 @@ __global__ __launch_bounds__(kBlock) void k_validate(int n, int nnz, const int* 
             *bad = 1;
             return;
         }
+}
+
+}  // namespace hz
+
+// ================================================================== mixed precision (complex64 inner solve)
+namespace hz {
+
+// out32_p = complex64(vals_p * dinv[col_p]) (Jacobi) or complex64(vals_p)
+__global__ __launch_bounds__(kBlock) void k_demote_vals(int64_t nnz, const int* __restrict__ ci,
+                                                        const double2* __restrict__ vals,
+                                                        const double2* __restrict__ dinv, float2* __restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= nnz) return;
+    double2 v = vals[p];
+    if (dinv != nullptr) v = cmul<double>(v, dinv[ci[p]]);
+    out[p] = mk<float>((float)v.x, (float)v.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_demote_vec(int n, const double2* __restrict__ in, float2* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double2 v = in[i];
+    out[i] = mk<float>((float)v.x, (float)v.y);
+}
+
+// Outer scalars of the refinement live in a second SolverScal: bnorm, relres,
+// status/done, and outer_rn = ||r|| of the current outer residual.
+__global__ __launch_bounds__(kBlock) void k_fin_bnorm(const double* __restrict__ part, int G, SolverScal* sc) {
+    double s[1];
+    sum_partials<1>(part, G, s);
+    if (threadIdx.x == 0) sc->bnorm = __builtin_sqrt(s[0]);
+}
+
+// After r = b - A x: decide convergence; otherwise record ||r|| for the next correction.
+__global__ __launch_bounds__(kBlock) void k_fin_outer(const double* __restrict__ part, int G, SolverScal* sc,
+                                                      int outer, int max_outer) {
+    double s[1];
+    sum_partials<1>(part, G, s);
+    if (threadIdx.x != 0) return;
+    const double rn = __builtin_sqrt(s[0]), bn = sc->bnorm;
+    sc->outer_rn = rn;
+    if (!__builtin_isfinite(rn) || !__builtin_isfinite(bn)) return finish(sc, ST_NONFINITE, outer);
+    if (bn == 0.0) {
+        sc->zero_x = 1;
+        sc->relres = 0.0;
+        return finish(sc, ST_OK, outer);
+    }
+    const double rel = rn / bn;
+    sc->relres = rel;
+    sc->relres_true = rel;
+    if (rel <= sc->rtol) return finish(sc, ST_OK, outer);
+    if (outer >= max_outer) return finish(sc, ST_NOT_CONVERGED, outer);
+}
+
+// b32 = complex64(r / ||r||)
+__global__ __launch_bounds__(kBlock) void k_demote_scaled(int n, const double2* __restrict__ r, const SolverScal* sc,
+                                                          float2* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double inv = 1.0 / sc->outer_rn;
+    const double2 v = r[i];
+    out[i] = mk<float>((float)(v.x * inv), (float)(v.y * inv));
+}
+
+// x += ||r|| * D^{-1} d  (FP64 update of the FP64 iterate)
+__global__ __launch_bounds__(kBlock) void k_promote_add(int n, const float2* __restrict__ d, const float2* __restrict__ dinv,
+                                                        const SolverScal* sc, double2* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double rn = sc->outer_rn;
+    double2 dv = mk<double>((double)d[i].x, (double)d[i].y);
+    if (dinv != nullptr) dv = zmul(mk<double>((double)dinv[i].x, (double)dinv[i].y), dv);
+    double2 xv = x[i];
+    xv.x = __builtin_fma(rn, dv.x, xv.x);
+    xv.y = __builtin_fma(rn, dv.y, xv.y);
+    x[i] = xv;
 }
 
 }  // namespace hz

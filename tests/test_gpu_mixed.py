@@ -1,0 +1,92 @@
+"""GPU parity of the mixed-precision solve (complex64 inner BiCGStab, complex128 refinement).
+
+The bar is the FP64 one: the true residual of the returned x, recomputed with
+the oracle's complex128 SpMV, meets rtol; the error against the FP64 solution
+is reported and bounded by the conditioning.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hz():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2112_06465_amd as hz
+
+    return hz
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def dev_csr(A):
+    return dev(A.row_ptr), dev(A.col_idx), dev(A.vals)
+
+
+def true_relres(A, x, b):
+    return np.linalg.norm(b - O.zspmv(A, x)) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_mixed_cube_reaches_fp64_tolerance(hz, jacobi):
+    A, b, _ = W.config_cube(20)
+    tol = 1e-10
+    flags = hz.PRECOND_JACOBI if jacobi else hz.PRECOND_NONE
+    rp, ci, v = dev_csr(A)
+    x, info = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=tol, inner_rtol=1e-4, flags=flags)
+    assert info["status"] == hz.OK, info
+    assert info["outer_steps"] >= 2
+    x = x.cpu().numpy()
+    rr = true_relres(A, x, b)
+    assert rr <= tol * (1 + 1e-3), rr
+    assert abs(info["relres_true"] - rr) <= 1e-3 * rr
+    xo, io = O.zbicgstab_mixed(A, b, tol=tol, inner_tol=1e-4, jacobi=jacobi)
+    assert io["status"] == O.OK
+    x64, _ = O.zbicgstab(A, b, tol=1e-12, jacobi=jacobi)
+    err = np.linalg.norm(x - x64) / np.linalg.norm(x64)
+    print(f"mixed cube jacobi={jacobi}: outer={info['outer_steps']} inner={info['iterations']} "
+          f"(oracle {io['outer_steps']}/{io['iterations']}) relres={rr:.2e} err_vs_fp64={err:.2e}")
+    assert err < 1e-6
+
+
+def test_mixed_small_systems_match_dense_lu(hz):
+    for A, b in [W.config_cube(10, seed=3)[:2], W.config_cylinder(h=1 / 3, k=3.0, seed=1)[:2]]:
+        rp, ci, v = dev_csr(A)
+        x, info = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-11, flags=hz.PRECOND_JACOBI)
+        assert info["status"] == hz.OK
+        D = O.to_dense(A)
+        xd = np.linalg.solve(D, b)
+        x = x.cpu().numpy()
+        assert np.linalg.norm(b - D @ x) / np.linalg.norm(b) <= 1e-11 * (1 + 1e-3)
+        assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 10 * np.linalg.cond(D) * 1e-11
+
+
+def test_mixed_special_cases(hz):
+    A, b, _ = W.config_cube(6)
+    rp, ci, v = dev_csr(A)
+    x, info = hz.zbicgstab_solve_mixed(rp, ci, v, dev(np.zeros(A.n, complex)), x=dev(np.ones(A.n, complex)),
+                                       flags=hz.PRECOND_NONE)
+    assert info["status"] == hz.OK and torch.count_nonzero(x) == 0
+    x, info = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-12, max_outer=0)
+    assert info["status"] == hz.NOT_CONVERGED and info["outer_steps"] == 0
+    assert torch.count_nonzero(x) == 0
+    x, info = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-12, max_outer=1)
+    assert info["status"] == hz.NOT_CONVERGED and info["outer_steps"] == 1
+
+
+def test_mixed_cylinder_full_size(hz):
+    A, b, _ = W.config_cylinder()
+    rp, ci, v = dev_csr(A)
+    x, info = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-10, inner_rtol=1e-4, flags=hz.PRECOND_JACOBI)
+    assert info["status"] == hz.OK, info
+    rr = true_relres(A, x.cpu().numpy(), b)
+    print(f"mixed cylinder: outer={info['outer_steps']} inner={info['iterations']} relres={rr:.2e}")
+    assert rr <= 1e-10 * (1 + 1e-3)
