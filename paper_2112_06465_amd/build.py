@@ -22,7 +22,7 @@ HEADERS = ["hz_kernels.hpp"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
-    "-std=c++17",
+    "-std=c++20",
     "-fPIC",
     "-shared",
     # no packed FP32 instructions in device code

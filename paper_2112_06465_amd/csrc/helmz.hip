@@ -15,13 +15,15 @@ using hz::cx;
 using hz::Geom;
 using hz::kBlock;
 using hz::kMaxGrid;
-using hz::kMaxParts;
+using hz::kParts;
 using hz::SolverScal;
 
 struct hz_handle {
     int device;
-    double* part;          // kMaxParts * kMaxGrid partials for standalone reductions
+    double* part;          // kParts * kMaxGrid partials for standalone reductions
     int* dflag;            // device word for CSR validation
+    unsigned long long* dcount;  // device counter for the locality test
+    unsigned long long* hcount;  // pinned host copy
     int* hflag;            // pinned host word
     SolverScal* hsc;       // pinned host copy of the solver scalars
     SolverScal* hsc2;      // pinned host copy of the refinement's outer scalars
@@ -46,8 +48,9 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
         if ((call) != hipSuccess) return HZ_ERR_HIP;  \
     } while (0)
 
-// Lanes per row for the vector-CSR kernel: the smallest power of two not
-// below the mean row length, in [2, 64].  HZ_SPMV_LANES overrides (tuning).
+// Lanes per row for the vector-CSR kernels: the smallest power of two not
+// below half the mean row length, in [2, 64], so each lane holds about two
+// entries of a row.  HZ_SPMV_LANES overrides (tuning).
 int pick_lanes(int n, int64_t nnz) {
     if (const char* env = std::getenv("HZ_SPMV_LANES")) {
         int v = std::atoi(env);
@@ -55,39 +58,48 @@ int pick_lanes(int n, int64_t nnz) {
     }
     const double mean = n > 0 ? double(nnz) / double(n) : 1.0;
     int L = 2;
-    while (L < 64 && L < mean) L *= 2;
+    while (L < 64 && 2 * L < mean) L *= 2;
     return L;
 }
 
-// Contiguous chunks of rows per block (see hz_kernels.hpp): G blocks, a
-// multiple of 8 when there are at least 8, each chunk a multiple of `step`.
+// Contiguous chunks of rows per block (see hz_kernels.hpp): G <= kMaxGrid
+// blocks, a multiple of 8 when there are at least 8, chunk = ceil(n / G).
 Geom geom_for(int n, int step) {
     const int64_t steps = (int64_t(n) + step - 1) / step;
     int64_t G = steps < kMaxGrid ? steps : kMaxGrid;
     if (G < 1) G = 1;
     if (G >= hz::kXcd) G -= G % hz::kXcd;
-    const int64_t per = (steps + G - 1) / G;
-    return Geom{int(G), int(per * step)};
+    const int64_t chunk = (int64_t(n) + G - 1) / G;
+    return Geom{int(G), int(chunk > 0 ? chunk : 1)};
 }
 
 inline dim3 grid1(int64_t n) { return dim3(unsigned((n + kBlock - 1) / kBlock)); }
 
+// Entries per lane batch: U independent loads of each kind per lane.
+constexpr int batch_for(int L) { return L >= 16 ? 1 : 2; }
+
+// Calls f.template operator()<L, U>() for the lane width chosen at run time.
+template <typename F> void with_lanes(int L, F&& f) {
+    switch (L) {
+        case 2: f.template operator()<2, batch_for(2)>(); break;
+        case 4: f.template operator()<4, batch_for(4)>(); break;
+        case 8: f.template operator()<8, batch_for(8)>(); break;
+        case 16: f.template operator()<16, batch_for(16)>(); break;
+        case 32: f.template operator()<32, batch_for(32)>(); break;
+        default: f.template operator()<64, batch_for(64)>(); break;
+    }
+}
+
 template <typename T, int EPI>
 void launch_spmv(int L, const hz::SpmvArgs<T>& a, hipStream_t s) {
-    const dim3 g(a.geo.G), b(kBlock);
-    switch (L) {
-        case 2: hipLaunchKernelGGL((hz::k_spmv<T, 2, EPI>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((hz::k_spmv<T, 4, EPI>), g, b, 0, s, a); break;
-        case 8: hipLaunchKernelGGL((hz::k_spmv<T, 8, EPI>), g, b, 0, s, a); break;
-        case 16: hipLaunchKernelGGL((hz::k_spmv<T, 16, EPI>), g, b, 0, s, a); break;
-        case 32: hipLaunchKernelGGL((hz::k_spmv<T, 32, EPI>), g, b, 0, s, a); break;
-        default: hipLaunchKernelGGL((hz::k_spmv<T, 64, EPI>), g, b, 0, s, a); break;
-    }
+    with_lanes(L, [&]<int LL, int UU>() {
+        hipLaunchKernelGGL((hz::k_spmv<T, LL, UU, EPI>), dim3(a.geo.G), dim3(kBlock), 0, s, a);
+    });
 }
 
 template <typename T>
 hz::SpmvArgs<T> spmv_args(int n, Geom geo, const int* rp, const int* ci, const cx<T>* v, const cx<T>* x, cx<T>* y,
-                          const cx<T>* w, double* part, const SolverScal* sc) {
+                          const cx<T>* w, double* part) {
     hz::SpmvArgs<T> a;
     a.n = n;
     a.geo = geo;
@@ -98,24 +110,6 @@ hz::SpmvArgs<T> spmv_args(int n, Geom geo, const int* rp, const int* ci, const c
     a.y = y;
     a.w = w;
     a.part = part;
-    a.sc = sc;
-    return a;
-}
-
-template <typename T>
-hz::VecArgs<T> vec_args(int n, Geom geo, const cx<T>* a_, const cx<T>* b_, const cx<T>* c_, cx<T>* o1, cx<T>* o2,
-                        const cx<T>* w, double* part, SolverScal* sc) {
-    hz::VecArgs<T> a;
-    a.n = n;
-    a.geo = geo;
-    a.a = a_;
-    a.b = b_;
-    a.c = c_;
-    a.o1 = o1;
-    a.o2 = o2;
-    a.w = w;
-    a.part = part;
-    a.sc = sc;
     return a;
 }
 
@@ -127,6 +121,24 @@ int validate_csr(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, con
     HZ_HIP(hipMemcpyAsync(h->hflag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
     HZ_HIP(hipStreamSynchronize(s));
     return *h->hflag ? HZ_ERR_INVALID : HZ_OK;
+}
+
+// Enqueue the locality count: entries with |col - row| > kFarRows.  Read
+// *h->hcount after the next stream synchronisation.
+constexpr int kFarRows = 32768;  // 512 KiB of complex128 x on either side of the row
+int enqueue_far_count(hz_handle* h, hipStream_t s, int n, const int* rp, const int* ci) {
+    HZ_HIP(hipMemsetAsync(h->dcount, 0, sizeof(unsigned long long), s));
+    hipLaunchKernelGGL(hz::k_far_count, grid1(n), dim3(kBlock), 0, s, n, rp, ci, kFarRows, h->dcount);
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipMemcpyAsync(h->hcount, h->dcount, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    return HZ_OK;
+}
+
+// Fused iteration (p and s formed per gathered column) unless more than 5 %
+// of the entries lie far from the diagonal; HZ_FUSED=0/1 overrides.
+bool choose_fused(const hz_handle* h, int64_t nnz) {
+    if (const char* env = std::getenv("HZ_FUSED")) return std::atoi(env) != 0;
+    return double(*h->hcount) <= 0.05 * double(nnz);
 }
 
 int check_csr_args(int n, int nnz, const int* rp, const int* ci, const void* vals) {
@@ -142,7 +154,7 @@ int check_csr_args(int n, int nnz, const int* rp, const int* ci, const void* val
 struct SolveWs {
     SolverScal* sc;
     double* part;
-    void* vec[6];  // r, rhat, p, v, s, t
+    void* vec[8];  // r, rhat, p0, p1, v0, v1, s, t
     void* dinv;
     void* ahat;
 };
@@ -158,7 +170,7 @@ size_t ws_layout(int n, int64_t nnz, bool jacobi, char* base, SolveWs* out) {
     };
     SolveWs w{};
     w.sc = static_cast<SolverScal*>(take(sizeof(SolverScal)));
-    w.part = static_cast<double*>(take(sizeof(double) * kMaxParts * kMaxGrid));
+    w.part = static_cast<double*>(take(sizeof(double) * kParts * kMaxGrid));
     for (auto& v : w.vec) v = take(vb);
     w.dinv = jacobi ? take(vb) : nullptr;
     w.ahat = jacobi ? take(sizeof(cx<T>) * size_t(nnz > 0 ? nnz : 1)) : nullptr;
@@ -166,50 +178,66 @@ size_t ws_layout(int n, int64_t nnz, bool jacobi, char* base, SolveWs* out) {
     return off;
 }
 
+// Arguments shared by the three kernels of an iteration.
+template <typename T>
+hz::BicgArgs<T> bicg_args(int n, Geom geo, const int* rp, const int* ci, const cx<T>* av, cx<T>* x, const SolveWs& w) {
+    hz::BicgArgs<T> a;
+    a.n = n;
+    a.geo = geo;
+    a.row_ptr = rp;
+    a.col_idx = ci;
+    a.vals = av;
+    a.r = static_cast<cx<T>*>(w.vec[0]);
+    a.rh = static_cast<const cx<T>*>(w.vec[1]);
+    a.p[0] = static_cast<cx<T>*>(w.vec[2]);
+    a.p[1] = static_cast<cx<T>*>(w.vec[3]);
+    a.v[0] = static_cast<cx<T>*>(w.vec[4]);
+    a.v[1] = static_cast<cx<T>*>(w.vec[5]);
+    a.s = static_cast<cx<T>*>(w.vec[6]);
+    a.t = static_cast<cx<T>*>(w.vec[7]);
+    a.x = x;
+    a.part = w.part;
+    a.sc = w.sc;
+    return a;
+}
+
 // The iteration loop of BiCGStab on the (possibly column-scaled) matrix
 // `av`.  On entry r, rhat and the scalars are initialised (k_fin_init ran).
-// Launches at most maxiter iterations, polling sc->done every `poll`
-// iterations.  x holds the iterate (the scaled one, y, under Jacobi).
+// Launches at most maxiter iterations of three kernels, then one more
+// A-kernel that concludes the last iteration; polls sc->done between
+// chunks of 8, 16, ..., 64 iterations.  x holds the iterate (the scaled one,
+// y, under Jacobi).
 template <typename T>
 int iterate(hz_handle* h, hipStream_t s, int n, int L, Geom geo, const int* rp, const int* ci, const cx<T>* av,
-            cx<T>* x, const SolveWs& w, int maxiter) {
-    cx<T>* r = static_cast<cx<T>*>(w.vec[0]);
-    cx<T>* rh = static_cast<cx<T>*>(w.vec[1]);
-    cx<T>* p = static_cast<cx<T>*>(w.vec[2]);
-    cx<T>* v = static_cast<cx<T>*>(w.vec[3]);
-    cx<T>* sv = static_cast<cx<T>*>(w.vec[4]);
-    cx<T>* t = static_cast<cx<T>*>(w.vec[5]);
-    SolverScal* sc = w.sc;
-    double* part = w.part;
-    const dim3 G(geo.G), B(kBlock), one(1);
-
-    const auto pupd = vec_args<T>(n, geo, r, nullptr, v, p, nullptr, nullptr, nullptr, sc);
-    const auto sp1 = spmv_args<T>(n, geo, rp, ci, av, p, v, rh, part, sc);
-    const auto supd = vec_args<T>(n, geo, r, v, nullptr, sv, nullptr, nullptr, part, sc);
-    const auto sp2 = spmv_args<T>(n, geo, rp, ci, av, sv, t, nullptr, part, sc);
-    const auto xr = vec_args<T>(n, geo, p, sv, t, x, r, rh, part, sc);
-
+            cx<T>* x, const SolveWs& w, int maxiter, bool fused) {
+    const hz::BicgArgs<T> a = bicg_args<T>(n, geo, rp, ci, av, x, w);
+    const dim3 G(geo.G), B(kBlock);
     int launched = 0, poll = 8;
-    while (launched < maxiter) {
-        const int m = (maxiter - launched) < poll ? (maxiter - launched) : poll;
-        for (int k = 0; k < m; ++k) {
-            hipLaunchKernelGGL(hz::k_pupd<T>, G, B, 0, s, pupd);
-            launch_spmv<T, hz::EPI_DOT_W>(L, sp1, s);
-            hipLaunchKernelGGL(hz::k_fin_alpha, one, B, 0, s, part, geo.G, sc);
-            hipLaunchKernelGGL(hz::k_supd<T>, G, B, 0, s, supd);
-            hipLaunchKernelGGL(hz::k_fin_half, one, B, 0, s, part, geo.G, sc);
-            launch_spmv<T, hz::EPI_TS>(L, sp2, s);
-            hipLaunchKernelGGL(hz::k_fin_omega, one, B, 0, s, part, geo.G, sc);
-            hipLaunchKernelGGL(hz::k_xr<T>, G, B, 0, s, xr);
-            hipLaunchKernelGGL(hz::k_fin_rho, one, B, 0, s, part, geo.G, sc);
+    with_lanes(L, [&]<int LL, int UU>() {
+        while (launched < maxiter) {
+            const int m = (maxiter - launched) < poll ? (maxiter - launched) : poll;
+            for (int k = 0; k < m; ++k) {
+                if (fused) {
+                    hipLaunchKernelGGL((hz::k_bicg_A<T, LL, UU>), G, B, 0, s, a);
+                    hipLaunchKernelGGL((hz::k_bicg_B<T, LL, UU>), G, B, 0, s, a);
+                } else {
+                    hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, s, a);
+                    hipLaunchKernelGGL((hz::k_bicg_A1<T, LL, UU>), G, B, 0, s, a);
+                    hipLaunchKernelGGL((hz::k_bicg_S<T>), G, B, 0, s, a);
+                    hipLaunchKernelGGL((hz::k_bicg_B1<T, LL, UU>), G, B, 0, s, a);
+                }
+                hipLaunchKernelGGL((hz::k_bicg_C<T>), G, B, 0, s, a);
+            }
+            launched += m;
+            if (launched == maxiter) hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, s, a);
+            if (hipGetLastError() != hipSuccess) return;
+            if (hipMemcpyAsync(h->hflag, &w.sc->done, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return;
+            if (hipStreamSynchronize(s) != hipSuccess) return;
+            if (*h->hflag) break;
+            if (poll < 64) poll *= 2;
         }
-        HZ_HIP(hipGetLastError());
-        launched += m;
-        HZ_HIP(hipMemcpyAsync(h->hflag, &sc->done, sizeof(int), hipMemcpyDeviceToHost, s));
-        HZ_HIP(hipStreamSynchronize(s));
-        if (*h->hflag) break;
-        if (poll < 64) poll *= 2;
-    }
+    });
+    HZ_HIP(hipGetLastError());
     return HZ_OK;
 }
 
@@ -236,7 +264,7 @@ size_t mixed_layout(int n, int64_t nnz, bool jacobi, char* base, MixedWs* out) {
     MixedWs m{};
     m.outer = static_cast<SolverScal*>(take(sizeof(SolverScal)));
     m.in.sc = static_cast<SolverScal*>(take(sizeof(SolverScal)));
-    m.in.part = static_cast<double*>(take(sizeof(double) * kMaxParts * kMaxGrid));
+    m.in.part = static_cast<double*>(take(sizeof(double) * kParts * kMaxGrid));
     for (auto& v : m.in.vec) v = take(sizeof(float2) * nn);
     m.in.dinv = jacobi ? take(sizeof(float2) * nn) : nullptr;
     m.in.ahat = take(sizeof(float2) * size_t(nnz > 0 ? nnz : 1));
@@ -272,8 +300,11 @@ int hz_handle_create(hz_handle** out) {
     hz_handle* h = new (std::nothrow) hz_handle();
     if (h == nullptr) return HZ_ERR_HIP;
     if (hipGetDevice(&h->device) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&h->part), sizeof(double) * kMaxParts * kMaxGrid) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&h->part), sizeof(double) * kParts * kMaxGrid) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&h->dflag), sizeof(int)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&h->dcount), sizeof(unsigned long long)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h->hcount), sizeof(unsigned long long), hipHostMallocDefault) !=
+            hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&h->hflag), sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&h->hsc), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&h->hsc2), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess) {
@@ -288,6 +319,8 @@ int hz_handle_destroy(hz_handle* h) {
     if (h == nullptr) return HZ_OK;
     if (h->part) (void)hipFree(h->part);
     if (h->dflag) (void)hipFree(h->dflag);
+    if (h->dcount) (void)hipFree(h->dcount);
+    if (h->hcount) (void)hipHostFree(h->hcount);
     if (h->hflag) (void)hipHostFree(h->hflag);
     if (h->hsc) (void)hipHostFree(h->hsc);
     if (h->hsc2) (void)hipHostFree(h->hsc2);
@@ -314,8 +347,7 @@ int csr_zspmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, con
     const int L = pick_lanes(n, nnz);
     const Geom geo = geom_for(n, kBlock / L);
     auto a = spmv_args<double>(n, geo, rp, ci, reinterpret_cast<const double2*>(vals),
-                               reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nullptr, nullptr,
-                               nullptr);
+                               reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nullptr, nullptr);
     launch_spmv<double, hz::EPI_NONE>(L, a, s);
     HZ_HIP(hipGetLastError());
     return HZ_OK;
@@ -329,7 +361,7 @@ int csr_cspmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, con
     const int L = pick_lanes(n, nnz);
     const Geom geo = geom_for(n, kBlock / L);
     auto a = spmv_args<float>(n, geo, rp, ci, reinterpret_cast<const float2*>(vals), reinterpret_cast<const float2*>(x),
-                              reinterpret_cast<float2*>(y), nullptr, nullptr, nullptr);
+                              reinterpret_cast<float2*>(y), nullptr, nullptr);
     launch_spmv<float, hz::EPI_NONE>(L, a, s);
     HZ_HIP(hipGetLastError());
     return HZ_OK;
@@ -412,7 +444,7 @@ int zbicgstab_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* r
     double2* xd = reinterpret_cast<double2*>(x);
     double2* r = static_cast<double2*>(w.vec[0]);
     double2* rh = static_cast<double2*>(w.vec[1]);
-    double2* t = static_cast<double2*>(w.vec[5]);
+    double2* t = static_cast<double2*>(w.vec[7]);
     double2* dinv = static_cast<double2*>(w.dinv);
 
     SolverScal* hs = h->hsc;
@@ -433,31 +465,32 @@ int zbicgstab_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* r
         HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
     } else {
         if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, dinv, xd, 1);
-        launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, Aop, xd, r, bd, w.part, nullptr), s);
+        launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, Aop, xd, r, bd, w.part + hz::kPartI * kMaxGrid), s);
         rsrc = r;
     }
-    hipLaunchKernelGGL(hz::k_init<double>, dim3(geo.G), dim3(kBlock), 0, s,
-                       vec_args<double>(n, geo, bd, rsrc, nullptr, r, rh, nullptr, w.part, w.sc));
+    hipLaunchKernelGGL(hz::k_init<double>, dim3(geo.G), dim3(kBlock), 0, s, n, geo, bd, rsrc, r, rh, w.part);
     hipLaunchKernelGGL(hz::k_fin_init, dim3(1), dim3(kBlock), 0, s, w.part, geo.G, w.sc);
     HZ_HIP(hipGetLastError());
+    rc = enqueue_far_count(h, s, n, rp, ci);
+    if (rc) return rc;
     HZ_HIP(hipMemcpyAsync(hs, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
     HZ_HIP(hipStreamSynchronize(s));
     if (hs->bad_diag) return HZ_ERR_INVALID;
 
     if (!hs->done) {
-        rc = iterate<double>(h, s, n, L, geo, rp, ci, Aop, xd, w, maxiter);
+        rc = iterate<double>(h, s, n, L, geo, rp, ci, Aop, xd, w, maxiter, choose_fused(h, nnz));
         if (rc) return rc;
     }
     hipLaunchKernelGGL(hz::k_zero_if<double>, grid1(n), dim3(kBlock), 0, s, n, w.sc, xd);
     if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, dinv, xd, 0);
     // true residual with the caller's matrix
-    launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, t, bd, w.part, nullptr), s);
+    launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, t, bd, w.part + hz::kPartI * kMaxGrid), s);
     hipLaunchKernelGGL(hz::k_fin_true, dim3(1), dim3(kBlock), 0, s, w.part, geo.G, w.sc);
     HZ_HIP(hipGetLastError());
     HZ_HIP(hipMemcpyAsync(hs, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
     HZ_HIP(hipStreamSynchronize(s));
     info->status = hs->status;
-    info->iterations = hs->iter;
+    info->iterations = hs->iters;
     info->outer_steps = 0;
     info->relres_recursive = hs->relres;
     info->relres_true = hs->relres_true;
@@ -515,22 +548,25 @@ int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const 
         hipLaunchKernelGGL(hz::k_demote_vals, grid1(nnz), B, 0, s, int64_t(nnz), ci, A, dinv64,
                            static_cast<float2*>(m.in.ahat));
     if (flags & HZ_X0_ZERO) HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
-    hipLaunchKernelGGL(hz::k_dot_part<1>, dim3(geo.G), B, 0, s, n, geo, bd, nullptr, m.in.part);
-    hipLaunchKernelGGL(hz::k_fin_bnorm, one, B, 0, s, m.in.part, geo.G, m.outer);
+    double* partI = m.in.part + hz::kPartI * kMaxGrid;
+    hipLaunchKernelGGL(hz::k_dot_part<1>, dim3(geo.G), B, 0, s, n, geo, bd, nullptr, partI);
+    hipLaunchKernelGGL(hz::k_fin_bnorm, one, B, 0, s, partI, geo.G, m.outer);
     HZ_HIP(hipGetLastError());
+    rc = enqueue_far_count(h, s, n, rp, ci);
+    if (rc) return rc;
     SolverScal* ho = h->hsc2;
     SolverScal* hi = h->hsc;
     HZ_HIP(hipMemcpyAsync(ho, m.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
     HZ_HIP(hipStreamSynchronize(s));
     if (ho->bad_diag) return HZ_ERR_INVALID;
+    const bool fused = choose_fused(h, nnz);
 
     const float2* dinv32 = jacobi ? static_cast<const float2*>(m.in.dinv) : nullptr;
     int inner_total = 0, outer = 0;
     for (;; ++outer) {
         // r = b - A x in FP64, and the outer decision
-        launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, m.r64, bd, m.in.part, nullptr),
-                                           s);
-        hipLaunchKernelGGL(hz::k_fin_outer, one, B, 0, s, m.in.part, geo.G, m.outer, outer, max_outer);
+        launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, m.r64, bd, partI), s);
+        hipLaunchKernelGGL(hz::k_fin_outer, one, B, 0, s, partI, geo.G, m.outer, outer, max_outer);
         HZ_HIP(hipGetLastError());
         HZ_HIP(hipMemcpyAsync(ho, m.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
         HZ_HIP(hipStreamSynchronize(s));
@@ -540,15 +576,16 @@ int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const 
                            m.b32);
         HZ_HIP(hipMemsetAsync(m.d32, 0, 8 * size_t(n), s));
         hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, m.in.sc, inner_rtol, maxiter);
-        hipLaunchKernelGGL(hz::k_init<float>, dim3(geo.G), B, 0, s,
-                           vec_args<float>(n, geo, m.b32, m.b32, nullptr, r32, rh32, nullptr, m.in.part, m.in.sc));
+        hipLaunchKernelGGL(hz::k_init<float>, dim3(geo.G), B, 0, s, n, geo, static_cast<const float2*>(m.b32),
+                           static_cast<const float2*>(m.b32), r32, rh32, m.in.part);
         hipLaunchKernelGGL(hz::k_fin_init, one, B, 0, s, m.in.part, geo.G, m.in.sc);
         HZ_HIP(hipGetLastError());
-        rc = iterate<float>(h, s, n, L, geo, rp, ci, static_cast<const float2*>(m.in.ahat), m.d32, m.in, maxiter);
+        rc = iterate<float>(h, s, n, L, geo, rp, ci, static_cast<const float2*>(m.in.ahat), m.d32, m.in, maxiter,
+                            fused);
         if (rc) return rc;
         HZ_HIP(hipMemcpyAsync(hi, m.in.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
         HZ_HIP(hipStreamSynchronize(s));
-        inner_total += hi->iter;
+        inner_total += hi->iters;
         if (hi->status == HZ_NONFINITE) {
             info->status = HZ_NONFINITE;
             info->iterations = inner_total;

@@ -1,8 +1,11 @@
 // Device kernels of the helmz library (gfx950 / CDNA4, wave64).
 //
-// Every kernel that reduces writes one fixed-order partial per block and a
-// single-block kernel sums the partials in index order, so results are
-// bitwise reproducible run to run (no floating-point atomics anywhere).
+// Reductions: every reducing kernel writes one fixed-order partial per block
+// (component-major, stride kMaxGrid).  The kernel that needs the total sums
+// the partials itself, redundantly in every block and in a fixed order, so
+// all blocks hold bitwise the same scalar and no single-block finaliser
+// kernel sits between two streaming kernels.  No floating-point atomics:
+// results are bitwise reproducible run to run.
 //
 // Row ownership: a launch of G blocks splits the rows into G contiguous
 // chunks.  Hardware dispatches block b to XCD (b mod 8); block b works on
@@ -19,9 +22,16 @@ namespace hz {
 
 constexpr int kWave = 64;
 constexpr int kXcd = 8;
-constexpr int kBlock = 256;
-constexpr int kMaxGrid = 2048;  // bound on blocks (= partials) of a reducing launch
-constexpr int kMaxParts = 4;    // components per partial
+constexpr int kBlock = 1024;   // threads per block (16 waves)
+constexpr int kMaxGrid = 512;  // bound on blocks (= partials) of a reducing launch: 2 blocks per CU
+#define HZ_STREAM_BOUNDS __launch_bounds__(1024, 8)  // 8 waves per SIMD (two blocks per CU): <= 64 VGPRs
+
+// partial-sum regions (component index; component c lives at part[c * kMaxGrid + block])
+constexpr int kPartA = 0;  // <rhat, v>                      (2)
+constexpr int kPartB = 2;  // ||s||^2, <t, s>, ||t||^2         (4)
+constexpr int kPartC = 6;  // <rhat, r>, ||r||^2               (3)
+constexpr int kPartI = 9;  // ||b||^2 / residual norms          (1)
+constexpr int kParts = 10;
 
 // ------------------------------------------------------------------ complex
 
@@ -51,7 +61,7 @@ template <typename T> __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx
 template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
     return mk<T>(fmaT(a.x, b.x, -a.y * b.y), fmaT(a.x, b.y, a.y * b.x));
 }
-// conj(a) b, accumulated in double
+// c + conj(a) b, accumulated in double
 __device__ __forceinline__ double2 cdotacc(double ar, double ai, double br, double bi, double2 c) {
     c.x = __builtin_fma(ar, br, c.x);
     c.x = __builtin_fma(ai, bi, c.x);
@@ -74,6 +84,7 @@ __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ bool zfinite(double2 a) { return __builtin_isfinite(a.x) && __builtin_isfinite(a.y); }
 __device__ __forceinline__ bool zzero(double2 a) { return a.x == 0.0 && a.y == 0.0; }
+template <typename T> __device__ __forceinline__ cx<T> narrow(double2 a) { return mk<T>((T)a.x, (T)a.y); }
 
 // ------------------------------------------------------------------ lane exchange (DPP / ds_swizzle)
 
@@ -127,12 +138,13 @@ template <int L, typename T> __device__ __forceinline__ T group_sum(T v) {
 }
 
 // Block sum of K doubles; the result is valid in thread 0 only.  Waves are
-// combined in a fixed order.
+// combined in a fixed order.  Safe to call repeatedly in one kernel.
 template <int K> __device__ __forceinline__ void block_sum(double (&v)[K]) {
     __shared__ double lds[kBlock / kWave][K];
     const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = group_sum<64>(v[k]);
+    __syncthreads();  // a previous call's reader is done with lds
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < K; ++k) lds[wid][k] = v[k];
@@ -148,16 +160,33 @@ template <int K> __device__ __forceinline__ void block_sum(double (&v)[K]) {
     }
 }
 
-// Sum K component arrays of G partials (component k at part[k*G + g]) in a
-// fixed order: thread t adds g = t, t+256, ... sequentially, then block_sum.
-template <int K> __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int G, double (&out)[K]) {
+// Sum of K partial components (component k at part[k*kMaxGrid + g], g < G)
+// in a fixed order, delivered to every thread of the block.
+template <int K> __device__ __forceinline__ void head_sum(const double* __restrict__ part, int G, double (&out)[K]) {
+    __shared__ double bc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         double s = 0.0;
-        for (int g = threadIdx.x; g < G; g += kBlock) s += part[k * G + g];
+        for (int g = threadIdx.x; g < G; g += kBlock) s += part[k * kMaxGrid + g];
         out[k] = s;
     }
     block_sum<K>(out);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) bc[k] = out[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = bc[k];
+}
+
+// Store a block's K partials (thread 0 holds them after block_sum).
+template <int K> __device__ __forceinline__ void store_partials(double* __restrict__ part, int lb, double (&e)[K]) {
+    block_sum<K>(e);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) part[k * kMaxGrid + lb] = e[k];
+    }
 }
 
 // ------------------------------------------------------------------ launch geometry
@@ -165,36 +194,93 @@ template <int K> __device__ __forceinline__ void sum_partials(const double* __re
 // Chunked row ownership of a launch (see the file comment).
 struct Geom {
     int G;      // blocks
-    int chunk;  // rows per block, a multiple of the rows one block step covers
+    int chunk;  // rows per block
 };
 
 __device__ __forceinline__ int logical_block(int b, int G) {
     return (G % kXcd == 0) ? (b % kXcd) * (G / kXcd) + b / kXcd : b;
 }
 
+struct RowRange {
+    int lb;
+    int64_t r0, r1;
+};
+__device__ __forceinline__ RowRange rows_of_block(int n, Geom geo) {
+    RowRange r;
+    r.lb = logical_block(blockIdx.x, geo.G);
+    r.r0 = (int64_t)r.lb * geo.chunk;
+    r.r1 = r.r0 + geo.chunk < (int64_t)n ? r.r0 + geo.chunk : (int64_t)n;
+    return r;
+}
+
+// ------------------------------------------------------------------ row product (vector CSR)
+
+// sum_p vals_p * op(col_p) over one row, computed by L lanes: lane l takes
+// entries beg+l, beg+l+L, ...; each lane issues U (col, value) loads, then U
+// operand gathers, then U complex FMAs, so U independent loads of each kind
+// are in flight per lane.  Returns the lane's partial (the caller sums the
+// group).  Entry order per lane is sequential, so results are deterministic.
+template <typename T, int L, int U, typename Op>
+__device__ __forceinline__ cx<T> row_partial(int beg, int end, int lane, const int* __restrict__ ci,
+                                             const cx<T>* __restrict__ vals, Op op) {
+    cx<T> acc = mk<T>(T(0), T(0));
+    for (int base = beg + lane; base < end; base += L * U) {
+        int c[U];
+        cx<T> a[U], o[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = base + u * L;
+            if (p < end) {
+                c[u] = ci[p];
+                a[u] = vals[p];
+            } else {
+                c[u] = -1;
+                a[u] = mk<T>(T(0), T(0));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) o[u] = c[u] >= 0 ? op(c[u]) : mk<T>(T(0), T(0));
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c[u] >= 0) acc = cfma<T>(a[u], o[u], acc);
+    }
+    return acc;
+}
+
 // ------------------------------------------------------------------ solver scalars (device resident)
 
+// Written only by thread 0 of block 0 of a kernel, and read only by later
+// kernels (never by other blocks of the writing kernel), except `done`,
+// whose early read by other blocks leads to the same exit they compute.
 struct alignas(256) SolverScal {
-    double2 rho;    // <rhat, r> for the current iteration
-    double2 alpha;  // rho / <rhat, v>
-    double2 omega;  // <t, s> / <t, t>
-    double2 beta;   // (rho_new / rho) (alpha / omega)
-    double bnorm;   // ||b||
+    double2 rho2[2];  // rho of iteration i in slot i & 1
+    double2 alpha;    // alpha of the current iteration
+    double2 omega;    // omega of the last completed iteration
+    double2 beta;
+    double bnorm;  // ||b||
     double rtol;
     double relres;       // last recursive ||r|| / ||b|| (or ||s|| / ||b||)
     double relres_true;  // filled by the final residual check
-    int iter;            // current iteration, 1-based
+    double outer_rn;     // refinement: ||b - A x|| of the current outer step
+    int iter;            // next iteration to run (1-based); written by the third kernel of an iteration
+    int cur;             // iteration in progress; written by the first kernel of an iteration
     int maxiter;
     int status;  // solver status once done
     int done;    // 1 once the solve has ended (all later kernels are no-ops)
-    int half;    // the half step met the tolerance: x += alpha p and stop
-    int first;   // iteration 1: p = r
+    int iters;   // reported iteration count
     int zero_x;  // ||b|| = 0: the solution is x = 0
     int bad_diag;  // Jacobi requested with a zero diagonal entry
-    double outer_rn;  // refinement: ||b - A x|| of the current outer step
+    int pending;   // half-step exit taken in iteration `pending`; the next A-kernel concludes
 };
 
 enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = 2, ST_NONFINITE = 3 };
+
+__device__ __forceinline__ void finish(SolverScal* sc, int status, int iterations) {
+    sc->status = status;
+    sc->iters = iterations;
+    sc->done = 1;
+}
+__device__ __forceinline__ bool leader() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
 // Reset a scalar block before a solve (one thread).
 __global__ void k_sc_init(SolverScal* sc, double rtol, int maxiter) {
@@ -202,23 +288,15 @@ __global__ void k_sc_init(SolverScal* sc, double rtol, int maxiter) {
     SolverScal z = {};
     z.rtol = rtol;
     z.maxiter = maxiter;
-    z.status = 1;
+    z.status = ST_NOT_CONVERGED;
     *sc = z;
 }
 
-__device__ __forceinline__ void finish(SolverScal* sc, int status, int iterations) {
-    sc->status = status;
-    sc->iter = iterations;
-    sc->done = 1;
-}
-
-// ------------------------------------------------------------------ SpMV with fused epilogues
+// ------------------------------------------------------------------ standalone SpMV with residual epilogue
 
 enum : int {
-    EPI_NONE = 0,   // y = A x
-    EPI_DOT_W = 1,  // y = A x;  partial conj(w_i) y_i            (2 comps)
-    EPI_TS = 2,     // y = A x;  partials conj(y_i) x_i, |y_i|^2   (3 comps)
-    EPI_RESID = 3   // y = w - A x; partial |y_i|^2                (1 comp)
+    EPI_NONE = 0,  // y = A x
+    EPI_RESID = 1  // y = w - A x; partial ||y||^2 (1 component)
 };
 
 template <typename T> struct SpmvArgs {
@@ -229,39 +307,23 @@ template <typename T> struct SpmvArgs {
     const cx<T>* __restrict__ vals;
     const cx<T>* __restrict__ x;
     cx<T>* __restrict__ y;
-    const cx<T>* __restrict__ w;  // rhat (EPI_DOT_W) or b (EPI_RESID)
-    double* __restrict__ part;    // partials, component-major, stride geo.G
-    const SolverScal* sc;         // skip when done (and, for EPI_TS, on a half-step exit); may be null
+    const cx<T>* __restrict__ w;  // b for EPI_RESID
+    double* __restrict__ part;    // region for EPI_RESID's partial
 };
 
-template <int EPI> constexpr int epi_parts() { return EPI == EPI_DOT_W ? 2 : EPI == EPI_TS ? 3 : EPI == EPI_RESID ? 1 : 0; }
-
-// Vector CSR: L lanes per row, BLOCK/L rows per block step.  Lane l of a row
-// handles entries beg+l, beg+l+L, ...; the row total is a DPP group sum.
-template <typename T, int L, int EPI>
-__global__ __launch_bounds__(kBlock) void k_spmv(const SpmvArgs<T> a) {
-    if (a.sc != nullptr) {
-        if (a.sc->done) return;
-        if (EPI == EPI_TS && a.sc->half) return;
-    }
-    constexpr int RPS = kBlock / L;  // rows per block step
-    constexpr int K = epi_parts<EPI>();
-    const int lb = logical_block(blockIdx.x, a.geo.G);
-    const int64_t r0 = (int64_t)lb * a.geo.chunk;
-    const int64_t r1 = r0 + a.geo.chunk < (int64_t)a.n ? r0 + a.geo.chunk : (int64_t)a.n;
+template <typename T, int L, int U, int EPI>
+__global__ HZ_STREAM_BOUNDS void k_spmv(const SpmvArgs<T> a) {
+    constexpr int RPS = kBlock / L;
+    const RowRange rr = rows_of_block(a.n, a.geo);
     const int g = threadIdx.x / L, lane = threadIdx.x % L;
-    double e[K > 0 ? K : 1];
-#pragma unroll
-    for (int k = 0; k < (K > 0 ? K : 1); ++k) e[k] = 0.0;
-
-    for (int64_t base = r0; base < r1; base += RPS) {  // uniform trip count in the block
+    const cx<T>* __restrict__ xv = a.x;
+    auto op = [xv](int c) { return xv[c]; };
+    double e[1] = {0.0};
+    for (int64_t base = rr.r0; base < rr.r1; base += RPS) {  // uniform trip count in the block
         const int64_t row = base + g;
-        const bool ok = row < r1;
+        const bool ok = row < rr.r1;
         cx<T> acc = mk<T>(T(0), T(0));
-        if (ok) {
-            const int beg = a.row_ptr[row], end = a.row_ptr[row + 1];
-            for (int p = beg + lane; p < end; p += L) acc = cfma<T>(a.vals[p], a.x[a.col_idx[p]], acc);
-        }
+        if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, op);
         acc.x = group_sum<L>(acc.x);
         acc.y = group_sum<L>(acc.y);
         if (ok && lane == 0) {
@@ -273,253 +335,434 @@ __global__ __launch_bounds__(kBlock) void k_spmv(const SpmvArgs<T> a) {
                 e[0] = __builtin_fma((double)acc.y, (double)acc.y, e[0]);
             }
             a.y[row] = acc;
-            if constexpr (EPI == EPI_DOT_W) {
-                const cx<T> wv = a.w[row];
-                double2 c = mk<double>(e[0], e[1]);
-                c = cdotacc(wv.x, wv.y, acc.x, acc.y, c);
-                e[0] = c.x;
-                e[1] = c.y;
-            }
-            if constexpr (EPI == EPI_TS) {
-                const cx<T> sv = a.x[row];
-                double2 c = mk<double>(e[0], e[1]);
-                c = cdotacc(acc.x, acc.y, sv.x, sv.y, c);
-                e[0] = c.x;
-                e[1] = c.y;
-                e[2] = __builtin_fma((double)acc.x, (double)acc.x, e[2]);
-                e[2] = __builtin_fma((double)acc.y, (double)acc.y, e[2]);
-            }
         }
     }
-    if constexpr (K > 0) {
-        block_sum<K>(e);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) a.part[k * a.geo.G + lb] = e[k];
-        }
-    }
+    if constexpr (EPI == EPI_RESID) store_partials<1>(a.part, rr.lb, e);
 }
 
-// ------------------------------------------------------------------ element-wise kernels
+// ------------------------------------------------------------------ BiCGStab: three kernels per iteration
+//
+// Iteration i (Section 7's P-BiCGSTAB, right-preconditioned; A here is the
+// column-scaled matrix under Jacobi):
+//   A-kernel: decide the end of iteration i-1 from <rhat,r>, ||r||; beta;
+//             v = A p with p = r + beta (p_old - omega v_old) formed for every
+//             gathered column; store p, v; partial <rhat, v>.
+//   B-kernel: alpha = rho / <rhat, v>; t = A s with s = r - alpha v formed for
+//             every gathered column; store s, t; partials ||s||^2, <t,s>, ||t||^2.
+//   C-kernel: half-step test on ||s||; omega = <t,s>/<t,t>;
+//             x += alpha p + omega s; r = s - omega t; partials <rhat,r>, ||r||^2.
+// p and v are double-buffered by the parity of i, so the A-kernel reads the
+// old vectors while writing the new ones.
 
-#define HZ_ROWS(a)                                                                           \
-    const int lb = logical_block(blockIdx.x, (a).geo.G);                                     \
-    const int64_t r0 = (int64_t)lb * (a).geo.chunk;                                          \
-    const int64_t r1 = r0 + (a).geo.chunk < (int64_t)(a).n ? r0 + (a).geo.chunk : (int64_t)(a).n
-
-template <typename T> struct VecArgs {
+template <typename T> struct BicgArgs {
     int n;
     Geom geo;
-    const cx<T>* __restrict__ a;
-    const cx<T>* __restrict__ b;
-    const cx<T>* __restrict__ c;
-    cx<T>* __restrict__ o1;
-    cx<T>* __restrict__ o2;
-    const cx<T>* __restrict__ w;
-    double* __restrict__ part;
+    const int* __restrict__ row_ptr;
+    const int* __restrict__ col_idx;
+    const cx<T>* __restrict__ vals;
+    cx<T>* r;
+    const cx<T>* rh;
+    cx<T>* p[2];
+    cx<T>* v[2];
+    cx<T>* s;
+    cx<T>* t;
+    cx<T>* x;
+    double* part;
     SolverScal* sc;
 };
 
-// p = r                       (first iteration)
-// p = r + beta (p - omega v)  (otherwise)            a = r, c = v, o1 = p
-template <typename T> __global__ __launch_bounds__(kBlock) void k_pupd(const VecArgs<T> a) {
-    if (a.sc->done) return;
-    HZ_ROWS(a);
-    const bool first = a.sc->first != 0;
-    const double2 bd = a.sc->beta, od = a.sc->omega;
-    const cx<T> beta = mk<T>((T)bd.x, (T)bd.y), omega = mk<T>((T)od.x, (T)od.y);
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
-        const cx<T> r = a.a[i];
-        if (first) {
-            a.o1[i] = r;
-        } else {
-            const cx<T> p = a.o1[i], v = a.c[i];
-            cx<T> d = mk<T>(p.x - fmaT(omega.x, v.x, -omega.y * v.y), p.y - fmaT(omega.x, v.y, omega.y * v.x));
-            a.o1[i] = cfma<T>(beta, d, r);
+// Start of iteration i = sc->iter: conclude iteration i-1 (convergence on
+// ||r||, breakdown, iteration limit) from the partials <rhat, r>, ||r||^2,
+// then rho_i and beta.  Returns false when the solve has ended (every block
+// returns); block 0 records the decision.
+struct IterStart {
+    int it;
+    double2 rho, beta, omega;
+};
+template <typename T>
+__device__ __forceinline__ bool iteration_start(const BicgArgs<T>& a, IterStart& st) {
+    SolverScal* sc = a.sc;
+    if (sc->done) return false;
+    if (sc->pending) {  // every block of the previous kernel has applied x += alpha p
+        if (leader()) finish(sc, ST_OK, sc->pending);
+        return false;
+    }
+    const int it = sc->iter;
+    double h[3];
+    head_sum<3>(a.part + kPartC * kMaxGrid, a.geo.G, h);
+    const double2 rho = mk<double>(h[0], h[1]);
+    double2 beta = mk<double>(0.0, 0.0), om = mk<double>(0.0, 0.0);
+    if (it > 1) {
+        const double rel = __builtin_sqrt(h[2]) / sc->bnorm;
+        om = sc->omega;
+        int stt = -1, sit = 0;
+        if (!__builtin_isfinite(rel)) stt = ST_NONFINITE, sit = it - 1;
+        else if (rel <= sc->rtol) stt = ST_OK, sit = it - 1;
+        else if (zzero(om)) stt = ST_BREAKDOWN, sit = it - 1;
+        else if (it - 1 >= sc->maxiter) stt = ST_NOT_CONVERGED, sit = sc->maxiter;
+        else if (!zfinite(rho)) stt = ST_NONFINITE, sit = it;
+        else if (zzero(rho)) stt = ST_BREAKDOWN, sit = it;
+        else {
+            beta = zmul(zdiv(rho, sc->rho2[(it - 1) & 1]), zdiv(sc->alpha, om));
+            if (!zfinite(beta)) stt = ST_NONFINITE, sit = it;
+        }
+        if (leader()) sc->relres = rel;
+        if (stt >= 0) {
+            if (leader()) finish(sc, stt, sit);
+            return false;
         }
     }
-}
-
-// s = r - alpha v ; partial ||s||^2                  a = r, b = v, o1 = s
-template <typename T> __global__ __launch_bounds__(kBlock) void k_supd(const VecArgs<T> a) {
-    if (a.sc->done) return;
-    HZ_ROWS(a);
-    const double2 ad = a.sc->alpha;
-    const cx<T> al = mk<T>((T)ad.x, (T)ad.y);
-    double e[1] = {0.0};
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
-        const cx<T> r = a.a[i], v = a.b[i];
-        cx<T> s = cfma<T>(mk<T>(-al.x, -al.y), v, r);
-        a.o1[i] = s;
-        e[0] = __builtin_fma((double)s.x, (double)s.x, e[0]);
-        e[0] = __builtin_fma((double)s.y, (double)s.y, e[0]);
+    if (leader()) {
+        sc->rho2[it & 1] = rho;
+        sc->beta = beta;
+        sc->cur = it;
     }
-    block_sum<1>(e);
-    if (threadIdx.x == 0) a.part[lb] = e[0];
+    st.it = it;
+    st.rho = rho;
+    st.beta = beta;
+    st.omega = om;
+    return true;
 }
 
-// Full step: x += alpha p + omega s ; r = s - omega t ; partials conj(rhat) r, ||r||^2
-// Half-step exit: x += alpha p only.      a = p, b = s, c = t, o1 = x, o2 = r, w = rhat
-template <typename T> __global__ __launch_bounds__(kBlock) void k_xr(const VecArgs<T> a) {
-    if (a.sc->done) return;
-    HZ_ROWS(a);
-    const double2 ad = a.sc->alpha, od = a.sc->omega;
-    const cx<T> al = mk<T>((T)ad.x, (T)ad.y), om = mk<T>((T)od.x, (T)od.y);
-    if (a.sc->half) {
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) a.o1[i] = cfma<T>(al, a.a[i], a.o1[i]);
+// p_i = r_i (first iteration) or r_i + beta (p_old_i - omega v_old_i)
+template <typename T>
+__device__ __forceinline__ cx<T> p_update(bool first, cx<T> bt, cx<T> omt, cx<T> rc, cx<T> pc, cx<T> vc) {
+    if (first) return rc;
+    const cx<T> d = mk<T>(pc.x - fmaT(omt.x, vc.x, -omt.y * vc.y), pc.y - fmaT(omt.x, vc.y, omt.y * vc.x));
+    return cfma<T>(bt, d, rc);
+}
+
+template <typename T, int L, int U>
+__global__ HZ_STREAM_BOUNDS void k_bicg_A(const BicgArgs<T> a) {
+    IterStart st;
+    if (!iteration_start(a, st)) return;
+    const int it = st.it;
+    const double2 beta = st.beta, om = st.omega;
+    const bool first = it == 1;
+    const cx<T> bt = narrow<T>(beta), omt = narrow<T>(om);
+    const cx<T>* __restrict__ r = a.r;
+    const cx<T>* __restrict__ pold = a.p[(it - 1) & 1];
+    const cx<T>* __restrict__ vold = a.v[(it - 1) & 1];
+    cx<T>* __restrict__ pnew = a.p[it & 1];
+    cx<T>* __restrict__ vnew = a.v[it & 1];
+    auto pcol = [=](int c) {
+        if (first) return r[c];
+        return p_update<T>(false, bt, omt, r[c], pold[c], vold[c]);
+    };
+    constexpr int RPS = kBlock / L;
+    const RowRange rr = rows_of_block(a.n, a.geo);
+    const int g = threadIdx.x / L, lane = threadIdx.x % L;
+    double e[2] = {0.0, 0.0};
+    for (int64_t base = rr.r0; base < rr.r1; base += RPS) {
+        const int64_t row = base + g;
+        const bool ok = row < rr.r1;
+        cx<T> acc = mk<T>(T(0), T(0));
+        if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, pcol);
+        acc.x = group_sum<L>(acc.x);
+        acc.y = group_sum<L>(acc.y);
+        if (ok && lane == 0) {
+            pnew[row] = pcol((int)row);
+            vnew[row] = acc;
+            const cx<T> w = a.rh[row];
+            double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+        }
+    }
+    store_partials<2>(a.part + kPartA * kMaxGrid, rr.lb, e);
+}
+
+template <typename T, int L, int U>
+__global__ HZ_STREAM_BOUNDS void k_bicg_B(const BicgArgs<T> a) {
+    SolverScal* sc = a.sc;
+    if (sc->done) return;
+    const int it = sc->cur;
+    double h[2];
+    head_sum<2>(a.part + kPartA * kMaxGrid, a.geo.G, h);
+    const double2 sigma = mk<double>(h[0], h[1]);
+    if (!zfinite(sigma) || zzero(sigma)) {
+        if (leader()) finish(sc, zzero(sigma) ? ST_BREAKDOWN : ST_NONFINITE, it);
         return;
     }
+    const double2 alpha = zdiv(sc->rho2[it & 1], sigma);
+    if (leader()) sc->alpha = alpha;
+    const cx<T> al = narrow<T>(alpha);
+    const cx<T>* __restrict__ r = a.r;
+    const cx<T>* __restrict__ v = a.v[it & 1];
+    auto scol = [=](int c) { return cfma<T>(mk<T>(-al.x, -al.y), v[c], r[c]); };
+    constexpr int RPS = kBlock / L;
+    const RowRange rr = rows_of_block(a.n, a.geo);
+    const int g = threadIdx.x / L, lane = threadIdx.x % L;
+    double e[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t base = rr.r0; base < rr.r1; base += RPS) {
+        const int64_t row = base + g;
+        const bool ok = row < rr.r1;
+        cx<T> acc = mk<T>(T(0), T(0));
+        if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, scol);
+        acc.x = group_sum<L>(acc.x);
+        acc.y = group_sum<L>(acc.y);
+        if (ok && lane == 0) {
+            const cx<T> s = scol((int)row);
+            a.s[row] = s;
+            a.t[row] = acc;
+            e[0] = __builtin_fma((double)s.x, (double)s.x, e[0]);
+            e[0] = __builtin_fma((double)s.y, (double)s.y, e[0]);
+            double2 c = cdotacc(acc.x, acc.y, s.x, s.y, mk<double>(e[1], e[2]));
+            e[1] = c.x;
+            e[2] = c.y;
+            e[3] = __builtin_fma((double)acc.x, (double)acc.x, e[3]);
+            e[3] = __builtin_fma((double)acc.y, (double)acc.y, e[3]);
+        }
+    }
+    store_partials<4>(a.part + kPartB * kMaxGrid, rr.lb, e);
+}
+
+template <typename T>
+__global__ HZ_STREAM_BOUNDS void k_bicg_C(const BicgArgs<T> a) {
+    SolverScal* sc = a.sc;
+    if (sc->done) return;
+    const int it = sc->cur;
+    double h[4];
+    head_sum<4>(a.part + kPartB * kMaxGrid, a.geo.G, h);
+    const double rel = __builtin_sqrt(h[0]) / sc->bnorm;
+    const double2 alpha = sc->alpha;
+    const cx<T> al = narrow<T>(alpha);
+    const cx<T>* __restrict__ p = a.p[it & 1];
+    const RowRange rr = rows_of_block(a.n, a.geo);
+    if (!__builtin_isfinite(rel)) {
+        if (leader()) finish(sc, ST_NONFINITE, it);
+        return;
+    }
+    if (rel <= sc->rtol) {  // half-step exit: x += alpha p (concluded by the next A-kernel)
+        for (int64_t i = rr.r0 + threadIdx.x; i < rr.r1; i += kBlock) a.x[i] = cfma<T>(al, p[i], a.x[i]);
+        if (leader()) {
+            sc->relres = rel;
+            sc->pending = it;
+        }
+        return;
+    }
+    const double2 ts = mk<double>(h[1], h[2]);
+    const double tt = h[3];
+    int st = -1;
+    double2 om = mk<double>(0.0, 0.0);
+    if (!zfinite(ts) || !__builtin_isfinite(tt)) st = ST_NONFINITE;
+    else if (tt == 0.0) st = ST_BREAKDOWN;
+    else {
+        om = zdiv(ts, mk<double>(tt, 0.0));
+        if (!zfinite(om)) st = ST_NONFINITE;
+    }
+    if (st >= 0) {
+        if (leader()) finish(sc, st, it);
+        return;
+    }
+    if (leader()) {
+        sc->omega = om;
+        sc->iter = it + 1;
+    }
+    const cx<T> omt = narrow<T>(om), nom = mk<T>(-omt.x, -omt.y);
     double e[3] = {0.0, 0.0, 0.0};
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
-        const cx<T> p = a.a[i], s = a.b[i], t = a.c[i], rh = a.w[i];
-        cx<T> x = a.o1[i];
-        x = cfma<T>(al, p, x);
-        x = cfma<T>(om, s, x);
-        a.o1[i] = x;
-        const cx<T> r = cfma<T>(mk<T>(-om.x, -om.y), t, s);
-        a.o2[i] = r;
-        double2 c = mk<double>(e[0], e[1]);
-        c = cdotacc(rh.x, rh.y, r.x, r.y, c);
+    for (int64_t i = rr.r0 + threadIdx.x; i < rr.r1; i += kBlock) {
+        const cx<T> sv = a.s[i], tv = a.t[i], rh = a.rh[i];
+        cx<T> x = a.x[i];
+        x = cfma<T>(al, p[i], x);
+        x = cfma<T>(omt, sv, x);
+        a.x[i] = x;
+        const cx<T> r = cfma<T>(nom, tv, sv);
+        a.r[i] = r;
+        double2 c = cdotacc(rh.x, rh.y, r.x, r.y, mk<double>(e[0], e[1]));
         e[0] = c.x;
         e[1] = c.y;
         e[2] = __builtin_fma((double)r.x, (double)r.x, e[2]);
         e[2] = __builtin_fma((double)r.y, (double)r.y, e[2]);
     }
-    block_sum<3>(e);
-    if (threadIdx.x == 0) {
-        a.part[lb] = e[0];
-        a.part[a.geo.G + lb] = e[1];
-        a.part[2 * a.geo.G + lb] = e[2];
-    }
+    store_partials<3>(a.part + kPartC * kMaxGrid, rr.lb, e);
 }
 
-// Solve set-up: r = src, rhat = src; partials ||b||^2, ||r||^2.
-// a = b, b = src (b itself, or the residual b - A x0), o1 = r, o2 = rhat
-template <typename T> __global__ __launch_bounds__(kBlock) void k_init(const VecArgs<T> a) {
-    HZ_ROWS(a);
+
+// ------------------------------------------------------------------ gather-light variant (five kernels)
+//
+// For matrices whose column indices are far from the row (a random node
+// numbering), forming p and s for every gathered column multiplies the
+// number of scattered reads.  This variant materialises them first, so
+// each product gathers one vector:
+//   P-kernel: iteration_start, p = r + beta (p_old - omega v_old)   (element-wise)
+//   A1-kernel: v = A p; partial <rhat, v>
+//   S-kernel: alpha = rho / <rhat, v>; s = r - alpha v; partial ||s||^2
+//   B1-kernel: t = A s; partials <t, s>, ||t||^2
+//   C-kernel: as in the fused variant.
+
+template <typename T>
+__global__ HZ_STREAM_BOUNDS void k_bicg_P(const BicgArgs<T> a) {
+    IterStart st;
+    if (!iteration_start(a, st)) return;
+    const int it = st.it;
+    const bool first = it == 1;
+    const cx<T> bt = narrow<T>(st.beta), omt = narrow<T>(st.omega);
+    const cx<T>* __restrict__ pold = a.p[(it - 1) & 1];
+    const cx<T>* __restrict__ vold = a.v[(it - 1) & 1];
+    cx<T>* __restrict__ pnew = a.p[it & 1];
+    const RowRange rr = rows_of_block(a.n, a.geo);
+    for (int64_t i = rr.r0 + threadIdx.x; i < rr.r1; i += kBlock)
+        pnew[i] = first ? a.r[i] : p_update<T>(false, bt, omt, a.r[i], pold[i], vold[i]);
+}
+
+template <typename T, int L, int U>
+__global__ HZ_STREAM_BOUNDS void k_bicg_A1(const BicgArgs<T> a) {
+    SolverScal* sc = a.sc;
+    if (sc->done || sc->pending) return;
+    const int it = sc->cur;
+    const cx<T>* __restrict__ p = a.p[it & 1];
+    cx<T>* __restrict__ v = a.v[it & 1];
+    auto pcol = [p](int c) { return p[c]; };
+    constexpr int RPS = kBlock / L;
+    const RowRange rr = rows_of_block(a.n, a.geo);
+    const int g = threadIdx.x / L, lane = threadIdx.x % L;
     double e[2] = {0.0, 0.0};
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
-        const cx<T> bv = a.a[i], r = a.b[i];
-        if (a.o1 != a.b) a.o1[i] = r;
-        a.o2[i] = r;
-        e[0] = __builtin_fma((double)bv.x, (double)bv.x, e[0]);
-        e[0] = __builtin_fma((double)bv.y, (double)bv.y, e[0]);
-        e[1] = __builtin_fma((double)r.x, (double)r.x, e[1]);
-        e[1] = __builtin_fma((double)r.y, (double)r.y, e[1]);
+    for (int64_t base = rr.r0; base < rr.r1; base += RPS) {
+        const int64_t row = base + g;
+        const bool ok = row < rr.r1;
+        cx<T> acc = mk<T>(T(0), T(0));
+        if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, pcol);
+        acc.x = group_sum<L>(acc.x);
+        acc.y = group_sum<L>(acc.y);
+        if (ok && lane == 0) {
+            v[row] = acc;
+            const cx<T> w = a.rh[row];
+            double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+        }
     }
-    block_sum<2>(e);
-    if (threadIdx.x == 0) {
-        a.part[lb] = e[0];
-        a.part[a.geo.G + lb] = e[1];
-    }
+    store_partials<2>(a.part + kPartA * kMaxGrid, rr.lb, e);
 }
 
-// ------------------------------------------------------------------ single-block finalisers
-
-__global__ __launch_bounds__(kBlock) void k_fin_init(const double* __restrict__ part, int G, SolverScal* sc) {
-    double s[2];
-    sum_partials<2>(part, G, s);
-    if (threadIdx.x != 0) return;
-    const double bn = __builtin_sqrt(s[0]);
-    sc->bnorm = bn;
-    sc->iter = 1;
-    sc->first = 1;
-    sc->half = 0;
-    sc->done = 0;
-    sc->zero_x = 0;
-    sc->status = ST_NOT_CONVERGED;
-    sc->rho = mk<double>(s[1], 0.0);
-    sc->alpha = sc->omega = sc->beta = mk<double>(1.0, 0.0);
-    if (!__builtin_isfinite(bn) || !__builtin_isfinite(s[1])) {
-        finish(sc, ST_NONFINITE, 0);
+template <typename T>
+__global__ HZ_STREAM_BOUNDS void k_bicg_S(const BicgArgs<T> a) {
+    SolverScal* sc = a.sc;
+    if (sc->done) return;
+    const int it = sc->cur;
+    double h[2];
+    head_sum<2>(a.part + kPartA * kMaxGrid, a.geo.G, h);
+    const double2 sigma = mk<double>(h[0], h[1]);
+    if (!zfinite(sigma) || zzero(sigma)) {
+        if (leader()) finish(sc, zzero(sigma) ? ST_BREAKDOWN : ST_NONFINITE, it);
         return;
     }
+    const double2 alpha = zdiv(sc->rho2[it & 1], sigma);
+    if (leader()) sc->alpha = alpha;
+    const cx<T> nal = mk<T>((T)-alpha.x, (T)-alpha.y);
+    const cx<T>* __restrict__ v = a.v[it & 1];
+    const RowRange rr = rows_of_block(a.n, a.geo);
+    double e[1] = {0.0};
+    for (int64_t i = rr.r0 + threadIdx.x; i < rr.r1; i += kBlock) {
+        const cx<T> s = cfma<T>(nal, v[i], a.r[i]);
+        a.s[i] = s;
+        e[0] = __builtin_fma((double)s.x, (double)s.x, e[0]);
+        e[0] = __builtin_fma((double)s.y, (double)s.y, e[0]);
+    }
+    store_partials<1>(a.part + kPartB * kMaxGrid, rr.lb, e);
+}
+
+template <typename T, int L, int U>
+__global__ HZ_STREAM_BOUNDS void k_bicg_B1(const BicgArgs<T> a) {
+    SolverScal* sc = a.sc;
+    if (sc->done) return;
+    const cx<T>* __restrict__ sv = a.s;
+    auto scol = [sv](int c) { return sv[c]; };
+    constexpr int RPS = kBlock / L;
+    const RowRange rr = rows_of_block(a.n, a.geo);
+    const int g = threadIdx.x / L, lane = threadIdx.x % L;
+    double e[3] = {0.0, 0.0, 0.0};
+    for (int64_t base = rr.r0; base < rr.r1; base += RPS) {
+        const int64_t row = base + g;
+        const bool ok = row < rr.r1;
+        cx<T> acc = mk<T>(T(0), T(0));
+        if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, scol);
+        acc.x = group_sum<L>(acc.x);
+        acc.y = group_sum<L>(acc.y);
+        if (ok && lane == 0) {
+            const cx<T> s = sv[row];
+            a.t[row] = acc;
+            double2 c = cdotacc(acc.x, acc.y, s.x, s.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+            e[2] = __builtin_fma((double)acc.x, (double)acc.x, e[2]);
+            e[2] = __builtin_fma((double)acc.y, (double)acc.y, e[2]);
+        }
+    }
+    store_partials<3>(a.part + (kPartB + 1) * kMaxGrid, rr.lb, e);
+}
+
+// Locality of a CSR matrix: count of entries with |col - row| > W (integer atomics).
+__global__ __launch_bounds__(kBlock) void k_far_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                      int W, unsigned long long* __restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double c = 0.0;  // exact: counts stay far below 2^53
+    if (i < n)
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+            const int64_t d = (int64_t)ci[p] - i;
+            c += (d > W || d < -W) ? 1.0 : 0.0;
+        }
+    c = group_sum<64>(c);
+    if (threadIdx.x % kWave == 0 && c != 0.0) atomicAdd(count, (unsigned long long)c);
+}
+
+// Solve set-up: r = src (b, or the residual b - A x0), rhat = r;
+// partials <rhat, r>, ||r||^2 (region C) and ||b||^2 (region I).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init(int n, Geom geo, const cx<T>* __restrict__ b, const cx<T>* src,
+                                                 cx<T>* r, cx<T>* __restrict__ rh, double* __restrict__ part) {
+    const RowRange rr = rows_of_block(n, geo);
+    double e[3] = {0.0, 0.0, 0.0}, eb[1] = {0.0};
+    for (int64_t i = rr.r0 + threadIdx.x; i < rr.r1; i += kBlock) {
+        const cx<T> bv = b[i], rv = src[i];
+        if (r != src) r[i] = rv;
+        rh[i] = rv;
+        eb[0] = __builtin_fma((double)bv.x, (double)bv.x, eb[0]);
+        eb[0] = __builtin_fma((double)bv.y, (double)bv.y, eb[0]);
+        double2 c = cdotacc(rv.x, rv.y, rv.x, rv.y, mk<double>(e[0], e[1]));
+        e[0] = c.x;
+        e[1] = c.y;
+        e[2] = __builtin_fma((double)rv.x, (double)rv.x, e[2]);
+        e[2] = __builtin_fma((double)rv.y, (double)rv.y, e[2]);
+    }
+    store_partials<3>(part + kPartC * kMaxGrid, rr.lb, e);
+    store_partials<1>(part + kPartI * kMaxGrid, rr.lb, eb);
+}
+
+// ||b||, initial convergence test; iteration 1 comes next.
+__global__ __launch_bounds__(kBlock) void k_fin_init(const double* __restrict__ part, int G, SolverScal* sc) {
+    double hb[1], hr[3];
+    head_sum<1>(part + kPartI * kMaxGrid, G, hb);
+    head_sum<3>(part + kPartC * kMaxGrid, G, hr);
+    if (threadIdx.x != 0) return;
+    const double bn = __builtin_sqrt(hb[0]);
+    sc->bnorm = bn;
+    sc->iter = 1;
+    sc->cur = 0;
+    sc->done = 0;
+    sc->zero_x = 0;
+    sc->iters = 0;
+    sc->pending = 0;
+    sc->status = ST_NOT_CONVERGED;
+    sc->alpha = sc->omega = sc->beta = mk<double>(1.0, 0.0);
+    if (!__builtin_isfinite(bn) || !__builtin_isfinite(hr[2])) return finish(sc, ST_NONFINITE, 0);
     if (bn == 0.0) {
         sc->zero_x = 1;
         sc->relres = 0.0;
-        finish(sc, ST_OK, 0);
-        return;
+        return finish(sc, ST_OK, 0);
     }
-    const double rel = __builtin_sqrt(s[1]) / bn;
+    const double rel = __builtin_sqrt(hr[2]) / bn;
     sc->relres = rel;
     if (rel <= sc->rtol) finish(sc, ST_OK, 0);
     else if (sc->maxiter <= 0) finish(sc, ST_NOT_CONVERGED, 0);
 }
 
-// alpha = rho / <rhat, v>
-__global__ __launch_bounds__(kBlock) void k_fin_alpha(const double* __restrict__ part, int G, SolverScal* sc) {
-    if (sc->done) return;
-    double s[2];
-    sum_partials<2>(part, G, s);
-    if (threadIdx.x != 0) return;
-    const double2 sigma = mk<double>(s[0], s[1]);
-    if (!zfinite(sigma)) return finish(sc, ST_NONFINITE, sc->iter);
-    if (zzero(sigma)) return finish(sc, ST_BREAKDOWN, sc->iter);
-    sc->alpha = zdiv(sc->rho, sigma);
-}
-
-// half-step test on ||s||
-__global__ __launch_bounds__(kBlock) void k_fin_half(const double* __restrict__ part, int G, SolverScal* sc) {
-    if (sc->done) return;
-    double s[1];
-    sum_partials<1>(part, G, s);
-    if (threadIdx.x != 0) return;
-    const double rel = __builtin_sqrt(s[0]) / sc->bnorm;
-    if (!__builtin_isfinite(rel)) return finish(sc, ST_NONFINITE, sc->iter);
-    if (rel <= sc->rtol) {
-        sc->relres = rel;
-        sc->half = 1;
-    }
-}
-
-// omega = <t, s> / <t, t>
-__global__ __launch_bounds__(kBlock) void k_fin_omega(const double* __restrict__ part, int G, SolverScal* sc) {
-    if (sc->done || sc->half) return;
-    double s[3];
-    sum_partials<3>(part, G, s);
-    if (threadIdx.x != 0) return;
-    const double2 ts = mk<double>(s[0], s[1]);
-    const double tt = s[2];
-    if (!zfinite(ts) || !__builtin_isfinite(tt)) return finish(sc, ST_NONFINITE, sc->iter);
-    if (tt == 0.0) return finish(sc, ST_BREAKDOWN, sc->iter);
-    const double2 om = zdiv(ts, mk<double>(tt, 0.0));
-    if (!zfinite(om)) return finish(sc, ST_NONFINITE, sc->iter);
-    sc->omega = om;
-}
-
-// end of an iteration: convergence on ||r||, breakdown tests, next rho and beta
-__global__ __launch_bounds__(kBlock) void k_fin_rho(const double* __restrict__ part, int G, SolverScal* sc) {
-    if (sc->done) return;
-    if (sc->half) {  // x was updated with alpha p by k_xr
-        if (threadIdx.x == 0) finish(sc, ST_OK, sc->iter);
-        return;
-    }
-    double s[3];
-    sum_partials<3>(part, G, s);
-    if (threadIdx.x != 0) return;
-    const int it = sc->iter;
-    const double rel = __builtin_sqrt(s[2]) / sc->bnorm;
-    sc->relres = rel;
-    if (!__builtin_isfinite(rel)) return finish(sc, ST_NONFINITE, it);
-    if (rel <= sc->rtol) return finish(sc, ST_OK, it);
-    if (zzero(sc->omega)) return finish(sc, ST_BREAKDOWN, it);
-    if (it >= sc->maxiter) return finish(sc, ST_NOT_CONVERGED, sc->maxiter);
-    const double2 rho_new = mk<double>(s[0], s[1]);
-    if (!zfinite(rho_new)) return finish(sc, ST_NONFINITE, it + 1);
-    if (zzero(rho_new)) return finish(sc, ST_BREAKDOWN, it + 1);
-    const double2 beta = zmul(zdiv(rho_new, sc->rho), zdiv(sc->alpha, sc->omega));
-    if (!zfinite(beta)) return finish(sc, ST_NONFINITE, it + 1);
-    sc->beta = beta;
-    sc->rho = rho_new;
-    sc->first = 0;
-    sc->iter = it + 1;
-}
-
-// relres_true = sqrt(sum) / ||b||
+// relres_true = sqrt(sum of region I) / ||b||
 __global__ __launch_bounds__(kBlock) void k_fin_true(const double* __restrict__ part, int G, SolverScal* sc) {
-    double s[1];
-    sum_partials<1>(part, G, s);
-    if (threadIdx.x == 0) sc->relres_true = sc->bnorm > 0.0 ? __builtin_sqrt(s[0]) / sc->bnorm : 0.0;
+    double h[1];
+    head_sum<1>(part + kPartI * kMaxGrid, G, h);
+    if (threadIdx.x == 0) sc->relres_true = sc->bnorm > 0.0 ? __builtin_sqrt(h[0]) / sc->bnorm : 0.0;
 }
 
 // ------------------------------------------------------------------ Jacobi folding: A D^{-1}
@@ -535,7 +778,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_diag(int n, const int* __rest
     for (int p = rp[i]; p < rp[i + 1]; ++p)
         if (ci[p] == i) d = vals[p];
     if (d.x == T(0) && d.y == T(0)) {
-        sc->bad_diag = 1;  // benign race: every writer stores 1
+        sc->bad_diag = 1;  // every writer stores 1
         dinv[i] = mk<T>(T(0), T(0));
         return;
     }
@@ -578,16 +821,12 @@ __global__ __launch_bounds__(kBlock) void k_zero_if(int n, const SolverScal* sc,
 template <int MODE>  // 0: conj(x) y  (2 comps), 1: |x|^2 (1 comp)
 __global__ __launch_bounds__(kBlock) void k_dot_part(int n, Geom geo, const double2* __restrict__ x,
                                                      const double2* __restrict__ y, double* __restrict__ part) {
-    struct {
-        int n;
-        Geom geo;
-    } a{n, geo};
-    HZ_ROWS(a);
+    const RowRange rr = rows_of_block(n, geo);
     constexpr int K = MODE == 0 ? 2 : 1;
     double e[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) e[k] = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+    for (int64_t i = rr.r0 + threadIdx.x; i < rr.r1; i += kBlock) {
         const double2 xv = x[i];
         if constexpr (MODE == 0) {
             const double2 yv = y[i];
@@ -599,18 +838,14 @@ __global__ __launch_bounds__(kBlock) void k_dot_part(int n, Geom geo, const doub
             e[0] = __builtin_fma(xv.y, xv.y, e[0]);
         }
     }
-    block_sum<K>(e);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) part[k * geo.G + lb] = e[k];
-    }
+    store_partials<K>(part, rr.lb, e);
 }
 
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_dot_fin(const double* __restrict__ part, int G, void* out) {
     constexpr int K = MODE == 0 ? 2 : 1;
     double s[K];
-    sum_partials<K>(part, G, s);
+    head_sum<K>(part, G, s);
     if (threadIdx.x != 0) return;
     if constexpr (MODE == 0) {
         static_cast<double2*>(out)[0] = mk<double>(s[0], s[1]);
@@ -676,7 +911,7 @@ __global__ __launch_bounds__(kBlock) void k_demote_vec(int n, const double2* __r
 // status/done, and outer_rn = ||r|| of the current outer residual.
 __global__ __launch_bounds__(kBlock) void k_fin_bnorm(const double* __restrict__ part, int G, SolverScal* sc) {
     double s[1];
-    sum_partials<1>(part, G, s);
+    head_sum<1>(part, G, s);
     if (threadIdx.x == 0) sc->bnorm = __builtin_sqrt(s[0]);
 }
 
@@ -684,7 +919,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_bnorm(const double* __restrict__
 __global__ __launch_bounds__(kBlock) void k_fin_outer(const double* __restrict__ part, int G, SolverScal* sc,
                                                       int outer, int max_outer) {
     double s[1];
-    sum_partials<1>(part, G, s);
+    head_sum<1>(part, G, s);
     if (threadIdx.x != 0) return;
     const double rn = __builtin_sqrt(s[0]), bn = sc->bnorm;
     sc->outer_rn = rn;

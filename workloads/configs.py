@@ -107,7 +107,9 @@ def config_cabin(h: float = 0.012, k: float = 40.0, seed: int = 0, permute: bool
     asm = assemble_helmholtz_p1(mesh, k, mesh["robin_sel"])
     A = asm["A"]
     n = A.n
-    perm = rng.permutation(n) if permute else np.arange(n)
+    perm = rng.permutation(n)  # drawn either way, so both numberings share the right-hand side
+    if not permute:
+        perm = np.arange(n)
     interior = np.flatnonzero(~mesh["boundary_node"])
     b, node = point_source_rhs(n, interior, rng)
     if permute:
