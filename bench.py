@@ -145,6 +145,60 @@ def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10):
     return res
 
 
+def batched_cubes(hz, torch, dev, B=32, tol=1e-8):
+    """32 independent 7-point cubes (N ~ U{16..64}, own k): one batched solve vs 32 sequential solves."""
+    import oracle as O
+    import workloads as W
+
+    systems, info = W.config_cube_batch(B=B)
+    row_off = np.zeros(B + 1, dtype=np.int64)
+    rps, cis, vs, bs, nnz_off = [], [], [], [], 0
+    for j, (A, b) in enumerate(systems):
+        row_off[j + 1] = row_off[j] + A.n
+        rps.append(A.row_ptr[:-1].astype(np.int64) + nnz_off)
+        cis.append(A.col_idx.astype(np.int64) + row_off[j])
+        vs.append(A.vals)
+        bs.append(b)
+        nnz_off += A.nnz
+    rp = torch.from_numpy(np.concatenate(rps + [np.array([nnz_off])]).astype(np.int32)).to(dev)
+    ci = torch.from_numpy(np.concatenate(cis).astype(np.int32)).to(dev)
+    vv = torch.from_numpy(np.concatenate(vs)).to(dev)
+    bb = torch.from_numpy(np.concatenate(bs)).to(dev)
+    ro = row_off.astype(np.int32)
+    xb = torch.zeros_like(bb)
+    flags = hz.PRECOND_NONE | hz.X0_ZERO
+    wsb = torch.empty(hz.zbicgstab_batched_workspace_bytes(ro, nnz_off, flags) + 256, dtype=torch.uint8, device=dev)
+    singles = [tuple(torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col_idx, A.vals, b)) for A, b in systems]
+    wss = hz.workspace(max(A.n for A, _ in systems), max(A.nnz for A, _ in systems), flags, dev)
+    xs = [torch.zeros_like(s[3]) for s in singles]
+
+    def run_batched():
+        return hz.zbicgstab_solve_batched(ro, rp, ci, vv, bb, x=xb, rtol=tol, maxiter=50000, flags=flags, ws=wsb)
+
+    def run_sequential():
+        return [hz.zbicgstab_solve(*s, x=x, rtol=tol, maxiter=50000, flags=flags, ws=wss) for s, x in zip(singles, xs)]
+
+    res = {"workload": f"{B} cubes N~U{{16..64}} (sum n={int(row_off[-1])}, nnz={nnz_off}), unpreconditioned, tol {tol:g}"}
+    for label, fn in (("batched", run_batched), ("sequential", run_sequential)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        res[label + "_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        if label == "batched":
+            infos = out[1]
+            res["iterations_min_max"] = [min(i["iterations"] for i in infos), max(i["iterations"] for i in infos)]
+            res["all_ok"] = all(i["status"] == 0 for i in infos)
+            xh = xb.cpu().numpy()
+            res["max_relres_true_oracle_spmv"] = max(
+                float(np.linalg.norm(b - O.zspmv(A, xh[row_off[j]:row_off[j + 1]])) / np.linalg.norm(b))
+                for j, (A, b) in enumerate(systems)
+            )
+    res["speedup"] = round(res["sequential_ms"] / res["batched_ms"], 3)
+    return res
+
+
 def calib_copy():
     import torch
 
@@ -167,7 +221,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--no-time-to-tol", action="store_true")
-    ap.add_argument("--cabin", action="store_true", help="also time FP64 vs mixed to 1e-10 on the cabin")
+    ap.add_argument("--no-cabin", action="store_true", help="skip FP64 vs mixed to 1e-10 on the cabin")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched cube solve")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -292,13 +347,15 @@ def main():
     }
     if not args.no_time_to_tol:
         out["time_to_tol"] = [time_to_tol(hz, torch, dev, "cylinder", rp, ci, vals, b, A)]
-        if args.cabin:
+        if not args.no_cabin:
             Ac, bc, _ = W.config_cabin()
             t = time_to_tol(
                 hz, torch, dev, "cabin", torch.from_numpy(Ac.row_ptr).to(dev), torch.from_numpy(Ac.col_idx).to(dev),
                 torch.from_numpy(Ac.vals).to(dev), torch.from_numpy(bc).to(dev), Ac
             )
             out["time_to_tol"].append(t)
+    if not args.no_batched:
+        out["batched"] = batched_cubes(hz, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, b_np, x_np)
     print(json.dumps(out), flush=True)

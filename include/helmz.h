@@ -59,6 +59,7 @@ enum {
 #define HZ_PRECOND_JACOBI 0x1 /* right preconditioner M = diag(A)          */
 #define HZ_X0_ZERO 0x4        /* ignore x on entry, start from 0 (paper)   */
 #define HZ_VALIDATE 0x8       /* check CSR structure on the device first   */
+#define HZ_SYMMETRIC 0x10     /* caller asserts A = A^T (adjoint shortcut) */
 
 typedef struct {
     int status;              /* HZ_OK / HZ_NOT_CONVERGED / HZ_BREAKDOWN / HZ_NONFINITE */
@@ -120,6 +121,29 @@ int zbicgstab_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const i
                     const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol, int maxiter, int flags, void *ws,
                     size_t ws_bytes, hz_solve_info *info);
 
+/*
+ * Workspace (bytes) for zbicgstab_solve_batched.  row_off is a HOST array of
+ * nsys+1 row offsets (row_off[0] = 0, non-decreasing).
+ */
+size_t zbicgstab_batched_workspace_bytes(int nsys, const int *row_off, int nnz, int flags);
+
+/*
+ * Solve nsys independent systems A_j x_j = b_j in one launch sequence: the
+ * systems are the diagonal blocks of one block-diagonal CSR matrix (rows
+ * row_off[j] .. row_off[j+1]-1 of row_ptr/col_idx/vals, GLOBAL column
+ * indices inside the block), b and x are the concatenated vectors.  Every
+ * system runs its own preconditioned BiCGStab (Section 7) with its own
+ * scalars, convergence test and exit, exactly as zbicgstab_solve would;
+ * systems that finish early stop consuming bandwidth.  infos is a HOST array
+ * of nsys results.  Returns the largest status over the systems, or a
+ * negative error.  Flags, stream and workspace as for zbicgstab_solve.
+ * Systems on one sparsity pattern (a frequency sweep) are passed the same
+ * way, with the pattern repeated per block.
+ */
+int zbicgstab_solve_batched(hz_handle *handle, hz_stream stream, int nsys, const int *row_off, int nnz,
+                            const int *row_ptr, const int *col_idx, const hz_c128 *vals, const hz_c128 *b, hz_c128 *x,
+                            double rtol, int maxiter, int flags, void *ws, size_t ws_bytes, hz_solve_info *infos);
+
 /* Device workspace (bytes) that zbicgstab_solve_mixed needs. */
 size_t zbicgstab_mixed_workspace_bytes(int n, int nnz, int flags);
 
@@ -141,6 +165,44 @@ int zbicgstab_solve_mixed(hz_handle *handle, hz_stream stream, int n, int nnz, c
                           const int *col_idx, const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol,
                           double inner_rtol, int maxiter, int max_outer, int flags, void *ws, size_t ws_bytes,
                           hz_solve_info *info);
+
+/*
+ * y = A x for a rectangular m x ncols complex128 CSR matrix (same storage
+ * as csr_zspmv; row_ptr has m+1 entries, 0 <= col_idx < ncols).  Used to
+ * chain entry gradients to the parameters the entries depend on.
+ */
+int csr_zspmv_rect(hz_handle *handle, hz_stream stream, int m, int ncols, int nnz, const int *row_ptr,
+                   const int *col_idx, const hz_c128 *vals, const hz_c128 *x, hz_c128 *y);
+
+/*
+ * grad_vals[p] = -lambda_i * conj(x_j) for every stored entry p = (i, j):
+ * the gradient of a real loss L with respect to the entries of A, where x
+ * solves A x = b and lambda solves A^H lambda = dL/dx (real-pair convention
+ * g = dL/dRe + i dL/dIm, as torch uses).  Differentiation of the paper's
+ * solve (Section 7) is an extension; the formula follows from
+ * dx = -A^{-1} dA x.
+ */
+int csr_zgrad_vals(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+                   const hz_c128 *lambda, const hz_c128 *x, hz_c128 *grad_vals);
+
+/* Device workspace (bytes) that zbicgstab_adjoint needs for these flags. */
+size_t zbicgstab_adjoint_workspace_bytes(int n, int nnz, int flags);
+
+/*
+ * Backward of x = A^{-1} b (Section 7's solve, differentiated): given
+ * grad_x = dL/dx (real-pair convention), solve A^H lambda = grad_x by the
+ * same preconditioned BiCGStab (rtol, maxiter, HZ_PRECOND_JACOBI as for
+ * zbicgstab_solve; the initial guess is zero), write grad_b = lambda and,
+ * if grad_vals is not NULL, grad_vals[p] = -lambda_i conj(x_j) on A's
+ * pattern (x = the forward solution).  With HZ_SYMMETRIC the caller
+ * asserts A = A^T and the solve runs on conj(grad_x) with A itself;
+ * otherwise A^H is formed in the workspace (deterministically: rows sorted
+ * by column).  Synchronises the stream; returns the adjoint solve's status.
+ */
+int zbicgstab_adjoint(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+                      const hz_c128 *vals, const hz_c128 *x, const hz_c128 *grad_x, hz_c128 *grad_b,
+                      hz_c128 *grad_vals, double rtol, int maxiter, int flags, void *ws, size_t ws_bytes,
+                      hz_solve_info *info);
 
 #ifdef __cplusplus
 }

@@ -11,10 +11,13 @@ from .binding import (  # noqa: F401
     OK,
     PRECOND_JACOBI,
     PRECOND_NONE,
+    SYMMETRIC,
     VALIDATE,
     X0_ZERO,
     csr_cspmv,
+    csr_zgrad_vals,
     csr_zspmv,
+    csr_zspmv_rect,
     dznrm2,
     handle,
     workspace,
@@ -23,7 +26,12 @@ from .binding import (  # noqa: F401
     zbicgstab_mixed_workspace_bytes,
     zbicgstab_solve,
     zbicgstab_solve_mixed,
+    zbicgstab_adjoint,
+    zbicgstab_batched_workspace_bytes,
+    zbicgstab_solve_batched,
+    zbicgstab_adjoint_workspace_bytes,
     zbicgstab_workspace_bytes,
     zdotc,
 )
+from .autograd import EntryMap, HelmholtzSolve, SolveOptions, entry_map, helmholtz_solve  # noqa: F401
 from ._lib import HelmzError, lib_path, load  # noqa: F401

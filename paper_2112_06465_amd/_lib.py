@@ -55,6 +55,12 @@ SIGNATURES = {
     "zbicgstab_workspace_bytes": (SZ, [I, I, I]),
     "zbicgstab_solve": (I, [P, P, I, I, P, P, P, P, P, D, I, I, P, SZ, C.POINTER(HzInfo)]),
     "zbicgstab_mixed_workspace_bytes": (SZ, [I, I, I]),
+    "zbicgstab_batched_workspace_bytes": (SZ, [I, P, I, I]),
+    "zbicgstab_solve_batched": (I, [P, P, I, P, I, P, P, P, P, P, D, I, I, P, SZ, P]),
+    "csr_zspmv_rect": (I, [P, P, I, I, I, P, P, P, P, P]),
+    "csr_zgrad_vals": (I, [P, P, I, I, P, P, P, P, P]),
+    "zbicgstab_adjoint_workspace_bytes": (SZ, [I, I, I]),
+    "zbicgstab_adjoint": (I, [P, P, I, I, P, P, P, P, P, P, P, D, I, I, P, SZ, C.POINTER(HzInfo)]),
     "zbicgstab_solve_mixed": (I, [P, P, I, I, P, P, P, P, P, D, D, I, I, I, P, SZ, C.POINTER(HzInfo)]),
 }
 

@@ -15,7 +15,7 @@ import torch
 from ._lib import HelmzError, HzC128, HzInfo, load
 
 OK, NOT_CONVERGED, BREAKDOWN, NONFINITE = 0, 1, 2, 3
-PRECOND_NONE, PRECOND_JACOBI, X0_ZERO, VALIDATE = 0x0, 0x1, 0x4, 0x8
+PRECOND_NONE, PRECOND_JACOBI, X0_ZERO, VALIDATE, SYMMETRIC = 0x0, 0x1, 0x4, 0x8, 0x10
 
 _handles: dict[int, int] = {}
 _hlock = threading.Lock()
@@ -235,3 +235,113 @@ def zbicgstab_solve_mixed(
                                       int(maxiter), int(max_outer), int(flags), wp, wbytes, C.byref(info))
     _check("zbicgstab_solve_mixed", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
     return x, info.as_dict()
+
+
+def csr_zspmv_rect(row_ptr, col_idx, vals, x, y=None):
+    """y = A x for a rectangular complex128 CSR matrix with row_ptr.numel()-1 rows (csr_zspmv_rect)."""
+    dev = vals.device
+    _need(row_ptr, "row_ptr", torch.int32, dev)
+    _need(col_idx, "col_idx", torch.int32, dev)
+    _need(vals, "vals", torch.complex128, dev)
+    _need(x, "x", torch.complex128, dev)
+    m, nnz = row_ptr.numel() - 1, col_idx.numel()
+    if m < 0 or vals.numel() != nnz:
+        raise ValueError("inconsistent CSR sizes")
+    if y is None:
+        y = torch.empty(m, dtype=torch.complex128, device=dev)
+    _need(y, "y", torch.complex128, dev)
+    rc = load().csr_zspmv_rect(handle(dev), _stream(dev), m, x.numel(), nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                               vals.data_ptr(), x.data_ptr(), y.data_ptr())
+    _check("csr_zspmv_rect", rc)
+    return y
+
+
+def csr_zgrad_vals(row_ptr, col_idx, lam, x, out=None):
+    """out[p] = -lam_i conj(x_j) on the pattern (csr_zgrad_vals)."""
+    dev = lam.device
+    _need(row_ptr, "row_ptr", torch.int32, dev)
+    _need(col_idx, "col_idx", torch.int32, dev)
+    _need(lam, "lambda", torch.complex128, dev)
+    _need(x, "x", torch.complex128, dev)
+    n, nnz = row_ptr.numel() - 1, col_idx.numel()
+    if out is None:
+        out = torch.empty(nnz, dtype=torch.complex128, device=dev)
+    _need(out, "grad_vals", torch.complex128, dev)
+    rc = load().csr_zgrad_vals(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                               lam.data_ptr(), x.data_ptr(), out.data_ptr())
+    _check("csr_zgrad_vals", rc)
+    return out
+
+
+def zbicgstab_adjoint_workspace_bytes(n: int, nnz: int, flags: int = 0) -> int:
+    return int(load().zbicgstab_adjoint_workspace_bytes(int(n), int(nnz), int(flags)))
+
+
+def zbicgstab_adjoint(row_ptr, col_idx, vals, x, grad_x, rtol=1e-10, maxiter=20000, flags=PRECOND_NONE,
+                      want_grad_vals=True, ws=None):
+    """Backward of x = A^{-1} b (zbicgstab_adjoint).  Returns (grad_b, grad_vals or None, info)."""
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    _need(grad_x, "grad_x", torch.complex128, dev)
+    if grad_x.numel() != n:
+        raise ValueError("grad_x has the wrong length")
+    grad_b = torch.empty(n, dtype=torch.complex128, device=dev)
+    grad_vals = None
+    if want_grad_vals:
+        _need(x, "x", torch.complex128, dev)
+        grad_vals = torch.empty(nnz, dtype=torch.complex128, device=dev)
+    need = zbicgstab_adjoint_workspace_bytes(n, nnz, flags)
+    if ws is None:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    _need(ws, "ws", torch.uint8, dev)
+    wp, wbytes = _aligned_ptr(ws, need)
+    info = HzInfo()
+    rc = load().zbicgstab_adjoint(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                                  vals.data_ptr(), x.data_ptr() if want_grad_vals else None, grad_x.data_ptr(),
+                                  grad_b.data_ptr(), grad_vals.data_ptr() if want_grad_vals else None, float(rtol),
+                                  int(maxiter), int(flags), wp, wbytes, C.byref(info))
+    _check("zbicgstab_adjoint", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
+    return grad_b, grad_vals, info.as_dict()
+
+
+def _row_off_array(row_off):
+    import numpy as np
+
+    ro = np.ascontiguousarray(np.asarray(row_off, dtype=np.int32))
+    if ro.ndim != 1 or ro.size < 2:
+        raise ValueError("row_off must hold nsys + 1 offsets")
+    return ro
+
+
+def zbicgstab_batched_workspace_bytes(row_off, nnz: int, flags: int = 0) -> int:
+    ro = _row_off_array(row_off)
+    return int(load().zbicgstab_batched_workspace_bytes(ro.size - 1, ro.ctypes.data, int(nnz), int(flags)))
+
+
+def zbicgstab_solve_batched(row_off, row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxiter=20000,
+                            flags=PRECOND_NONE | X0_ZERO, ws=None):
+    """Solve the diagonal blocks of a block-diagonal system independently (zbicgstab_solve_batched).
+
+    ``row_off`` (host, nsys + 1 offsets) delimits the systems.  Returns
+    (x, [info per system]).
+    """
+    ro = _row_off_array(row_off)
+    nsys = ro.size - 1
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    if int(ro[-1]) != n:
+        raise ValueError("row_off[-1] must equal the number of rows")
+    _need(b, "b", torch.complex128, dev)
+    if x is None:
+        x = torch.zeros(n, dtype=torch.complex128, device=dev)
+        flags |= X0_ZERO
+    _need(x, "x", torch.complex128, dev)
+    need = zbicgstab_batched_workspace_bytes(ro, nnz, flags)
+    if ws is None:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    _need(ws, "ws", torch.uint8, dev)
+    wp, wbytes = _aligned_ptr(ws, need)
+    infos = (HzInfo * nsys)()
+    rc = load().zbicgstab_solve_batched(handle(dev), _stream(dev), nsys, ro.ctypes.data, nnz, row_ptr.data_ptr(),
+                                        col_idx.data_ptr(), vals.data_ptr(), b.data_ptr(), x.data_ptr(), float(rtol),
+                                        int(maxiter), int(flags), wp, wbytes, C.cast(infos, C.c_void_p))
+    _check("zbicgstab_solve_batched", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
+    return x, [i.as_dict() for i in infos]

@@ -3,13 +3,16 @@
 // hz_kernels.hpp; the host only sequences launches and polls a done flag.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "helmz.h"
 #include "hz_kernels.hpp"
+#include "hz_adjoint.hpp"
 
 using hz::cx;
 using hz::Geom;
@@ -149,19 +152,73 @@ int check_csr_args(int n, int nnz, const int* rp, const int* ci, const void* val
     return HZ_OK;
 }
 
-// ------------------------------------------------------------------ solver workspace
+// ------------------------------------------------------------------ solver work map and workspace
 
+using hz::BlockMap;
+using hz::SysMap;
+
+// Work map of a solver launch over nsys systems with host row offsets
+// row_off[0..nsys].  One system: the G <= kMaxGrid blocks of geom_for, each
+// a contiguous row chunk.  Several systems: every system gets
+// ceil(n_j / R) blocks (R rows per block, chosen so the whole launch has
+// about kMaxGrid blocks), blocks of one system are consecutive, and the
+// total is padded to a multiple of 8 with empty blocks.
+struct WorkMap {
+    int nsys = 0, G = 0, stride = 0;
+    std::vector<BlockMap> blocks;
+    std::vector<SysMap> systems;
+};
+
+WorkMap build_map(int nsys, const int* row_off, int L) {
+    WorkMap m;
+    m.nsys = nsys;
+    const int64_t N = int64_t(row_off[nsys]) - row_off[0];
+    if (nsys == 1) {
+        const Geom geo = geom_for(int(N), kBlock / L);
+        for (int b = 0; b < geo.G; ++b) {
+            const int64_t r0 = std::min<int64_t>(N, int64_t(b) * geo.chunk);
+            const int64_t r1 = std::min<int64_t>(N, r0 + geo.chunk);
+            m.blocks.push_back(BlockMap{0, int(row_off[0] + r0), int(row_off[0] + r1), b});
+        }
+        m.systems.push_back(SysMap{0, geo.G, row_off[0], row_off[1]});
+    } else {
+        const int64_t R = std::max<int64_t>(kBlock / L, (N + kMaxGrid - 1) / kMaxGrid);
+        for (int j = 0; j < nsys; ++j) {
+            const int64_t nj = int64_t(row_off[j + 1]) - row_off[j];
+            const int64_t gj = std::max<int64_t>(1, (nj + R - 1) / R);
+            const int64_t chunk = std::max<int64_t>(1, (nj + gj - 1) / gj);
+            m.systems.push_back(SysMap{int(m.blocks.size()), int(gj), row_off[j], row_off[j + 1]});
+            for (int64_t b = 0; b < gj; ++b) {
+                const int64_t r0 = std::min<int64_t>(nj, b * chunk), r1 = std::min<int64_t>(nj, r0 + chunk);
+                m.blocks.push_back(BlockMap{j, int(row_off[j] + r0), int(row_off[j] + r1), int(b)});
+            }
+        }
+        while (m.blocks.size() >= size_t(hz::kXcd) && m.blocks.size() % hz::kXcd != 0)
+            m.blocks.push_back(BlockMap{-1, 0, 0, 0});
+    }
+    m.G = int(m.blocks.size());
+    m.stride = std::max(m.G, kMaxGrid);
+    return m;
+}
+
+// Solver workspace: per-system scalars, partials, the work map, a done
+// counter, eight vectors (r, rhat, p0, p1, v0, v1, s, t) and, under Jacobi,
+// D^{-1} and the column-scaled values.
 struct SolveWs {
     SolverScal* sc;
     double* part;
-    void* vec[8];  // r, rhat, p0, p1, v0, v1, s, t
+    BlockMap* bmap;
+    SysMap* smap;
+    int* ndone;
+    void* vec[8];
     void* dinv;
     void* ahat;
 };
 
 template <typename T>
-size_t ws_layout(int n, int64_t nnz, bool jacobi, char* base, SolveWs* out) {
+size_t ws_layout(int n, int64_t nnz, bool jacobi, int nsys, int G, char* base, SolveWs* out) {
     const size_t vb = align_up(sizeof(cx<T>) * size_t(n > 0 ? n : 1));
+    const int stride = std::max(G, kMaxGrid);
     size_t off = 0;
     auto take = [&](size_t bytes) -> void* {
         void* p = base ? base + off : nullptr;
@@ -169,8 +226,11 @@ size_t ws_layout(int n, int64_t nnz, bool jacobi, char* base, SolveWs* out) {
         return p;
     };
     SolveWs w{};
-    w.sc = static_cast<SolverScal*>(take(sizeof(SolverScal)));
-    w.part = static_cast<double*>(take(sizeof(double) * kParts * kMaxGrid));
+    w.sc = static_cast<SolverScal*>(take(sizeof(SolverScal) * size_t(nsys)));
+    w.part = static_cast<double*>(take(sizeof(double) * size_t(hz::kParts) * size_t(stride)));
+    w.bmap = static_cast<BlockMap*>(take(sizeof(BlockMap) * size_t(G)));
+    w.smap = static_cast<SysMap*>(take(sizeof(SysMap) * size_t(nsys)));
+    w.ndone = static_cast<int*>(take(sizeof(int)));
     for (auto& v : w.vec) v = take(vb);
     w.dinv = jacobi ? take(vb) : nullptr;
     w.ahat = jacobi ? take(sizeof(cx<T>) * size_t(nnz > 0 ? nnz : 1)) : nullptr;
@@ -178,15 +238,24 @@ size_t ws_layout(int n, int64_t nnz, bool jacobi, char* base, SolveWs* out) {
     return off;
 }
 
-// Arguments shared by the three kernels of an iteration.
+// Worst case of the one-system map: G <= kMaxGrid.
+template <typename T> size_t ws_bytes_single(int n, int64_t nnz, bool jacobi) {
+    return ws_layout<T>(n, nnz, jacobi, 1, kMaxGrid, nullptr, nullptr);
+}
+
 template <typename T>
-hz::BicgArgs<T> bicg_args(int n, Geom geo, const int* rp, const int* ci, const cx<T>* av, cx<T>* x, const SolveWs& w) {
+hz::BicgArgs<T> bicg_args(const WorkMap& m, const int* rp, const int* ci, const cx<T>* av, const cx<T>* b, cx<T>* x,
+                          const SolveWs& w) {
     hz::BicgArgs<T> a;
-    a.n = n;
-    a.geo = geo;
+    a.G = m.G;
+    a.stride = m.stride;
+    a.bmap = w.bmap;
+    a.smap = w.smap;
+    a.ndone = w.ndone;
     a.row_ptr = rp;
     a.col_idx = ci;
     a.vals = av;
+    a.b = b;
     a.r = static_cast<cx<T>*>(w.vec[0]);
     a.rh = static_cast<const cx<T>*>(w.vec[1]);
     a.p[0] = static_cast<cx<T>*>(w.vec[2]);
@@ -201,22 +270,28 @@ hz::BicgArgs<T> bicg_args(int n, Geom geo, const int* rp, const int* ci, const c
     return a;
 }
 
-// The iteration loop of BiCGStab on the (possibly column-scaled) matrix
-// `av`.  On entry r, rhat and the scalars are initialised (k_fin_init ran).
-// Launches at most maxiter iterations of three kernels, then one more
-// A-kernel that concludes the last iteration; polls sc->done between
-// chunks of 8, 16, ..., 64 iterations.  x holds the iterate (the scaled one,
-// y, under Jacobi).
+// Upload the map (host vectors stay alive until the caller's next sync).
+int upload_map(hipStream_t s, const WorkMap& m, const SolveWs& w) {
+    HZ_HIP(hipMemcpyAsync(w.bmap, m.blocks.data(), sizeof(BlockMap) * m.blocks.size(), hipMemcpyHostToDevice, s));
+    HZ_HIP(hipMemcpyAsync(w.smap, m.systems.data(), sizeof(SysMap) * m.systems.size(), hipMemcpyHostToDevice, s));
+    HZ_HIP(hipMemsetAsync(w.ndone, 0, sizeof(int), s));
+    return HZ_OK;
+}
+
+// The iteration loop of BiCGStab on the (possibly column-scaled) matrix in
+// `a` for every system of the map.  On entry r, rhat and the scalars are
+// initialised (k_fin_init ran).  Launches at most maxiter iterations, then
+// one more first kernel that concludes the last iteration; polls the
+// done-counter between chunks of 8, 16, ..., 64 iterations.
 template <typename T>
-int iterate(hz_handle* h, hipStream_t s, int n, int L, Geom geo, const int* rp, const int* ci, const cx<T>* av,
-            cx<T>* x, const SolveWs& w, int maxiter, bool fused) {
-    const hz::BicgArgs<T> a = bicg_args<T>(n, geo, rp, ci, av, x, w);
-    const dim3 G(geo.G), B(kBlock);
+int iterate(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>& a, int L, int maxiter, bool fused) {
+    const dim3 G(m.G), B(kBlock);
     int launched = 0, poll = 8;
+    int err = 0;
     with_lanes(L, [&]<int LL, int UU>() {
         while (launched < maxiter) {
-            const int m = (maxiter - launched) < poll ? (maxiter - launched) : poll;
-            for (int k = 0; k < m; ++k) {
+            const int k_n = (maxiter - launched) < poll ? (maxiter - launched) : poll;
+            for (int k = 0; k < k_n; ++k) {
                 if (fused) {
                     hipLaunchKernelGGL((hz::k_bicg_A<T, LL, UU>), G, B, 0, s, a);
                     hipLaunchKernelGGL((hz::k_bicg_B<T, LL, UU>), G, B, 0, s, a);
@@ -228,23 +303,109 @@ int iterate(hz_handle* h, hipStream_t s, int n, int L, Geom geo, const int* rp, 
                 }
                 hipLaunchKernelGGL((hz::k_bicg_C<T>), G, B, 0, s, a);
             }
-            launched += m;
+            launched += k_n;
             if (launched == maxiter) hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, s, a);
-            if (hipGetLastError() != hipSuccess) return;
-            if (hipMemcpyAsync(h->hflag, &w.sc->done, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return;
-            if (hipStreamSynchronize(s) != hipSuccess) return;
-            if (*h->hflag) break;
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(h->hflag, a.ndone, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                err = 1;
+                return;
+            }
+            if (*h->hflag >= m.nsys) break;
             if (poll < 64) poll *= 2;
         }
     });
+    if (err) return HZ_ERR_HIP;
     HZ_HIP(hipGetLastError());
     return HZ_OK;
 }
 
+template <typename T>
+void launch_sys_resid(int L, const WorkMap& m, const hz::BicgArgs<T>& a, const cx<T>* vals, const cx<T>* xin, cx<T>* y,
+                      hipStream_t s) {
+    with_lanes(L, [&]<int LL, int UU>() {
+        hipLaunchKernelGGL((hz::k_sys_resid<T, LL, UU>), dim3(m.G), dim3(kBlock), 0, s, a, vals, xin, y);
+    });
+}
+
+// FP64 solve of nsys systems after argument checks.  The matrix may be
+// block diagonal (row_off = the systems' row offsets, host array); x is
+// in/out; infos[j] receives system j's result.  Returns the largest status.
+int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nnz, const int* rp, const int* ci,
+               const double2* A, const double2* bd, double2* xd, double rtol, int maxiter, int flags, char* ws,
+               hz_solve_info* infos) {
+    const int n = row_off[nsys] - row_off[0];
+    const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
+    const int L = pick_lanes(n, nnz);
+    const WorkMap m = build_map(nsys, row_off, L);
+    SolveWs w;
+    ws_layout<double>(n, nnz, jacobi, nsys, m.G, ws, &w);
+    int rc = upload_map(s, m, w);
+    if (rc) return rc;
+    double2* r = static_cast<double2*>(w.vec[0]);
+    double2* t = static_cast<double2*>(w.vec[7]);
+    double2* dinv = static_cast<double2*>(w.dinv);
+    hipLaunchKernelGGL(hz::k_sc_init, dim3((nsys + 255) / 256), dim3(256), 0, s, w.sc, nsys, rtol, maxiter);
+
+    const double2* Aop = A;
+    if (jacobi) {
+        hipLaunchKernelGGL(hz::k_jacobi_diag<double>, grid1(n), dim3(kBlock), 0, s, n, rp, ci, A, dinv, w.sc);
+        double2* ah = static_cast<double2*>(w.ahat);
+        if (nnz > 0)
+            hipLaunchKernelGGL(hz::k_colscale<double>, grid1(nnz), dim3(kBlock), 0, s, int64_t(nnz), ci, A,
+                               static_cast<const double2*>(dinv), ah);
+        Aop = ah;
+    }
+    const hz::BicgArgs<double> a = bicg_args<double>(m, rp, ci, Aop, bd, xd, w);
+    // initial iterate (y = D x0 under Jacobi) and residual
+    const double2* rsrc = bd;
+    if (flags & HZ_X0_ZERO) {
+        HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
+    } else {
+        if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, dinv, xd, 1);
+        launch_sys_resid<double>(L, m, a, Aop, xd, r, s);
+        rsrc = r;
+    }
+    hipLaunchKernelGGL(hz::k_init<double>, dim3(m.G), dim3(kBlock), 0, s, a, rsrc);
+    hipLaunchKernelGGL(hz::k_fin_init<double>, dim3(nsys), dim3(kBlock), 0, s, a);
+    HZ_HIP(hipGetLastError());
+    rc = enqueue_far_count(h, s, n, rp, ci);
+    if (rc) return rc;
+    SolverScal* hs = h->hsc;
+    HZ_HIP(hipMemcpyAsync(hs, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipMemcpyAsync(h->hflag, w.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    if (hs->bad_diag) return HZ_ERR_INVALID;
+
+    if (*h->hflag < nsys) {
+        rc = iterate<double>(h, s, m, a, L, maxiter, choose_fused(h, nnz));
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(hz::k_zero_if<double>, dim3(m.G), dim3(kBlock), 0, s, a);
+    if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, dinv, xd, 0);
+    // true residual with the caller's matrix
+    const hz::BicgArgs<double> a0 = bicg_args<double>(m, rp, ci, A, bd, xd, w);
+    launch_sys_resid<double>(L, m, a0, A, xd, t, s);
+    hipLaunchKernelGGL(hz::k_fin_true<double>, dim3(nsys), dim3(kBlock), 0, s, a0);
+    HZ_HIP(hipGetLastError());
+    std::vector<SolverScal> out(nsys);
+    HZ_HIP(hipMemcpyAsync(out.data(), w.sc, sizeof(SolverScal) * size_t(nsys), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    int worst = HZ_OK;
+    for (int j = 0; j < nsys; ++j) {
+        infos[j].status = out[j].status;
+        infos[j].iterations = out[j].iters;
+        infos[j].outer_steps = 0;
+        infos[j].relres_recursive = out[j].relres;
+        infos[j].relres_true = out[j].relres_true;
+        worst = std::max(worst, out[j].status);
+    }
+    return worst;
+}
 
 // Mixed refinement workspace: outer scalars, the complex64 solver's own
-// workspace (vectors, partials, scalars, D^{-1}, demoted matrix), the FP64
-// residual and the complex64 right-hand side and correction.
+// workspace (vectors, partials, scalars, map, D^{-1}, demoted matrix), the
+// FP64 residual and the complex64 right-hand side and correction.
 struct MixedWs {
     SolverScal* outer;
     SolveWs in;
@@ -263,17 +424,59 @@ size_t mixed_layout(int n, int64_t nnz, bool jacobi, char* base, MixedWs* out) {
     const size_t nn = size_t(n > 0 ? n : 1);
     MixedWs m{};
     m.outer = static_cast<SolverScal*>(take(sizeof(SolverScal)));
-    m.in.sc = static_cast<SolverScal*>(take(sizeof(SolverScal)));
-    m.in.part = static_cast<double*>(take(sizeof(double) * kParts * kMaxGrid));
-    for (auto& v : m.in.vec) v = take(sizeof(float2) * nn);
-    m.in.dinv = jacobi ? take(sizeof(float2) * nn) : nullptr;
-    m.in.ahat = take(sizeof(float2) * size_t(nnz > 0 ? nnz : 1));
+    // the inner workspace always holds the demoted matrix (ahat) and, under Jacobi, D^{-1}
+    char* inner = static_cast<char*>(take(ws_layout<float>(n, nnz, true, 1, kMaxGrid, nullptr, nullptr)));
+    ws_layout<float>(n, nnz, true, 1, kMaxGrid, inner, &m.in);
+    if (!jacobi) m.in.dinv = nullptr;
     m.r64 = static_cast<double2*>(take(sizeof(double2) * nn));
     m.b32 = static_cast<float2*>(take(sizeof(float2) * nn));
     m.d32 = static_cast<float2*>(take(sizeof(float2) * nn));
     if (out) *out = m;
     return off;
 }
+
+// ------------------------------------------------------------------ adjoint
+
+// Adjoint workspace: the forward solver's workspace, conj(g), and (unless the
+// caller asserts A = A^T) the conjugate transpose A^H in CSR.
+struct AdjWs {
+    char* solve;
+    double2* gconj;
+    int* t_rp;
+    int* t_ci;
+    double2* t_vals;
+    int* fill;
+};
+
+size_t adjoint_layout(int n, int64_t nnz, int flags, char* base, AdjWs* out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const size_t nn = size_t(n > 0 ? n : 1), nz = size_t(nnz > 0 ? nnz : 1);
+    AdjWs a{};
+    a.solve = static_cast<char*>(take(ws_bytes_single<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0)));
+    a.gconj = static_cast<double2*>(take(sizeof(double2) * nn));
+    if (!(flags & HZ_SYMMETRIC)) {
+        a.t_rp = static_cast<int*>(take(sizeof(int) * (nn + 1)));
+        a.t_ci = static_cast<int*>(take(sizeof(int) * nz));
+        a.t_vals = static_cast<double2*>(take(sizeof(double2) * nz));
+        a.fill = static_cast<int*>(take(sizeof(int) * nn));
+    }
+    if (out) *out = a;
+    return off;
+}
+
+void launch_grad_vals(int n, const int* rp, const int* ci, const double2* lam, const double2* x, double2* gv, int L,
+                      hipStream_t s) {
+    const Geom geo = geom_for(n, kBlock / L);
+    with_lanes(L, [&]<int LL, int UU>() {
+        hipLaunchKernelGGL((hz::k_grad_vals<LL>), dim3(geo.G), dim3(kBlock), 0, s, n, geo, rp, ci, lam, x, gv);
+    });
+}
+
 
 }  // namespace
 
@@ -412,7 +615,7 @@ int zaxpy(hz_handle* h, hz_stream stream, int n, hz_c128 alpha, const hz_c128* x
 
 size_t zbicgstab_workspace_bytes(int n, int nnz, int flags) {
     if (n < 0 || nnz < 0) return 0;
-    return ws_layout<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr);
+    return ws_bytes_single<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0);
 }
 
 int zbicgstab_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c128* vals,
@@ -427,76 +630,61 @@ int zbicgstab_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* r
     if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
         return HZ_ERR_INVALID;
     if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
-    const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
-    SolveWs w;
-    const size_t need = ws_layout<double>(n, nnz, jacobi, static_cast<char*>(ws), &w);
+    const size_t need = ws_bytes_single<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0);
     if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
-
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (flags & HZ_VALIDATE) {
         rc = validate_csr(h, s, n, nnz, rp, ci);
         if (rc) return rc;
     }
-    const int L = pick_lanes(n, nnz);
-    const Geom geo = geom_for(n, kBlock / L);
-    const double2* A = reinterpret_cast<const double2*>(vals);
-    const double2* bd = reinterpret_cast<const double2*>(b);
-    double2* xd = reinterpret_cast<double2*>(x);
-    double2* r = static_cast<double2*>(w.vec[0]);
-    double2* rh = static_cast<double2*>(w.vec[1]);
-    double2* t = static_cast<double2*>(w.vec[7]);
-    double2* dinv = static_cast<double2*>(w.dinv);
-
-    SolverScal* hs = h->hsc;
-    hipLaunchKernelGGL(hz::k_sc_init, dim3(1), dim3(64), 0, s, w.sc, rtol, maxiter);
-
-    const double2* Aop = A;
-    if (jacobi) {
-        hipLaunchKernelGGL(hz::k_jacobi_diag<double>, grid1(n), dim3(kBlock), 0, s, n, rp, ci, A, dinv, w.sc);
-        double2* ah = static_cast<double2*>(w.ahat);
-        if (nnz > 0)
-            hipLaunchKernelGGL(hz::k_colscale<double>, grid1(nnz), dim3(kBlock), 0, s, int64_t(nnz), ci, A,
-                               static_cast<const double2*>(dinv), ah);
-        Aop = ah;
-    }
-    // initial iterate (y = D x0 under Jacobi) and residual
-    const double2* rsrc = bd;
-    if (flags & HZ_X0_ZERO) {
-        HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
-    } else {
-        if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, dinv, xd, 1);
-        launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, Aop, xd, r, bd, w.part + hz::kPartI * kMaxGrid), s);
-        rsrc = r;
-    }
-    hipLaunchKernelGGL(hz::k_init<double>, dim3(geo.G), dim3(kBlock), 0, s, n, geo, bd, rsrc, r, rh, w.part);
-    hipLaunchKernelGGL(hz::k_fin_init, dim3(1), dim3(kBlock), 0, s, w.part, geo.G, w.sc);
-    HZ_HIP(hipGetLastError());
-    rc = enqueue_far_count(h, s, n, rp, ci);
-    if (rc) return rc;
-    HZ_HIP(hipMemcpyAsync(hs, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
-    HZ_HIP(hipStreamSynchronize(s));
-    if (hs->bad_diag) return HZ_ERR_INVALID;
-
-    if (!hs->done) {
-        rc = iterate<double>(h, s, n, L, geo, rp, ci, Aop, xd, w, maxiter, choose_fused(h, nnz));
-        if (rc) return rc;
-    }
-    hipLaunchKernelGGL(hz::k_zero_if<double>, grid1(n), dim3(kBlock), 0, s, n, w.sc, xd);
-    if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, dinv, xd, 0);
-    // true residual with the caller's matrix
-    launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, t, bd, w.part + hz::kPartI * kMaxGrid), s);
-    hipLaunchKernelGGL(hz::k_fin_true, dim3(1), dim3(kBlock), 0, s, w.part, geo.G, w.sc);
-    HZ_HIP(hipGetLastError());
-    HZ_HIP(hipMemcpyAsync(hs, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
-    HZ_HIP(hipStreamSynchronize(s));
-    info->status = hs->status;
-    info->iterations = hs->iters;
-    info->outer_steps = 0;
-    info->relres_recursive = hs->relres;
-    info->relres_true = hs->relres_true;
-    return hs->status;
+    const int row_off[2] = {0, n};
+    return solve_fp64(h, s, 1, row_off, nnz, rp, ci, reinterpret_cast<const double2*>(vals),
+                      reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxiter, flags,
+                      static_cast<char*>(ws), info);
 }
 
+static int check_row_off(int nsys, const int* row_off, int* n_total) {
+    if (nsys < 1 || row_off == nullptr || row_off[0] != 0) return HZ_ERR_INVALID;
+    for (int j = 0; j < nsys; ++j)
+        if (row_off[j + 1] < row_off[j]) return HZ_ERR_INVALID;
+    *n_total = row_off[nsys];
+    return HZ_OK;
+}
+
+size_t zbicgstab_batched_workspace_bytes(int nsys, const int* row_off, int nnz, int flags) {
+    int n = 0;
+    if (nnz < 0 || check_row_off(nsys, row_off, &n) != HZ_OK) return 0;
+    const int L = pick_lanes(n, nnz);
+    const WorkMap m = build_map(nsys, row_off, L);
+    return ws_layout<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nsys, m.G, nullptr, nullptr);
+}
+
+int zbicgstab_solve_batched(hz_handle* h, hz_stream stream, int nsys, const int* row_off, int nnz, const int* rp,
+                            const int* ci, const hz_c128* vals, const hz_c128* b, hz_c128* x, double rtol, int maxiter,
+                            int flags, void* ws, size_t ws_bytes, hz_solve_info* infos) {
+    if (h == nullptr || infos == nullptr || nsys < 1) return HZ_ERR_INVALID;
+    std::memset(infos, 0, sizeof(hz_solve_info) * size_t(nsys));
+    int n = 0;
+    int rc = check_row_off(nsys, row_off, &n);
+    if (rc) return rc;
+    rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (!(rtol >= 0.0) || maxiter < 0) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
+        return HZ_ERR_INVALID;
+    if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
+    const size_t need = zbicgstab_batched_workspace_bytes(nsys, row_off, nnz, flags);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (flags & HZ_VALIDATE) {
+        rc = validate_csr(h, s, n, nnz, rp, ci);
+        if (rc) return rc;
+    }
+    return solve_fp64(h, s, nsys, row_off, nnz, rp, ci, reinterpret_cast<const double2*>(vals),
+                      reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxiter, flags,
+                      static_cast<char*>(ws), infos);
+}
 
 size_t zbicgstab_mixed_workspace_bytes(int n, int nnz, int flags) {
     if (n < 0 || nnz < 0) return 0;
@@ -516,8 +704,8 @@ int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const 
         return HZ_ERR_INVALID;
     if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
     const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
-    MixedWs m;
-    const size_t need = mixed_layout(n, nnz, jacobi, static_cast<char*>(ws), &m);
+    MixedWs mw;
+    const size_t need = mixed_layout(n, nnz, jacobi, static_cast<char*>(ws), &mw);
     if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
 
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -527,63 +715,66 @@ int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const 
     }
     const int L = pick_lanes(n, nnz);
     const Geom geo = geom_for(n, kBlock / L);
+    const int row_off[2] = {0, n};
+    const WorkMap m = build_map(1, row_off, L);
+    rc = upload_map(s, m, mw.in);
+    if (rc) return rc;
     const double2* A = reinterpret_cast<const double2*>(vals);
     const double2* bd = reinterpret_cast<const double2*>(b);
     double2* xd = reinterpret_cast<double2*>(x);
-    float2* r32 = static_cast<float2*>(m.in.vec[0]);
-    float2* rh32 = static_cast<float2*>(m.in.vec[1]);
     const dim3 one(1), B(kBlock);
+    double* partI = mw.in.part + hz::kPartI * m.stride;
 
-    hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, m.outer, rtol, max_outer);
-    hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, m.in.sc, inner_rtol, maxiter);
+    hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.outer, 1, rtol, max_outer);
+    hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.in.sc, 1, inner_rtol, maxiter);
     // complex64 copy of the (column-scaled) matrix; r64 holds the FP64 D^{-1} meanwhile
     const double2* dinv64 = nullptr;
     if (jacobi) {
-        hipLaunchKernelGGL(hz::k_jacobi_diag<double>, grid1(n), B, 0, s, n, rp, ci, A, m.r64, m.outer);
-        hipLaunchKernelGGL(hz::k_demote_vec, grid1(n), B, 0, s, n, static_cast<const double2*>(m.r64),
-                           static_cast<float2*>(m.in.dinv));
-        dinv64 = m.r64;
+        hipLaunchKernelGGL(hz::k_jacobi_diag<double>, grid1(n), B, 0, s, n, rp, ci, A, mw.r64, mw.outer);
+        hipLaunchKernelGGL(hz::k_demote_vec, grid1(n), B, 0, s, n, static_cast<const double2*>(mw.r64),
+                           static_cast<float2*>(mw.in.dinv));
+        dinv64 = mw.r64;
     }
     if (nnz > 0)
         hipLaunchKernelGGL(hz::k_demote_vals, grid1(nnz), B, 0, s, int64_t(nnz), ci, A, dinv64,
-                           static_cast<float2*>(m.in.ahat));
+                           static_cast<float2*>(mw.in.ahat));
     if (flags & HZ_X0_ZERO) HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
-    double* partI = m.in.part + hz::kPartI * kMaxGrid;
     hipLaunchKernelGGL(hz::k_dot_part<1>, dim3(geo.G), B, 0, s, n, geo, bd, nullptr, partI);
-    hipLaunchKernelGGL(hz::k_fin_bnorm, one, B, 0, s, partI, geo.G, m.outer);
+    hipLaunchKernelGGL(hz::k_fin_bnorm, one, B, 0, s, partI, geo.G, mw.outer);
     HZ_HIP(hipGetLastError());
     rc = enqueue_far_count(h, s, n, rp, ci);
     if (rc) return rc;
     SolverScal* ho = h->hsc2;
     SolverScal* hi = h->hsc;
-    HZ_HIP(hipMemcpyAsync(ho, m.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipMemcpyAsync(ho, mw.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
     HZ_HIP(hipStreamSynchronize(s));
     if (ho->bad_diag) return HZ_ERR_INVALID;
     const bool fused = choose_fused(h, nnz);
+    const hz::BicgArgs<float> ai =
+        bicg_args<float>(m, rp, ci, static_cast<const float2*>(mw.in.ahat), mw.b32, mw.d32, mw.in);
 
-    const float2* dinv32 = jacobi ? static_cast<const float2*>(m.in.dinv) : nullptr;
+    const float2* dinv32 = jacobi ? static_cast<const float2*>(mw.in.dinv) : nullptr;
     int inner_total = 0, outer = 0;
     for (;; ++outer) {
         // r = b - A x in FP64, and the outer decision
-        launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, m.r64, bd, partI), s);
-        hipLaunchKernelGGL(hz::k_fin_outer, one, B, 0, s, partI, geo.G, m.outer, outer, max_outer);
+        launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, mw.r64, bd, partI), s);
+        hipLaunchKernelGGL(hz::k_fin_outer, one, B, 0, s, partI, geo.G, mw.outer, outer, max_outer);
         HZ_HIP(hipGetLastError());
-        HZ_HIP(hipMemcpyAsync(ho, m.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipMemcpyAsync(ho, mw.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
         HZ_HIP(hipStreamSynchronize(s));
         if (ho->done) break;
         // inner complex64 solve of A d = r / ||r|| from d = 0
-        hipLaunchKernelGGL(hz::k_demote_scaled, grid1(n), B, 0, s, n, static_cast<const double2*>(m.r64), m.outer,
-                           m.b32);
-        HZ_HIP(hipMemsetAsync(m.d32, 0, 8 * size_t(n), s));
-        hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, m.in.sc, inner_rtol, maxiter);
-        hipLaunchKernelGGL(hz::k_init<float>, dim3(geo.G), B, 0, s, n, geo, static_cast<const float2*>(m.b32),
-                           static_cast<const float2*>(m.b32), r32, rh32, m.in.part);
-        hipLaunchKernelGGL(hz::k_fin_init, one, B, 0, s, m.in.part, geo.G, m.in.sc);
+        hipLaunchKernelGGL(hz::k_demote_scaled, grid1(n), B, 0, s, n, static_cast<const double2*>(mw.r64), mw.outer,
+                           mw.b32);
+        HZ_HIP(hipMemsetAsync(mw.d32, 0, 8 * size_t(n), s));
+        HZ_HIP(hipMemsetAsync(mw.in.ndone, 0, sizeof(int), s));
+        hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.in.sc, 1, inner_rtol, maxiter);
+        hipLaunchKernelGGL(hz::k_init<float>, dim3(m.G), B, 0, s, ai, static_cast<const float2*>(mw.b32));
+        hipLaunchKernelGGL(hz::k_fin_init<float>, one, B, 0, s, ai);
         HZ_HIP(hipGetLastError());
-        rc = iterate<float>(h, s, n, L, geo, rp, ci, static_cast<const float2*>(m.in.ahat), m.d32, m.in, maxiter,
-                            fused);
+        rc = iterate<float>(h, s, m, ai, L, maxiter, fused);
         if (rc) return rc;
-        HZ_HIP(hipMemcpyAsync(hi, m.in.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipMemcpyAsync(hi, mw.in.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
         HZ_HIP(hipStreamSynchronize(s));
         inner_total += hi->iters;
         if (hi->status == HZ_NONFINITE) {
@@ -592,10 +783,10 @@ int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const 
             info->outer_steps = outer + 1;
             return HZ_NONFINITE;
         }
-        hipLaunchKernelGGL(hz::k_promote_add, grid1(n), B, 0, s, n, static_cast<const float2*>(m.d32), dinv32,
-                           static_cast<const SolverScal*>(m.outer), xd);
+        hipLaunchKernelGGL(hz::k_promote_add, grid1(n), B, 0, s, n, static_cast<const float2*>(mw.d32), dinv32,
+                           static_cast<const SolverScal*>(mw.outer), xd);
     }
-    hipLaunchKernelGGL(hz::k_zero_if<double>, grid1(n), B, 0, s, n, static_cast<const SolverScal*>(m.outer), xd);
+    if (ho->zero_x) HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
     HZ_HIP(hipGetLastError());
     HZ_HIP(hipStreamSynchronize(s));
     info->status = ho->status;
@@ -604,6 +795,100 @@ int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const 
     info->relres_recursive = ho->relres;
     info->relres_true = ho->relres_true;
     return ho->status;
+}
+
+
+
+int csr_zspmv_rect(hz_handle* h, hz_stream stream, int m, int ncols, int nnz, const int* rp, const int* ci,
+                   const hz_c128* vals, const hz_c128* x, hz_c128* y) {
+    if (h == nullptr || m < 0 || ncols < 0) return HZ_ERR_INVALID;
+    int rc = check_csr_args(m, nnz, rp, ci, vals);
+    if (rc || m == 0) return rc;
+    if (y == nullptr || (ncols > 0 && x == nullptr)) return HZ_ERR_INVALID;
+    if (misaligned(x, 16) || misaligned(y, 16) || misaligned(vals, 16)) return HZ_ERR_INVALID;
+    if (ncols > 0 && overlap(x, 16 * size_t(ncols), y, 16 * size_t(m))) return HZ_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int L = pick_lanes(m, nnz);
+    const Geom geo = geom_for(m, kBlock / L);
+    auto a = spmv_args<double>(m, geo, rp, ci, reinterpret_cast<const double2*>(vals),
+                               reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nullptr, nullptr);
+    launch_spmv<double, hz::EPI_NONE>(L, a, s);
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+int csr_zgrad_vals(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c128* lambda,
+                   const hz_c128* x, hz_c128* grad_vals) {
+    if (h == nullptr) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, grad_vals);
+    if (rc || n == 0 || nnz == 0) return rc;
+    if (lambda == nullptr || x == nullptr || misaligned(lambda, 16) || misaligned(x, 16) || misaligned(grad_vals, 16))
+        return HZ_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    launch_grad_vals(n, rp, ci, reinterpret_cast<const double2*>(lambda), reinterpret_cast<const double2*>(x),
+                     reinterpret_cast<double2*>(grad_vals), pick_lanes(n, nnz), s);
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+size_t zbicgstab_adjoint_workspace_bytes(int n, int nnz, int flags) {
+    if (n < 0 || nnz < 0) return 0;
+    return adjoint_layout(n, nnz, flags, nullptr, nullptr);
+}
+
+int zbicgstab_adjoint(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c128* vals,
+                      const hz_c128* x, const hz_c128* grad_x, hz_c128* grad_b, hz_c128* grad_vals, double rtol,
+                      int maxiter, int flags, void* ws, size_t ws_bytes, hz_solve_info* info) {
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (h == nullptr || info == nullptr) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (!(rtol >= 0.0) || maxiter < 0) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (grad_x == nullptr || grad_b == nullptr || misaligned(grad_x, 16) || misaligned(grad_b, 16) ||
+        misaligned(vals, 16))
+        return HZ_ERR_INVALID;
+    if (grad_vals != nullptr && (x == nullptr || misaligned(x, 16) || misaligned(grad_vals, 16))) return HZ_ERR_INVALID;
+    if (overlap(grad_x, 16 * size_t(n), grad_b, 16 * size_t(n))) return HZ_ERR_INVALID;
+    AdjWs a;
+    const size_t need = adjoint_layout(n, nnz, flags, static_cast<char*>(ws), &a);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (flags & HZ_VALIDATE) {
+        rc = validate_csr(h, s, n, nnz, rp, ci);
+        if (rc) return rc;
+    }
+    const double2* A = reinterpret_cast<const double2*>(vals);
+    const double2* g = reinterpret_cast<const double2*>(grad_x);
+    double2* lam = reinterpret_cast<double2*>(grad_b);
+    const int sflags = (flags & HZ_PRECOND_JACOBI) | HZ_X0_ZERO;
+    const int row_off[2] = {0, n};
+    if (flags & HZ_SYMMETRIC) {
+        // A^H lambda = g  <=>  A conj(lambda) = conj(g)  when A = A^T
+        hipLaunchKernelGGL(hz::k_conj, grid1(n), dim3(kBlock), 0, s, n, g, a.gconj);
+        HZ_HIP(hipGetLastError());
+        rc = solve_fp64(h, s, 1, row_off, nnz, rp, ci, A, a.gconj, lam, rtol, maxiter, sflags, a.solve, info);
+        if (rc < 0) return rc;
+        hipLaunchKernelGGL(hz::k_conj, grid1(n), dim3(kBlock), 0, s, n, static_cast<const double2*>(lam), lam);
+    } else {
+        // A^H in CSR: column counts, scan, scatter, per-row sort
+        HZ_HIP(hipMemsetAsync(a.t_rp, 0, sizeof(int) * (size_t(n) + 1), s));
+        if (nnz > 0) hipLaunchKernelGGL(hz::k_tr_count, grid1(nnz), dim3(kBlock), 0, s, int64_t(nnz), ci, a.t_rp);
+        hipLaunchKernelGGL(hz::k_scan_1block, dim3(1), dim3(1024), 0, s, n + 1, a.t_rp);
+        HZ_HIP(hipMemcpyAsync(a.fill, a.t_rp, sizeof(int) * size_t(n), hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(hz::k_tr_scatter, grid1(n), dim3(kBlock), 0, s, n, rp, ci, A, a.fill, a.t_ci, a.t_vals);
+        hipLaunchKernelGGL(hz::k_tr_sort, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(a.t_rp), a.t_ci,
+                           a.t_vals);
+        HZ_HIP(hipGetLastError());
+        rc = solve_fp64(h, s, 1, row_off, nnz, a.t_rp, a.t_ci, a.t_vals, g, lam, rtol, maxiter, sflags, a.solve, info);
+        if (rc < 0) return rc;
+    }
+    if (grad_vals != nullptr && nnz > 0)
+        launch_grad_vals(n, rp, ci, lam, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(grad_vals),
+                         pick_lanes(n, nnz), s);
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipStreamSynchronize(s));
+    return info->status;
 }
 
 }  // extern "C"

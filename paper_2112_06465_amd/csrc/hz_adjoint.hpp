@@ -84,8 +84,8 @@ __global__ __launch_bounds__(kBlock) void k_tr_sort(int n, const int* __restrict
     }
 }
 
-// out = conj(in)
-__global__ __launch_bounds__(kBlock) void k_conj(int n, const double2* __restrict__ in, double2* __restrict__ out) {
+// out = conj(in); in and out may be the same array
+__global__ __launch_bounds__(kBlock) void k_conj(int n, const double2* in, double2* out) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i < n) {
         const double2 a = in[i];

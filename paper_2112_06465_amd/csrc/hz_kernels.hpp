@@ -249,9 +249,10 @@ __device__ __forceinline__ cx<T> row_partial(int beg, int end, int lane, const i
 
 // ------------------------------------------------------------------ solver scalars (device resident)
 
-// Written only by thread 0 of block 0 of a kernel, and read only by later
-// kernels (never by other blocks of the writing kernel), except `done`,
-// whose early read by other blocks leads to the same exit they compute.
+// One block per system.  Written only by thread 0 of the system's first
+// block, and read only by later kernels (never by other blocks of the
+// writing kernel), except `done`, whose early read by other blocks of the
+// system leads to the exit they would compute themselves.
 struct alignas(256) SolverScal {
     double2 rho2[2];  // rho of iteration i in slot i & 1
     double2 alpha;    // alpha of the current iteration
@@ -262,7 +263,7 @@ struct alignas(256) SolverScal {
     double relres;       // last recursive ||r|| / ||b|| (or ||s|| / ||b||)
     double relres_true;  // filled by the final residual check
     double outer_rn;     // refinement: ||b - A x|| of the current outer step
-    int iter;            // next iteration to run (1-based); written by the third kernel of an iteration
+    int iter;            // next iteration to run (1-based); written by the last kernel of an iteration
     int cur;             // iteration in progress; written by the first kernel of an iteration
     int maxiter;
     int status;  // solver status once done
@@ -270,26 +271,118 @@ struct alignas(256) SolverScal {
     int iters;   // reported iteration count
     int zero_x;  // ||b|| = 0: the solution is x = 0
     int bad_diag;  // Jacobi requested with a zero diagonal entry
-    int pending;   // half-step exit taken in iteration `pending`; the next A-kernel concludes
+    int pending;   // half-step exit taken in iteration `pending`; the next first kernel concludes
 };
 
 enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = 2, ST_NONFINITE = 3 };
 
-__device__ __forceinline__ void finish(SolverScal* sc, int status, int iterations) {
-    sc->status = status;
-    sc->iters = iterations;
-    sc->done = 1;
-}
-__device__ __forceinline__ bool leader() { return blockIdx.x == 0 && threadIdx.x == 0; }
-
-// Reset a scalar block before a solve (one thread).
-__global__ void k_sc_init(SolverScal* sc, double rtol, int maxiter) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Reset the scalar blocks of nsys systems before a solve.
+__global__ void k_sc_init(SolverScal* sc, int nsys, double rtol, int maxiter) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nsys) return;
     SolverScal z = {};
     z.rtol = rtol;
     z.maxiter = maxiter;
     z.status = ST_NOT_CONVERGED;
-    *sc = z;
+    sc[j] = z;
+}
+
+// ------------------------------------------------------------------ work map of a solver launch
+
+// Logical block lb of a solver launch belongs to system `sys`, owns rows
+// [r0, r1) of the (block-diagonal) matrix and is the `local`-th block of its
+// system; sys < 0 marks padding.  System j owns the contiguous logical block
+// range [gbeg, gbeg + gcnt).  A single solve is the one-system case.
+struct BlockMap {
+    int sys, r0, r1, local;
+};
+struct SysMap {
+    int gbeg, gcnt, row0, row1;
+};
+
+template <typename T> struct BicgArgs {
+    int G;       // blocks of every solver launch (a multiple of 8, or < 8)
+    int stride;  // partial component stride (>= G)
+    const BlockMap* bmap;
+    const SysMap* smap;
+    int* ndone;  // systems finished so far
+    const int* __restrict__ row_ptr;
+    const int* __restrict__ col_idx;
+    const cx<T>* __restrict__ vals;
+    const cx<T>* b;
+    cx<T>* r;
+    const cx<T>* rh;
+    cx<T>* p[2];
+    cx<T>* v[2];
+    cx<T>* s;
+    cx<T>* t;
+    cx<T>* x;
+    double* part;
+    SolverScal* sc;
+};
+
+struct SysBlock {
+    int lb, sys, local;
+    int64_t r0, r1;
+    int gbeg, gcnt;
+};
+template <typename T> __device__ __forceinline__ SysBlock sys_block(const BicgArgs<T>& a) {
+    SysBlock q;
+    q.lb = logical_block(blockIdx.x, a.G);
+    const BlockMap m = a.bmap[q.lb];
+    q.sys = m.sys;
+    q.local = m.local;
+    q.r0 = m.r0;
+    q.r1 = m.r1;
+    if (m.sys >= 0) {
+        const SysMap sm = a.smap[m.sys];
+        q.gbeg = sm.gbeg;
+        q.gcnt = sm.gcnt;
+    } else {
+        q.gbeg = q.gcnt = 0;
+    }
+    return q;
+}
+
+__device__ __forceinline__ bool sys_leader(const SysBlock& q) { return q.local == 0 && threadIdx.x == 0; }
+
+// Record the end of system q's solve (its leader thread only).
+__device__ __forceinline__ void finish(SolverScal* sc, int* ndone, int status, int iterations) {
+    sc->status = status;
+    sc->iters = iterations;
+    sc->done = 1;
+    atomicAdd(ndone, 1);
+}
+
+// Sum of K components over one system's partials [gbeg, gbeg + gcnt), in a
+// fixed order, delivered to every thread of the block.
+template <int K>
+__device__ __forceinline__ void sys_sum(const double* __restrict__ part, int stride, int gbeg, int gcnt,
+                                        double (&out)[K]) {
+    __shared__ double bc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int g = threadIdx.x; g < gcnt; g += kBlock) s += part[k * stride + gbeg + g];
+        out[k] = s;
+    }
+    block_sum<K>(out);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) bc[k] = out[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = bc[k];
+}
+
+template <int K>
+__device__ __forceinline__ void store_sys_partials(double* __restrict__ part, int stride, int lb, double (&e)[K]) {
+    block_sum<K>(e);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) part[k * stride + lb] = e[k];
+    }
 }
 
 // ------------------------------------------------------------------ standalone SpMV with residual epilogue
@@ -340,10 +433,40 @@ __global__ HZ_STREAM_BOUNDS void k_spmv(const SpmvArgs<T> a) {
     if constexpr (EPI == EPI_RESID) store_partials<1>(a.part, rr.lb, e);
 }
 
+// y = b - A x over the solver's work map, per-system partial ||y||^2 in
+// region I (the initial residual and the final true residual of a solve).
+template <typename T, int L, int U>
+__global__ HZ_STREAM_BOUNDS void k_sys_resid(const BicgArgs<T> a, const cx<T>* __restrict__ vals,
+                                             const cx<T>* __restrict__ xin, cx<T>* __restrict__ y) {
+    const SysBlock q = sys_block(a);
+    if (q.sys < 0) return;
+    constexpr int RPS = kBlock / L;
+    const int g = threadIdx.x / L, lane = threadIdx.x % L;
+    auto op = [xin](int c) { return xin[c]; };
+    double e[1] = {0.0};
+    for (int64_t base = q.r0; base < q.r1; base += RPS) {
+        const int64_t row = base + g;
+        const bool ok = row < q.r1;
+        cx<T> acc = mk<T>(T(0), T(0));
+        if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, vals, op);
+        acc.x = group_sum<L>(acc.x);
+        acc.y = group_sum<L>(acc.y);
+        if (ok && lane == 0) {
+            const cx<T> bw = a.b[row];
+            acc.x = bw.x - acc.x;
+            acc.y = bw.y - acc.y;
+            e[0] = __builtin_fma((double)acc.x, (double)acc.x, e[0]);
+            e[0] = __builtin_fma((double)acc.y, (double)acc.y, e[0]);
+            y[row] = acc;
+        }
+    }
+    store_sys_partials<1>(a.part + kPartI * a.stride, a.stride, q.lb, e);
+}
+
 // ------------------------------------------------------------------ BiCGStab: three kernels per iteration
 //
 // Iteration i (Section 7's P-BiCGSTAB, right-preconditioned; A here is the
-// column-scaled matrix under Jacobi):
+// column-scaled matrix under Jacobi), for every system of the launch:
 //   A-kernel: decide the end of iteration i-1 from <rhat,r>, ||r||; beta;
 //             v = A p with p = r + beta (p_old - omega v_old) formed for every
 //             gathered column; store p, v; partial <rhat, v>.
@@ -352,44 +475,30 @@ __global__ HZ_STREAM_BOUNDS void k_spmv(const SpmvArgs<T> a) {
 //   C-kernel: half-step test on ||s||; omega = <t,s>/<t,t>;
 //             x += alpha p + omega s; r = s - omega t; partials <rhat,r>, ||r||^2.
 // p and v are double-buffered by the parity of i, so the A-kernel reads the
-// old vectors while writing the new ones.
+// old vectors while writing the new ones.  Systems of a batch share nothing
+// but the launches: each has its own scalars, partial range and exit.
 
-template <typename T> struct BicgArgs {
-    int n;
-    Geom geo;
-    const int* __restrict__ row_ptr;
-    const int* __restrict__ col_idx;
-    const cx<T>* __restrict__ vals;
-    cx<T>* r;
-    const cx<T>* rh;
-    cx<T>* p[2];
-    cx<T>* v[2];
-    cx<T>* s;
-    cx<T>* t;
-    cx<T>* x;
-    double* part;
-    SolverScal* sc;
-};
-
-// Start of iteration i = sc->iter: conclude iteration i-1 (convergence on
-// ||r||, breakdown, iteration limit) from the partials <rhat, r>, ||r||^2,
-// then rho_i and beta.  Returns false when the solve has ended (every block
-// returns); block 0 records the decision.
+// Start of iteration i = sc->iter for the block's system: conclude iteration
+// i-1 (convergence on ||r||, breakdown, iteration limit) from the partials
+// <rhat, r>, ||r||^2, then rho_i and beta.  Returns false when the system's
+// solve has ended (every block of the system returns); its leader records
+// the decision.
 struct IterStart {
     int it;
     double2 rho, beta, omega;
 };
 template <typename T>
-__device__ __forceinline__ bool iteration_start(const BicgArgs<T>& a, IterStart& st) {
-    SolverScal* sc = a.sc;
+__device__ __forceinline__ bool iteration_start(const BicgArgs<T>& a, const SysBlock& q, IterStart& st) {
+    if (q.sys < 0) return false;
+    SolverScal* sc = a.sc + q.sys;
     if (sc->done) return false;
     if (sc->pending) {  // every block of the previous kernel has applied x += alpha p
-        if (leader()) finish(sc, ST_OK, sc->pending);
+        if (sys_leader(q)) finish(sc, a.ndone, ST_OK, sc->pending);
         return false;
     }
     const int it = sc->iter;
     double h[3];
-    head_sum<3>(a.part + kPartC * kMaxGrid, a.geo.G, h);
+    sys_sum<3>(a.part + kPartC * a.stride, a.stride, q.gbeg, q.gcnt, h);
     const double2 rho = mk<double>(h[0], h[1]);
     double2 beta = mk<double>(0.0, 0.0), om = mk<double>(0.0, 0.0);
     if (it > 1) {
@@ -406,13 +515,13 @@ __device__ __forceinline__ bool iteration_start(const BicgArgs<T>& a, IterStart&
             beta = zmul(zdiv(rho, sc->rho2[(it - 1) & 1]), zdiv(sc->alpha, om));
             if (!zfinite(beta)) stt = ST_NONFINITE, sit = it;
         }
-        if (leader()) sc->relres = rel;
+        if (sys_leader(q)) sc->relres = rel;
         if (stt >= 0) {
-            if (leader()) finish(sc, stt, sit);
+            if (sys_leader(q)) finish(sc, a.ndone, stt, sit);
             return false;
         }
     }
-    if (leader()) {
+    if (sys_leader(q)) {
         sc->rho2[it & 1] = rho;
         sc->beta = beta;
         sc->cur = it;
@@ -434,12 +543,12 @@ __device__ __forceinline__ cx<T> p_update(bool first, cx<T> bt, cx<T> omt, cx<T>
 
 template <typename T, int L, int U>
 __global__ HZ_STREAM_BOUNDS void k_bicg_A(const BicgArgs<T> a) {
+    const SysBlock q = sys_block(a);
     IterStart st;
-    if (!iteration_start(a, st)) return;
+    if (!iteration_start(a, q, st)) return;
     const int it = st.it;
-    const double2 beta = st.beta, om = st.omega;
     const bool first = it == 1;
-    const cx<T> bt = narrow<T>(beta), omt = narrow<T>(om);
+    const cx<T> bt = narrow<T>(st.beta), omt = narrow<T>(st.omega);
     const cx<T>* __restrict__ r = a.r;
     const cx<T>* __restrict__ pold = a.p[(it - 1) & 1];
     const cx<T>* __restrict__ vold = a.v[(it - 1) & 1];
@@ -450,12 +559,11 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_A(const BicgArgs<T> a) {
         return p_update<T>(false, bt, omt, r[c], pold[c], vold[c]);
     };
     constexpr int RPS = kBlock / L;
-    const RowRange rr = rows_of_block(a.n, a.geo);
     const int g = threadIdx.x / L, lane = threadIdx.x % L;
     double e[2] = {0.0, 0.0};
-    for (int64_t base = rr.r0; base < rr.r1; base += RPS) {
+    for (int64_t base = q.r0; base < q.r1; base += RPS) {
         const int64_t row = base + g;
-        const bool ok = row < rr.r1;
+        const bool ok = row < q.r1;
         cx<T> acc = mk<T>(T(0), T(0));
         if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, pcol);
         acc.x = group_sum<L>(acc.x);
@@ -469,34 +577,44 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_A(const BicgArgs<T> a) {
             e[1] = c.y;
         }
     }
-    store_partials<2>(a.part + kPartA * kMaxGrid, rr.lb, e);
+    store_sys_partials<2>(a.part + kPartA * a.stride, a.stride, q.lb, e);
+}
+
+// alpha = rho / <rhat, v> for the block's system; false when the system ends here.
+template <typename T>
+__device__ __forceinline__ bool alpha_step(const BicgArgs<T>& a, const SysBlock& q, int& it, double2& alpha) {
+    if (q.sys < 0) return false;
+    SolverScal* sc = a.sc + q.sys;
+    if (sc->done) return false;
+    it = sc->cur;
+    double h[2];
+    sys_sum<2>(a.part + kPartA * a.stride, a.stride, q.gbeg, q.gcnt, h);
+    const double2 sigma = mk<double>(h[0], h[1]);
+    if (!zfinite(sigma) || zzero(sigma)) {
+        if (sys_leader(q)) finish(sc, a.ndone, zzero(sigma) ? ST_BREAKDOWN : ST_NONFINITE, it);
+        return false;
+    }
+    alpha = zdiv(sc->rho2[it & 1], sigma);
+    if (sys_leader(q)) sc->alpha = alpha;
+    return true;
 }
 
 template <typename T, int L, int U>
 __global__ HZ_STREAM_BOUNDS void k_bicg_B(const BicgArgs<T> a) {
-    SolverScal* sc = a.sc;
-    if (sc->done) return;
-    const int it = sc->cur;
-    double h[2];
-    head_sum<2>(a.part + kPartA * kMaxGrid, a.geo.G, h);
-    const double2 sigma = mk<double>(h[0], h[1]);
-    if (!zfinite(sigma) || zzero(sigma)) {
-        if (leader()) finish(sc, zzero(sigma) ? ST_BREAKDOWN : ST_NONFINITE, it);
-        return;
-    }
-    const double2 alpha = zdiv(sc->rho2[it & 1], sigma);
-    if (leader()) sc->alpha = alpha;
+    const SysBlock q = sys_block(a);
+    int it;
+    double2 alpha;
+    if (!alpha_step(a, q, it, alpha)) return;
     const cx<T> al = narrow<T>(alpha);
     const cx<T>* __restrict__ r = a.r;
     const cx<T>* __restrict__ v = a.v[it & 1];
     auto scol = [=](int c) { return cfma<T>(mk<T>(-al.x, -al.y), v[c], r[c]); };
     constexpr int RPS = kBlock / L;
-    const RowRange rr = rows_of_block(a.n, a.geo);
     const int g = threadIdx.x / L, lane = threadIdx.x % L;
     double e[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t base = rr.r0; base < rr.r1; base += RPS) {
+    for (int64_t base = q.r0; base < q.r1; base += RPS) {
         const int64_t row = base + g;
-        const bool ok = row < rr.r1;
+        const bool ok = row < q.r1;
         cx<T> acc = mk<T>(T(0), T(0));
         if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, scol);
         acc.x = group_sum<L>(acc.x);
@@ -514,28 +632,29 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_B(const BicgArgs<T> a) {
             e[3] = __builtin_fma((double)acc.y, (double)acc.y, e[3]);
         }
     }
-    store_partials<4>(a.part + kPartB * kMaxGrid, rr.lb, e);
+    store_sys_partials<4>(a.part + kPartB * a.stride, a.stride, q.lb, e);
 }
 
 template <typename T>
 __global__ HZ_STREAM_BOUNDS void k_bicg_C(const BicgArgs<T> a) {
-    SolverScal* sc = a.sc;
+    const SysBlock q = sys_block(a);
+    if (q.sys < 0) return;
+    SolverScal* sc = a.sc + q.sys;
     if (sc->done) return;
     const int it = sc->cur;
     double h[4];
-    head_sum<4>(a.part + kPartB * kMaxGrid, a.geo.G, h);
+    sys_sum<4>(a.part + kPartB * a.stride, a.stride, q.gbeg, q.gcnt, h);
     const double rel = __builtin_sqrt(h[0]) / sc->bnorm;
     const double2 alpha = sc->alpha;
     const cx<T> al = narrow<T>(alpha);
     const cx<T>* __restrict__ p = a.p[it & 1];
-    const RowRange rr = rows_of_block(a.n, a.geo);
     if (!__builtin_isfinite(rel)) {
-        if (leader()) finish(sc, ST_NONFINITE, it);
+        if (sys_leader(q)) finish(sc, a.ndone, ST_NONFINITE, it);
         return;
     }
-    if (rel <= sc->rtol) {  // half-step exit: x += alpha p (concluded by the next A-kernel)
-        for (int64_t i = rr.r0 + threadIdx.x; i < rr.r1; i += kBlock) a.x[i] = cfma<T>(al, p[i], a.x[i]);
-        if (leader()) {
+    if (rel <= sc->rtol) {  // half-step exit: x += alpha p (concluded by the next first kernel)
+        for (int64_t i = q.r0 + threadIdx.x; i < q.r1; i += kBlock) a.x[i] = cfma<T>(al, p[i], a.x[i]);
+        if (sys_leader(q)) {
             sc->relres = rel;
             sc->pending = it;
         }
@@ -552,16 +671,16 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_C(const BicgArgs<T> a) {
         if (!zfinite(om)) st = ST_NONFINITE;
     }
     if (st >= 0) {
-        if (leader()) finish(sc, st, it);
+        if (sys_leader(q)) finish(sc, a.ndone, st, it);
         return;
     }
-    if (leader()) {
+    if (sys_leader(q)) {
         sc->omega = om;
         sc->iter = it + 1;
     }
     const cx<T> omt = narrow<T>(om), nom = mk<T>(-omt.x, -omt.y);
     double e[3] = {0.0, 0.0, 0.0};
-    for (int64_t i = rr.r0 + threadIdx.x; i < rr.r1; i += kBlock) {
+    for (int64_t i = q.r0 + threadIdx.x; i < q.r1; i += kBlock) {
         const cx<T> sv = a.s[i], tv = a.t[i], rh = a.rh[i];
         cx<T> x = a.x[i];
         x = cfma<T>(al, p[i], x);
@@ -575,9 +694,8 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_C(const BicgArgs<T> a) {
         e[2] = __builtin_fma((double)r.x, (double)r.x, e[2]);
         e[2] = __builtin_fma((double)r.y, (double)r.y, e[2]);
     }
-    store_partials<3>(a.part + kPartC * kMaxGrid, rr.lb, e);
+    store_sys_partials<3>(a.part + kPartC * a.stride, a.stride, q.lb, e);
 }
-
 
 // ------------------------------------------------------------------ gather-light variant (five kernels)
 //
@@ -593,34 +711,35 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_C(const BicgArgs<T> a) {
 
 template <typename T>
 __global__ HZ_STREAM_BOUNDS void k_bicg_P(const BicgArgs<T> a) {
+    const SysBlock q = sys_block(a);
     IterStart st;
-    if (!iteration_start(a, st)) return;
+    if (!iteration_start(a, q, st)) return;
     const int it = st.it;
     const bool first = it == 1;
     const cx<T> bt = narrow<T>(st.beta), omt = narrow<T>(st.omega);
     const cx<T>* __restrict__ pold = a.p[(it - 1) & 1];
     const cx<T>* __restrict__ vold = a.v[(it - 1) & 1];
     cx<T>* __restrict__ pnew = a.p[it & 1];
-    const RowRange rr = rows_of_block(a.n, a.geo);
-    for (int64_t i = rr.r0 + threadIdx.x; i < rr.r1; i += kBlock)
+    for (int64_t i = q.r0 + threadIdx.x; i < q.r1; i += kBlock)
         pnew[i] = first ? a.r[i] : p_update<T>(false, bt, omt, a.r[i], pold[i], vold[i]);
 }
 
 template <typename T, int L, int U>
 __global__ HZ_STREAM_BOUNDS void k_bicg_A1(const BicgArgs<T> a) {
-    SolverScal* sc = a.sc;
+    const SysBlock q = sys_block(a);
+    if (q.sys < 0) return;
+    const SolverScal* sc = a.sc + q.sys;
     if (sc->done || sc->pending) return;
     const int it = sc->cur;
     const cx<T>* __restrict__ p = a.p[it & 1];
     cx<T>* __restrict__ v = a.v[it & 1];
     auto pcol = [p](int c) { return p[c]; };
     constexpr int RPS = kBlock / L;
-    const RowRange rr = rows_of_block(a.n, a.geo);
     const int g = threadIdx.x / L, lane = threadIdx.x % L;
     double e[2] = {0.0, 0.0};
-    for (int64_t base = rr.r0; base < rr.r1; base += RPS) {
+    for (int64_t base = q.r0; base < q.r1; base += RPS) {
         const int64_t row = base + g;
-        const bool ok = row < rr.r1;
+        const bool ok = row < q.r1;
         cx<T> acc = mk<T>(T(0), T(0));
         if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, pcol);
         acc.x = group_sum<L>(acc.x);
@@ -633,49 +752,40 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_A1(const BicgArgs<T> a) {
             e[1] = c.y;
         }
     }
-    store_partials<2>(a.part + kPartA * kMaxGrid, rr.lb, e);
+    store_sys_partials<2>(a.part + kPartA * a.stride, a.stride, q.lb, e);
 }
 
 template <typename T>
 __global__ HZ_STREAM_BOUNDS void k_bicg_S(const BicgArgs<T> a) {
-    SolverScal* sc = a.sc;
-    if (sc->done) return;
-    const int it = sc->cur;
-    double h[2];
-    head_sum<2>(a.part + kPartA * kMaxGrid, a.geo.G, h);
-    const double2 sigma = mk<double>(h[0], h[1]);
-    if (!zfinite(sigma) || zzero(sigma)) {
-        if (leader()) finish(sc, zzero(sigma) ? ST_BREAKDOWN : ST_NONFINITE, it);
-        return;
-    }
-    const double2 alpha = zdiv(sc->rho2[it & 1], sigma);
-    if (leader()) sc->alpha = alpha;
+    const SysBlock q = sys_block(a);
+    int it;
+    double2 alpha;
+    if (!alpha_step(a, q, it, alpha)) return;
     const cx<T> nal = mk<T>((T)-alpha.x, (T)-alpha.y);
     const cx<T>* __restrict__ v = a.v[it & 1];
-    const RowRange rr = rows_of_block(a.n, a.geo);
     double e[1] = {0.0};
-    for (int64_t i = rr.r0 + threadIdx.x; i < rr.r1; i += kBlock) {
+    for (int64_t i = q.r0 + threadIdx.x; i < q.r1; i += kBlock) {
         const cx<T> s = cfma<T>(nal, v[i], a.r[i]);
         a.s[i] = s;
         e[0] = __builtin_fma((double)s.x, (double)s.x, e[0]);
         e[0] = __builtin_fma((double)s.y, (double)s.y, e[0]);
     }
-    store_partials<1>(a.part + kPartB * kMaxGrid, rr.lb, e);
+    store_sys_partials<1>(a.part + kPartB * a.stride, a.stride, q.lb, e);
 }
 
 template <typename T, int L, int U>
 __global__ HZ_STREAM_BOUNDS void k_bicg_B1(const BicgArgs<T> a) {
-    SolverScal* sc = a.sc;
-    if (sc->done) return;
+    const SysBlock q = sys_block(a);
+    if (q.sys < 0) return;
+    if (a.sc[q.sys].done) return;
     const cx<T>* __restrict__ sv = a.s;
     auto scol = [sv](int c) { return sv[c]; };
     constexpr int RPS = kBlock / L;
-    const RowRange rr = rows_of_block(a.n, a.geo);
     const int g = threadIdx.x / L, lane = threadIdx.x % L;
     double e[3] = {0.0, 0.0, 0.0};
-    for (int64_t base = rr.r0; base < rr.r1; base += RPS) {
+    for (int64_t base = q.r0; base < q.r1; base += RPS) {
         const int64_t row = base + g;
-        const bool ok = row < rr.r1;
+        const bool ok = row < q.r1;
         cx<T> acc = mk<T>(T(0), T(0));
         if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, scol);
         acc.x = group_sum<L>(acc.x);
@@ -690,7 +800,7 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_B1(const BicgArgs<T> a) {
             e[2] = __builtin_fma((double)acc.y, (double)acc.y, e[2]);
         }
     }
-    store_partials<3>(a.part + (kPartB + 1) * kMaxGrid, rr.lb, e);
+    store_sys_partials<3>(a.part + (kPartB + 1) * a.stride, a.stride, q.lb, e);
 }
 
 // Locality of a CSR matrix: count of entries with |col - row| > W (integer atomics).
@@ -710,14 +820,14 @@ __global__ __launch_bounds__(kBlock) void k_far_count(int n, const int* __restri
 // Solve set-up: r = src (b, or the residual b - A x0), rhat = r;
 // partials <rhat, r>, ||r||^2 (region C) and ||b||^2 (region I).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_init(int n, Geom geo, const cx<T>* __restrict__ b, const cx<T>* src,
-                                                 cx<T>* r, cx<T>* __restrict__ rh, double* __restrict__ part) {
-    const RowRange rr = rows_of_block(n, geo);
+__global__ __launch_bounds__(kBlock) void k_init(const BicgArgs<T> a, const cx<T>* src) {
+    const SysBlock q = sys_block(a);
+    if (q.sys < 0) return;
     double e[3] = {0.0, 0.0, 0.0}, eb[1] = {0.0};
-    for (int64_t i = rr.r0 + threadIdx.x; i < rr.r1; i += kBlock) {
-        const cx<T> bv = b[i], rv = src[i];
-        if (r != src) r[i] = rv;
-        rh[i] = rv;
+    for (int64_t i = q.r0 + threadIdx.x; i < q.r1; i += kBlock) {
+        const cx<T> bv = a.b[i], rv = src[i];
+        if (a.r != src) a.r[i] = rv;
+        const_cast<cx<T>*>(a.rh)[i] = rv;
         eb[0] = __builtin_fma((double)bv.x, (double)bv.x, eb[0]);
         eb[0] = __builtin_fma((double)bv.y, (double)bv.y, eb[0]);
         double2 c = cdotacc(rv.x, rv.y, rv.x, rv.y, mk<double>(e[0], e[1]));
@@ -726,15 +836,19 @@ __global__ __launch_bounds__(kBlock) void k_init(int n, Geom geo, const cx<T>* _
         e[2] = __builtin_fma((double)rv.x, (double)rv.x, e[2]);
         e[2] = __builtin_fma((double)rv.y, (double)rv.y, e[2]);
     }
-    store_partials<3>(part + kPartC * kMaxGrid, rr.lb, e);
-    store_partials<1>(part + kPartI * kMaxGrid, rr.lb, eb);
+    store_sys_partials<3>(a.part + kPartC * a.stride, a.stride, q.lb, e);
+    store_sys_partials<1>(a.part + kPartI * a.stride, a.stride, q.lb, eb);
 }
 
-// ||b||, initial convergence test; iteration 1 comes next.
-__global__ __launch_bounds__(kBlock) void k_fin_init(const double* __restrict__ part, int G, SolverScal* sc) {
+// ||b||, initial convergence test, per system (one block per system); iteration 1 comes next.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_init(const BicgArgs<T> a) {
+    const int j = blockIdx.x;
+    const SysMap sm = a.smap[j];
+    SolverScal* sc = a.sc + j;
     double hb[1], hr[3];
-    head_sum<1>(part + kPartI * kMaxGrid, G, hb);
-    head_sum<3>(part + kPartC * kMaxGrid, G, hr);
+    sys_sum<1>(a.part + kPartI * a.stride, a.stride, sm.gbeg, sm.gcnt, hb);
+    sys_sum<3>(a.part + kPartC * a.stride, a.stride, sm.gbeg, sm.gcnt, hr);
     if (threadIdx.x != 0) return;
     const double bn = __builtin_sqrt(hb[0]);
     sc->bnorm = bn;
@@ -746,23 +860,35 @@ __global__ __launch_bounds__(kBlock) void k_fin_init(const double* __restrict__ 
     sc->pending = 0;
     sc->status = ST_NOT_CONVERGED;
     sc->alpha = sc->omega = sc->beta = mk<double>(1.0, 0.0);
-    if (!__builtin_isfinite(bn) || !__builtin_isfinite(hr[2])) return finish(sc, ST_NONFINITE, 0);
+    if (!__builtin_isfinite(bn) || !__builtin_isfinite(hr[2])) return finish(sc, a.ndone, ST_NONFINITE, 0);
     if (bn == 0.0) {
         sc->zero_x = 1;
         sc->relres = 0.0;
-        return finish(sc, ST_OK, 0);
+        return finish(sc, a.ndone, ST_OK, 0);
     }
     const double rel = __builtin_sqrt(hr[2]) / bn;
     sc->relres = rel;
-    if (rel <= sc->rtol) finish(sc, ST_OK, 0);
-    else if (sc->maxiter <= 0) finish(sc, ST_NOT_CONVERGED, 0);
+    if (rel <= sc->rtol) finish(sc, a.ndone, ST_OK, 0);
+    else if (sc->maxiter <= 0) finish(sc, a.ndone, ST_NOT_CONVERGED, 0);
 }
 
-// relres_true = sqrt(sum of region I) / ||b||
-__global__ __launch_bounds__(kBlock) void k_fin_true(const double* __restrict__ part, int G, SolverScal* sc) {
+// relres_true = sqrt(region I over the system) / ||b||, one block per system
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fin_true(const BicgArgs<T> a) {
+    const int j = blockIdx.x;
+    const SysMap sm = a.smap[j];
     double h[1];
-    head_sum<1>(part + kPartI * kMaxGrid, G, h);
+    sys_sum<1>(a.part + kPartI * a.stride, a.stride, sm.gbeg, sm.gcnt, h);
+    SolverScal* sc = a.sc + j;
     if (threadIdx.x == 0) sc->relres_true = sc->bnorm > 0.0 ? __builtin_sqrt(h[0]) / sc->bnorm : 0.0;
+}
+
+// x = 0 on the rows of systems whose right-hand side is zero
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zero_if(const BicgArgs<T> a) {
+    const SysBlock q = sys_block(a);
+    if (q.sys < 0 || !a.sc[q.sys].zero_x) return;
+    for (int64_t i = q.r0 + threadIdx.x; i < q.r1; i += kBlock) a.x[i] = mk<T>(T(0), T(0));
 }
 
 // ------------------------------------------------------------------ Jacobi folding: A D^{-1}
@@ -809,12 +935,6 @@ __global__ __launch_bounds__(kBlock) void k_diag_apply(int n, const cx<T>* __res
     x[i] = cmul<T>(d, x[i]);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_zero_if(int n, const SolverScal* sc, cx<T>* __restrict__ x) {
-    if (!sc->zero_x) return;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) x[i] = mk<T>(T(0), T(0));
-}
 
 // ------------------------------------------------------------------ standalone BLAS-1
 
@@ -923,17 +1043,24 @@ __global__ __launch_bounds__(kBlock) void k_fin_outer(const double* __restrict__
     if (threadIdx.x != 0) return;
     const double rn = __builtin_sqrt(s[0]), bn = sc->bnorm;
     sc->outer_rn = rn;
-    if (!__builtin_isfinite(rn) || !__builtin_isfinite(bn)) return finish(sc, ST_NONFINITE, outer);
-    if (bn == 0.0) {
+    int st = -1;
+    if (!__builtin_isfinite(rn) || !__builtin_isfinite(bn)) st = ST_NONFINITE;
+    else if (bn == 0.0) {
         sc->zero_x = 1;
         sc->relres = 0.0;
-        return finish(sc, ST_OK, outer);
+        st = ST_OK;
+    } else {
+        const double rel = rn / bn;
+        sc->relres = rel;
+        sc->relres_true = rel;
+        if (rel <= sc->rtol) st = ST_OK;
+        else if (outer >= max_outer) st = ST_NOT_CONVERGED;
     }
-    const double rel = rn / bn;
-    sc->relres = rel;
-    sc->relres_true = rel;
-    if (rel <= sc->rtol) return finish(sc, ST_OK, outer);
-    if (outer >= max_outer) return finish(sc, ST_NOT_CONVERGED, outer);
+    if (st >= 0) {
+        sc->status = st;
+        sc->iters = outer;
+        sc->done = 1;
+    }
 }
 
 // b32 = complex64(r / ||r||)

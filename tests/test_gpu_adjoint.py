@@ -1,0 +1,197 @@
+"""GPU parity of the adjoint (backward) path.
+
+References: dense LAPACK solves of A x = b and A^H lambda = g on small systems,
+the oracle's entry-gradient formula, and central finite differences of the
+loss with exact (sparse LU) or GPU forward solves.  The loss is
+L = sum_r |x_r - t_r|^2 over seeded receivers; gradients follow torch's
+real-pair convention (dL/dRe + i dL/dIm).
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hz():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2112_06465_amd as hz
+
+    return hz
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def dev_csr(A):
+    return dev(A.row_ptr), dev(A.col_idx), dev(A.vals)
+
+
+def cn(rng, n):
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def _loss_np(x, rec, t):
+    return float(np.sum(np.abs(x[rec] - t) ** 2))
+
+
+def dense_reference(A, x, g):
+    D = O.to_dense(A)
+    lam = np.linalg.solve(D.conj().T, g)
+    rows = A.row_of_entry()
+    return lam, -lam[rows] * np.conj(x[A.col_idx])
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_adjoint_matches_dense_both_paths(hz, jacobi):
+    A, b, _ = W.config_cube(6, seed=5)
+    rng = np.random.default_rng(0)
+    g = cn(rng, A.n)
+    x = np.linalg.solve(O.to_dense(A), b)
+    lam_d, gv_d = dense_reference(A, x, g)
+    rp, ci, v = dev_csr(A)
+    base = hz.PRECOND_JACOBI if jacobi else hz.PRECOND_NONE
+    for flags in (base | hz.SYMMETRIC, base):
+        lam, gv, info = hz.zbicgstab_adjoint(rp, ci, v, dev(x), dev(g), rtol=1e-12, flags=flags)
+        assert info["status"] == hz.OK, info
+        lam, gv = lam.cpu().numpy(), gv.cpu().numpy()
+        assert np.linalg.norm(lam - lam_d) / np.linalg.norm(lam_d) < 1e-9
+        assert np.linalg.norm(gv - gv_d) / np.linalg.norm(gv_d) < 1e-9
+
+
+def test_adjoint_nonsymmetric_uses_explicit_transpose(hz):
+    A, b, _ = W.config_cube(7, seed=6)
+    A = A.with_vals(A.vals + 0.2j * np.sin(np.arange(A.nnz)))  # A != A^T
+    D = O.to_dense(A)
+    assert np.abs(D - D.T).max() > 0.1
+    rng = np.random.default_rng(1)
+    g = cn(rng, A.n)
+    x = np.linalg.solve(D, b)
+    lam_d, gv_d = dense_reference(A, x, g)
+    rp, ci, v = dev_csr(A)
+    lam, gv, info = hz.zbicgstab_adjoint(rp, ci, v, dev(x), dev(g), rtol=1e-12, flags=hz.PRECOND_JACOBI)
+    assert info["status"] == hz.OK
+    assert np.linalg.norm(lam.cpu().numpy() - lam_d) / np.linalg.norm(lam_d) < 1e-9
+    assert np.linalg.norm(gv.cpu().numpy() - gv_d) / np.linalg.norm(gv_d) < 1e-9
+    # asserting symmetry for a non-symmetric matrix gives the wrong answer: the flag is the caller's promise
+    lam_s, _, _ = hz.zbicgstab_adjoint(rp, ci, v, dev(x), dev(g), rtol=1e-12, flags=hz.PRECOND_JACOBI | hz.SYMMETRIC)
+    assert np.linalg.norm(lam_s.cpu().numpy() - lam_d) / np.linalg.norm(lam_d) > 1e-3
+
+
+def test_grad_vals_kernel_matches_oracle(hz):
+    A, _, _ = W.config_cylinder(h=0.1, k=8.0)
+    rng = np.random.default_rng(2)
+    lam, x = cn(rng, A.n), cn(rng, A.n)
+    gv = hz.csr_zgrad_vals(dev(A.row_ptr), dev(A.col_idx), dev(lam), dev(x)).cpu().numpy()
+    ref = O.zgrad_vals(A, lam, x)
+    assert np.all(np.abs(gv - ref) <= 4 * np.finfo(float).eps * np.abs(lam[A.row_of_entry()]) * np.abs(x[A.col_idx]))
+
+
+def test_rect_spmv_matches_scipy(hz):
+    rng = np.random.default_rng(3)
+    M = sp.random(300, 1700, density=0.01, random_state=4, format="csr") * (1 + 2j)
+    M.sort_indices()
+    x = cn(rng, 1700)
+    y = hz.csr_zspmv_rect(dev(M.indptr.astype(np.int32)), dev(M.indices.astype(np.int32)), dev(M.data), dev(x))
+    ref = M @ x
+    assert np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-14
+
+
+def test_autograd_matches_dense_reference(hz):
+    A, b, _ = W.config_cube(6, seed=8)
+    rng = np.random.default_rng(4)
+    rec = rng.choice(A.n, 30, replace=False)
+    t = cn(rng, 30)
+    rp, ci, _ = dev_csr(A)
+    vals = dev(A.vals).requires_grad_(True)
+    bt = dev(b).requires_grad_(True)
+    x = hz.helmholtz_solve(rp, ci, vals, bt, hz.SolveOptions(rtol=1e-12, symmetric=True))
+    loss = ((x[dev(rec)] - dev(t)).abs() ** 2).sum()
+    loss.backward()
+    xd = np.linalg.solve(O.to_dense(A), b)
+    g = np.zeros(A.n, complex)
+    g[rec] = 2 * (xd[rec] - t)
+    lam_d, gv_d = dense_reference(A, xd, g)
+    assert np.linalg.norm(bt.grad.cpu().numpy() - lam_d) / np.linalg.norm(lam_d) < 1e-8
+    assert np.linalg.norm(vals.grad.cpu().numpy() - gv_d) / np.linalg.norm(gv_d) < 1e-8
+
+
+def test_source_amplitude_gradient_full_cylinder(hz):
+    """Gradients w.r.t. 50 source amplitudes on the full cylinder (1000 receivers) by one adjoint solve.
+
+    Reference by a different route: with x = A^{-1} b, b = sum_s a_s e_s, the
+    real-pair gradient is dL/da_s = 2 (A^{-1} e_s)^H g, g = (x - t) on the
+    receivers; each column A^{-1} e_s is a forward solve.
+    """
+    A, cfg = W.config_adjoint()
+    rec, t, src, amps = cfg["receivers"], cfg["targets"], cfg["sources"], cfg["amps"]
+    rp, ci, vals = dev_csr(A)
+    opts = hz.SolveOptions(rtol=1e-11, symmetric=True, jacobi=True)
+    a = dev(amps).requires_grad_(True)
+    b = torch.zeros(A.n, dtype=torch.complex128, device="cuda:0").index_add(0, dev(src), a)
+    x = hz.helmholtz_solve(rp, ci, vals, b, opts)
+    loss = ((x[dev(rec)] - dev(t)).abs() ** 2).sum()
+    loss.backward()
+    grad = a.grad.cpu().numpy()
+    xr = x.detach().cpu().numpy()[rec] - t
+    for s in (0, 17, 49):
+        e = np.zeros(A.n, complex)
+        e[src[s]] = 1.0
+        y, info = hz.zbicgstab_solve(rp, ci, vals, dev(e), rtol=1e-11, flags=hz.PRECOND_JACOBI)
+        assert info["status"] == hz.OK
+        ref = 2.0 * np.vdot(y.cpu().numpy()[rec], xr)
+        assert abs(ref - grad[s]) <= 1e-6 * abs(grad).max(), (s, ref, grad[s])
+    # the loss itself, recomputed on the host from the GPU solution
+    assert abs(loss.item() - _loss_np(x.detach().cpu().numpy(), rec, t)) <= 1e-12 * loss.item()
+
+
+def _splu_loss(A_sp, b, rec, t):
+    return _loss_np(spla.splu(A_sp.tocsc()).solve(b), rec, t)
+
+
+@pytest.mark.parametrize("case", ["cube", "cylinder"])
+def test_impedance_gradient_matches_finite_differences(hz, case):
+    """dL/dbeta for per-node impedance coefficients through entry_map + one adjoint solve."""
+    if case == "cube":
+        A, b, _ = W.config_cube(20)
+        m = W.cube_impedance_map(A)
+    else:
+        A, b, info = W.config_cylinder(h=0.1, k=8.0, seed=3, with_parts=True)
+        m = W.fem_impedance_map(A, info["parts"]["tris"], A.meta["coords"], 8.0)
+    rp_, ci_, v_ = m["phi"]
+    Phi = sp.csr_matrix((v_, ci_, rp_), shape=m["shape"])
+    vals_rest = A.vals - Phi @ np.ones(A.n)
+    rng = np.random.default_rng(9)
+    rec = rng.choice(A.n, 200, replace=False)
+    t = cn(rng, 200) * 0.01
+    phi = tuple(dev(a) for a in m["phi"])
+    phi_h = tuple(dev(a) for a in m["phi_h"])
+    beta = torch.ones(A.n, dtype=torch.complex128, device="cuda:0", requires_grad=True)
+    vals = hz.entry_map(beta, dev(vals_rest), phi, phi_h)
+    rp, ci = dev(A.row_ptr), dev(A.col_idx)
+    x = hz.helmholtz_solve(rp, ci, vals, dev(b), hz.SolveOptions(rtol=1e-12, symmetric=True))
+    loss = ((x[dev(rec)] - dev(t)).abs() ** 2).sum()
+    loss.backward()
+    grad = beta.grad.cpu().numpy()
+    boundary = np.flatnonzero(np.asarray(Phi.sum(axis=0)).ravel() != 0)
+    assert np.all(grad[np.setdiff1d(np.arange(A.n), boundary)] == 0)
+    eps = 1e-6
+    for mnode in rng.choice(boundary, 6, replace=False):
+        vals_fd = []
+        for d in (eps, -eps, 1j * eps, -1j * eps):
+            bb = np.ones(A.n, complex)
+            bb[mnode] += d
+            Ab = sp.csr_matrix((vals_rest + Phi @ bb, A.col_idx, A.row_ptr), shape=(A.n, A.n))
+            vals_fd.append(_splu_loss(Ab, b, rec, t))
+        fd = (vals_fd[0] - vals_fd[1]) / (2 * eps) + 1j * (vals_fd[2] - vals_fd[3]) / (2 * eps)
+        # relative agreement, plus the rounding noise of a central difference of four loss values
+        noise = 10 * np.finfo(float).eps * loss.item() / eps
+        assert abs(fd - grad[mnode]) <= 1e-5 * abs(grad[mnode]) + noise, (mnode, fd, grad[mnode], noise)

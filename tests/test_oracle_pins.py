@@ -308,3 +308,33 @@ def test_entry_gradient_matches_central_differences():
             vals.append(_loss(np.linalg.solve(Dp, b), rec, t))
         fd = (vals[0] - vals[1]) / (2 * eps) + 1j * (vals[2] - vals[3]) / (2 * eps)
         assert abs(fd - gv[p]) <= 1e-5 * max(1e-3, abs(gv[p])), (p, fd, gv[p])
+
+
+def test_bicgstab_first_step_defining_properties():
+    """One BiCGStab step from x0 = 0 (no preconditioner): with rhat = r0 = b and p = b,
+    alpha makes s = b - alpha A b orthogonal to rhat (the bi-orthogonality condition) and
+    omega minimises ||s - omega t|| (t = A s), so r1 = s - omega t is orthogonal to t.
+    x1 = alpha b + omega s is then the oracle's iterate after maxiter = 1."""
+    rng = np.random.default_rng(12)
+    n = 6
+    D = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 4 * np.eye(n)
+    rows, cols = np.nonzero(np.ones((n, n)))
+    A = CSR(np.arange(0, n * n + 1, n, dtype=np.int32), cols.astype(np.int32), D[rows, cols].astype(complex))
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x1, info = O.zbicgstab(A, b, tol=1e-15, maxiter=1)
+    assert info["status"] == O.NOT_CONVERGED and info["iterations"] == 1
+    r1 = b - D @ x1
+    # the iterate lies in span{b, A b}; recover alpha and omega from it without the oracle's formulas
+    Ab = D @ b
+    # x1 = alpha b + omega (b - alpha A b) = (alpha + omega) b - alpha omega A b
+    coef, *_ = np.linalg.lstsq(np.stack([b, Ab], axis=1), x1, rcond=None)
+    assert np.linalg.norm(np.stack([b, Ab], axis=1) @ coef - x1) <= 1e-12 * np.linalg.norm(x1)
+    # alpha from the bi-orthogonality condition <b, b - alpha A b> = 0
+    alpha = np.vdot(b, b) / np.vdot(b, Ab)
+    s = b - alpha * Ab
+    assert abs(np.vdot(b, s)) <= 1e-12 * np.linalg.norm(b) * np.linalg.norm(s)
+    t = D @ s
+    assert abs(np.vdot(t, r1)) <= 1e-12 * np.linalg.norm(t) * np.linalg.norm(r1)
+    # and r1 is the least-squares residual of s on t
+    w_ls = np.vdot(t, s) / np.vdot(t, t)
+    assert np.linalg.norm(r1 - (s - w_ls * t)) <= 1e-12 * np.linalg.norm(s)

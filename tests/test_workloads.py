@@ -100,3 +100,22 @@ def test_freq_sweep_shares_pattern():
 def test_cube_batch_sizes():
     systems, info = W.config_cube_batch(B=4, nmin=4, nmax=7)
     assert [A.n for A, _ in systems] == [N**3 for N in info["Ns"]]
+
+
+def test_impedance_maps_reproduce_boundary_terms():
+    """Phi beta with beta = 1 equals the impedance part of the assembled matrix."""
+    A, _, _ = W.config_cube(8)
+    m = W.cube_impedance_map(A)
+    rp, ci, v = m["phi"]
+    Phi = sp.csr_matrix((v, ci, rp), shape=m["shape"])
+    d = Phi @ np.ones(A.n)
+    assert np.array_equal(d.imag != 0, np.isin(np.arange(A.nnz), W.entry_positions(A, A.meta["boundary_rows"], A.meta["boundary_rows"])))
+    assert np.allclose(d[d != 0], 1j * A.meta["k"] * A.meta["h"])
+    A, _, info = W.config_cylinder(h=0.25, k=3.0, with_parts=True)
+    asm = info["parts"]
+    m = W.fem_impedance_map(A, asm["tris"], A.meta["coords"], 3.0)
+    rp, ci, v = m["phi"]
+    Phi = sp.csr_matrix((v, ci, rp), shape=m["shape"])
+    assert np.max(np.abs(Phi @ np.ones(A.n) - 1j * 3.0 * asm["B"])) < 1e-15
+    rp2, ci2, v2 = m["phi_h"]
+    assert abs(sp.csr_matrix((v2, ci2, rp2), shape=(A.n, A.nnz)) - Phi.conj().T).max() == 0

@@ -17,6 +17,7 @@ from .csr import CSR
 from .rng import cn_vector, make_rng
 from .cube import helmholtz_cube, cube_wavenumber
 from .fem import kuhn_mesh, assemble_helmholtz_p1, cylinder_mesh, cabin_mesh
+from .impedance import cube_impedance_map, fem_impedance_map, entry_positions
 from .configs import (
     csr_example,
     config_cube,
@@ -39,6 +40,9 @@ __all__ = [
     "assemble_helmholtz_p1",
     "cylinder_mesh",
     "cabin_mesh",
+    "cube_impedance_map",
+    "fem_impedance_map",
+    "entry_positions",
     "csr_example",
     "config_cube",
     "config_cylinder",
