@@ -1,0 +1,86 @@
+"""The oracle's pins catch plausible mistakes planted in a scratch copy of the oracle (CPU only).
+
+Each mutant copies oracle/, workloads/ and the pin tests into a temporary
+directory, changes one line of the C oracle, and runs the pins there: they
+must fail.  The repository's own oracle is never modified.
+"""
+
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = {
+    "dot_without_conjugation": (
+        "krylov.c",
+        "static CPLX cmulc(CPLX a, CPLX b) { return cmk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re); }",
+        "static CPLX cmulc(CPLX a, CPLX b) { return cmk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }",
+    ),
+    "complex_product_sign": (
+        "krylov.c",
+        "return cmk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }",
+        "return cmk(a.re * b.re + a.im * b.im, a.re * b.im + a.im * b.re); }",
+    ),
+    "spmv_wrong_operand_index": (
+        "krylov.c",
+        "acc = cadd(acc, cmul(vals[p], x[col_idx[p]]));",
+        "acc = cadd(acc, cmul(vals[p], x[i]));",
+    ),
+    "beta_ratio_inverted": (
+        "krylov.c",
+        "CPLX beta = cmul(cdiv(rho, rho_prev), cdiv(alpha, omega));",
+        "CPLX beta = cmul(cdiv(rho_prev, rho), cdiv(alpha, omega));",
+    ),
+    "half_step_drops_update": (
+        "krylov.c",
+        "                x[i] = cadd(x[i], cmul(alpha, phat[i]));\n            status = OR_OK;",
+        "                x[i] = x[i];\n            status = OR_OK;",
+    ),
+    "omega_conjugated": (
+        "krylov.c",
+        "omega = cdiv(FN(dotc)(n, t, s), tt);",
+        "omega = cdiv(FN(dotc)(n, s, t), tt);",
+    ),
+    "axpy_drops_y": ("krylov.c", "y[i] = cadd(cmul(alpha, x[i]), y[i]);", "y[i] = cmul(alpha, x[i]);"),
+    "norm_drops_imaginary": ("krylov.c", "acc += x[i].re * x[i].re + x[i].im * x[i].im;", "acc += x[i].re * x[i].re;"),
+    "jacobi_not_inverted": ("krylov.c", "dinv[i] = cdiv(cmk(1, 0), d);", "dinv[i] = d;"),
+    "gradient_without_conjugation": (
+        "refine.c",
+        "grad_vals[p].re = -(l.re * xc.re + l.im * xc.im);\n            grad_vals[p].im = -(l.im * xc.re - l.re * xc.im);",
+        "grad_vals[p].re = -(l.re * xc.re - l.im * xc.im);\n            grad_vals[p].im = -(l.im * xc.re + l.re * xc.im);",
+    ),
+    "transpose_without_conjugation": ("refine.c", "t_vals[q].im = -vals[p].im;", "t_vals[q].im = vals[p].im;"),
+    "refinement_drops_scale": (
+        "refine.c",
+        "x[i].re = x[i].re + rn * (double)d32[i].re;",
+        "x[i].re = x[i].re + (double)d32[i].re;",
+    ),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    fname, old, new = MUTANTS[name]
+    work = tmp_path / "repo"
+    work.mkdir()
+    for d in ("oracle", "workloads", "tests"):
+        shutil.copytree(os.path.join(ROOT, d), work / d, ignore=shutil.ignore_patterns("*.so", "__pycache__"))
+    src = work / "oracle" / fname
+    text = src.read_text()
+    assert old in text, "mutation site moved: update the mutant"
+    src.write_text(text.replace(old, new))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run(
+        [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "tests/test_oracle_pins.py"],
+        cwd=work,
+        capture_output=True,
+        text=True,
+        timeout=600,
+        env=env,
+    )
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
