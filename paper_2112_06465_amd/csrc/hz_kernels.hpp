@@ -247,6 +247,48 @@ __device__ __forceinline__ cx<T> row_partial(int beg, int end, int lane, const i
     return acc;
 }
 
+// Row loop of a block: rows r0 + g, r0 + g + RPS, ... (g = thread / L).  With
+// PF the next step's row_ptr pair is loaded before the current row's product,
+// so that load's latency overlaps the current step (two more live registers;
+// kernels whose column functor gathers several vectors leave it off to stay
+// within 64 VGPRs).  epi(row, total) runs in lane 0 of each row's group after
+// the group sum.  The trip count is uniform across the block.
+template <typename T, int L, int U, bool PF = true, typename Op, typename Epi>
+__device__ __forceinline__ void for_rows(int64_t r0, int64_t r1, const int* __restrict__ rp,
+                                         const int* __restrict__ ci, const cx<T>* __restrict__ vals, Op op, Epi epi) {
+    constexpr int RPS = kBlock / L;
+    const int g = threadIdx.x / L, lane = threadIdx.x % L;
+    int64_t row = r0 + g;
+    int beg = 0, end = 0;
+    if (row < r1) {
+        beg = rp[row];
+        end = rp[row + 1];
+    }
+    for (int64_t base = r0; base < r1; base += RPS) {
+        const int64_t nrow = row + RPS;
+        int nbeg = 0, nend = 0;
+        if (PF && nrow < r1) {
+            nbeg = rp[nrow];
+            nend = rp[nrow + 1];
+        }
+        const bool ok = row < r1;
+        if (!PF && ok && base != r0) {
+            beg = rp[row];
+            end = rp[row + 1];
+        }
+        cx<T> acc = mk<T>(T(0), T(0));
+        if (ok) acc = row_partial<T, L, U>(beg, end, lane, ci, vals, op);
+        acc.x = group_sum<L>(acc.x);
+        acc.y = group_sum<L>(acc.y);
+        if (ok && lane == 0) epi(row, acc);
+        row = nrow;
+        if (PF) {
+            beg = nbeg;
+            end = nend;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ solver scalars (device resident)
 
 // One block per system.  Written only by thread 0 of the system's first
@@ -406,30 +448,20 @@ template <typename T> struct SpmvArgs {
 
 template <typename T, int L, int U, int EPI>
 __global__ HZ_STREAM_BOUNDS void k_spmv(const SpmvArgs<T> a) {
-    constexpr int RPS = kBlock / L;
     const RowRange rr = rows_of_block(a.n, a.geo);
-    const int g = threadIdx.x / L, lane = threadIdx.x % L;
     const cx<T>* __restrict__ xv = a.x;
     auto op = [xv](int c) { return xv[c]; };
     double e[1] = {0.0};
-    for (int64_t base = rr.r0; base < rr.r1; base += RPS) {  // uniform trip count in the block
-        const int64_t row = base + g;
-        const bool ok = row < rr.r1;
-        cx<T> acc = mk<T>(T(0), T(0));
-        if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, op);
-        acc.x = group_sum<L>(acc.x);
-        acc.y = group_sum<L>(acc.y);
-        if (ok && lane == 0) {
-            if constexpr (EPI == EPI_RESID) {
-                const cx<T> bw = a.w[row];
-                acc.x = bw.x - acc.x;
-                acc.y = bw.y - acc.y;
-                e[0] = __builtin_fma((double)acc.x, (double)acc.x, e[0]);
-                e[0] = __builtin_fma((double)acc.y, (double)acc.y, e[0]);
-            }
-            a.y[row] = acc;
+    for_rows<T, L, U>(rr.r0, rr.r1, a.row_ptr, a.col_idx, a.vals, op, [&](int64_t row, cx<T> acc) {
+        if constexpr (EPI == EPI_RESID) {
+            const cx<T> bw = a.w[row];
+            acc.x = bw.x - acc.x;
+            acc.y = bw.y - acc.y;
+            e[0] = __builtin_fma((double)acc.x, (double)acc.x, e[0]);
+            e[0] = __builtin_fma((double)acc.y, (double)acc.y, e[0]);
         }
-    }
+        a.y[row] = acc;
+    });
     if constexpr (EPI == EPI_RESID) store_partials<1>(a.part, rr.lb, e);
 }
 
@@ -440,26 +472,16 @@ __global__ HZ_STREAM_BOUNDS void k_sys_resid(const BicgArgs<T> a, const cx<T>* _
                                              const cx<T>* __restrict__ xin, cx<T>* __restrict__ y) {
     const SysBlock q = sys_block(a);
     if (q.sys < 0) return;
-    constexpr int RPS = kBlock / L;
-    const int g = threadIdx.x / L, lane = threadIdx.x % L;
     auto op = [xin](int c) { return xin[c]; };
     double e[1] = {0.0};
-    for (int64_t base = q.r0; base < q.r1; base += RPS) {
-        const int64_t row = base + g;
-        const bool ok = row < q.r1;
-        cx<T> acc = mk<T>(T(0), T(0));
-        if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, vals, op);
-        acc.x = group_sum<L>(acc.x);
-        acc.y = group_sum<L>(acc.y);
-        if (ok && lane == 0) {
-            const cx<T> bw = a.b[row];
-            acc.x = bw.x - acc.x;
-            acc.y = bw.y - acc.y;
-            e[0] = __builtin_fma((double)acc.x, (double)acc.x, e[0]);
-            e[0] = __builtin_fma((double)acc.y, (double)acc.y, e[0]);
-            y[row] = acc;
-        }
-    }
+    for_rows<T, L, U>(q.r0, q.r1, a.row_ptr, a.col_idx, vals, op, [&](int64_t row, cx<T> acc) {
+        const cx<T> bw = a.b[row];
+        acc.x = bw.x - acc.x;
+        acc.y = bw.y - acc.y;
+        e[0] = __builtin_fma((double)acc.x, (double)acc.x, e[0]);
+        e[0] = __builtin_fma((double)acc.y, (double)acc.y, e[0]);
+        y[row] = acc;
+    });
     store_sys_partials<1>(a.part + kPartI * a.stride, a.stride, q.lb, e);
 }
 
@@ -558,25 +580,15 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_A(const BicgArgs<T> a) {
         if (first) return r[c];
         return p_update<T>(false, bt, omt, r[c], pold[c], vold[c]);
     };
-    constexpr int RPS = kBlock / L;
-    const int g = threadIdx.x / L, lane = threadIdx.x % L;
     double e[2] = {0.0, 0.0};
-    for (int64_t base = q.r0; base < q.r1; base += RPS) {
-        const int64_t row = base + g;
-        const bool ok = row < q.r1;
-        cx<T> acc = mk<T>(T(0), T(0));
-        if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, pcol);
-        acc.x = group_sum<L>(acc.x);
-        acc.y = group_sum<L>(acc.y);
-        if (ok && lane == 0) {
-            pnew[row] = pcol((int)row);
-            vnew[row] = acc;
-            const cx<T> w = a.rh[row];
-            double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
-            e[0] = c.x;
-            e[1] = c.y;
-        }
-    }
+    for_rows<T, L, U, false>(q.r0, q.r1, a.row_ptr, a.col_idx, a.vals, pcol, [&](int64_t row, cx<T> acc) {
+        pnew[row] = pcol((int)row);
+        vnew[row] = acc;
+        const cx<T> w = a.rh[row];
+        double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
+        e[0] = c.x;
+        e[1] = c.y;
+    });
     store_sys_partials<2>(a.part + kPartA * a.stride, a.stride, q.lb, e);
 }
 
@@ -609,29 +621,19 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_B(const BicgArgs<T> a) {
     const cx<T>* __restrict__ r = a.r;
     const cx<T>* __restrict__ v = a.v[it & 1];
     auto scol = [=](int c) { return cfma<T>(mk<T>(-al.x, -al.y), v[c], r[c]); };
-    constexpr int RPS = kBlock / L;
-    const int g = threadIdx.x / L, lane = threadIdx.x % L;
     double e[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t base = q.r0; base < q.r1; base += RPS) {
-        const int64_t row = base + g;
-        const bool ok = row < q.r1;
-        cx<T> acc = mk<T>(T(0), T(0));
-        if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, scol);
-        acc.x = group_sum<L>(acc.x);
-        acc.y = group_sum<L>(acc.y);
-        if (ok && lane == 0) {
-            const cx<T> s = scol((int)row);
-            a.s[row] = s;
-            a.t[row] = acc;
-            e[0] = __builtin_fma((double)s.x, (double)s.x, e[0]);
-            e[0] = __builtin_fma((double)s.y, (double)s.y, e[0]);
-            double2 c = cdotacc(acc.x, acc.y, s.x, s.y, mk<double>(e[1], e[2]));
-            e[1] = c.x;
-            e[2] = c.y;
-            e[3] = __builtin_fma((double)acc.x, (double)acc.x, e[3]);
-            e[3] = __builtin_fma((double)acc.y, (double)acc.y, e[3]);
-        }
-    }
+    for_rows<T, L, U>(q.r0, q.r1, a.row_ptr, a.col_idx, a.vals, scol, [&](int64_t row, cx<T> acc) {
+        const cx<T> s = scol((int)row);
+        a.s[row] = s;
+        a.t[row] = acc;
+        e[0] = __builtin_fma((double)s.x, (double)s.x, e[0]);
+        e[0] = __builtin_fma((double)s.y, (double)s.y, e[0]);
+        double2 c = cdotacc(acc.x, acc.y, s.x, s.y, mk<double>(e[1], e[2]));
+        e[1] = c.x;
+        e[2] = c.y;
+        e[3] = __builtin_fma((double)acc.x, (double)acc.x, e[3]);
+        e[3] = __builtin_fma((double)acc.y, (double)acc.y, e[3]);
+    });
     store_sys_partials<4>(a.part + kPartB * a.stride, a.stride, q.lb, e);
 }
 
@@ -734,24 +736,14 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_A1(const BicgArgs<T> a) {
     const cx<T>* __restrict__ p = a.p[it & 1];
     cx<T>* __restrict__ v = a.v[it & 1];
     auto pcol = [p](int c) { return p[c]; };
-    constexpr int RPS = kBlock / L;
-    const int g = threadIdx.x / L, lane = threadIdx.x % L;
     double e[2] = {0.0, 0.0};
-    for (int64_t base = q.r0; base < q.r1; base += RPS) {
-        const int64_t row = base + g;
-        const bool ok = row < q.r1;
-        cx<T> acc = mk<T>(T(0), T(0));
-        if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, pcol);
-        acc.x = group_sum<L>(acc.x);
-        acc.y = group_sum<L>(acc.y);
-        if (ok && lane == 0) {
-            v[row] = acc;
-            const cx<T> w = a.rh[row];
-            double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
-            e[0] = c.x;
-            e[1] = c.y;
-        }
-    }
+    for_rows<T, L, U>(q.r0, q.r1, a.row_ptr, a.col_idx, a.vals, pcol, [&](int64_t row, cx<T> acc) {
+        v[row] = acc;
+        const cx<T> w = a.rh[row];
+        double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
+        e[0] = c.x;
+        e[1] = c.y;
+    });
     store_sys_partials<2>(a.part + kPartA * a.stride, a.stride, q.lb, e);
 }
 
@@ -780,26 +772,16 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_B1(const BicgArgs<T> a) {
     if (a.sc[q.sys].done) return;
     const cx<T>* __restrict__ sv = a.s;
     auto scol = [sv](int c) { return sv[c]; };
-    constexpr int RPS = kBlock / L;
-    const int g = threadIdx.x / L, lane = threadIdx.x % L;
     double e[3] = {0.0, 0.0, 0.0};
-    for (int64_t base = q.r0; base < q.r1; base += RPS) {
-        const int64_t row = base + g;
-        const bool ok = row < q.r1;
-        cx<T> acc = mk<T>(T(0), T(0));
-        if (ok) acc = row_partial<T, L, U>(a.row_ptr[row], a.row_ptr[row + 1], lane, a.col_idx, a.vals, scol);
-        acc.x = group_sum<L>(acc.x);
-        acc.y = group_sum<L>(acc.y);
-        if (ok && lane == 0) {
-            const cx<T> s = sv[row];
-            a.t[row] = acc;
-            double2 c = cdotacc(acc.x, acc.y, s.x, s.y, mk<double>(e[0], e[1]));
-            e[0] = c.x;
-            e[1] = c.y;
-            e[2] = __builtin_fma((double)acc.x, (double)acc.x, e[2]);
-            e[2] = __builtin_fma((double)acc.y, (double)acc.y, e[2]);
-        }
-    }
+    for_rows<T, L, U>(q.r0, q.r1, a.row_ptr, a.col_idx, a.vals, scol, [&](int64_t row, cx<T> acc) {
+        const cx<T> s = sv[row];
+        a.t[row] = acc;
+        double2 c = cdotacc(acc.x, acc.y, s.x, s.y, mk<double>(e[0], e[1]));
+        e[0] = c.x;
+        e[1] = c.y;
+        e[2] = __builtin_fma((double)acc.x, (double)acc.x, e[2]);
+        e[2] = __builtin_fma((double)acc.y, (double)acc.y, e[2]);
+    });
     store_sys_partials<3>(a.part + (kPartB + 1) * a.stride, a.stride, q.lb, e);
 }
 
