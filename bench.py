@@ -111,7 +111,7 @@ def cpu_baseline(A, b, x_spmv, budget_iters=300):
     }
 
 
-def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10):
+def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10, caller_order_too=False):
     """Wall time of a Jacobi-BiCGStab solve to tol: plain FP64 vs complex64-inner refinement."""
     import oracle as O
 
@@ -121,11 +121,16 @@ def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10):
     wsm = hz.mixed_workspace(n, nnz, flags, dev)
     x = torch.zeros_like(b)
     res = {"workload": f"{name} (n={n}, nnz={nnz})", "tol": tol}
-    for label, fn in (
+    runs = [
         ("fp64", lambda: hz.zbicgstab_solve(rp, ci, vals, b, x=x, rtol=tol, maxiter=50000, flags=flags, ws=ws)),
         ("mixed", lambda: hz.zbicgstab_solve_mixed(rp, ci, vals, b, x=x, rtol=tol, inner_rtol=1e-4, maxiter=50000,
                                                    flags=flags, ws=wsm)),
-    ):
+    ]
+    if caller_order_too:
+        # the same FP64 solve kept in the caller's numbering (no level-set renumbering)
+        runs.append(("fp64_caller_order", lambda: hz.zbicgstab_solve(rp, ci, vals, b, x=x, rtol=tol, maxiter=50000,
+                                                                     flags=flags | hz.NO_REORDER, ws=ws)))
+    for label, fn in runs:
         fn()  # warm-up (also the JIT of nothing: the library is precompiled)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -136,13 +141,125 @@ def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10):
         bh = b.cpu().numpy()
         rr = float(np.linalg.norm(bh - O.zspmv(A, xh)) / np.linalg.norm(bh))
         res[label] = {"ms": round(ms, 3), "iterations": info["iterations"], "outer_steps": info["outer_steps"],
-                      "status": info["status"], "relres_true_oracle_spmv": rr}
+                      "status": info["status"], "renumbered": info["renumbered"], "relres_true_oracle_spmv": rr}
         if label == "fp64":
             x64 = xh.copy()
         else:
             res[label]["rel_err_vs_fp64"] = float(np.linalg.norm(xh - x64) / np.linalg.norm(x64))
     res["mixed_speedup"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)
     return res
+
+
+def spmv_cabin(hz, torch, dev, A, rp, ci, vals, reps=10):
+    """zSpMV on the cabin (403 MB, beyond the Infinity Cache) in the given random numbering and in level sets."""
+    n, nnz = A.n, A.nnz
+    rng = np.random.default_rng(1)
+    x = torch.from_numpy(rng.standard_normal(n) + 1j * rng.standard_normal(n)).to(dev)
+    y = torch.empty_like(x)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+    def timed(r, c, v, xx):
+        for _ in range(2):
+            hz.csr_zspmv(r, c, v, xx, y)
+        ev[0].record()
+        for _ in range(reps):
+            hz.csr_zspmv(r, c, v, xx, y)
+        ev[1].record()
+        torch.cuda.synchronize()
+        us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+        gbs = spmv_bytes(n, nnz) / (us * 1e-6) / 1e9
+        return {"us": round(us, 2), "GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+    res = {"workload": f"cabin (n={n}, nnz={nnz}), algorithmic bytes {spmv_bytes(n, nnz)}, {reps} launches"}
+    res["given_numbering"] = timed(rp, ci, vals, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    perm, inv, level = hz.csr_level_order(rp, ci)
+    rp2, ci2, v2 = hz.csr_zpermute(rp, ci, vals, perm, inv)
+    torch.cuda.synchronize()
+    res["analysis_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+    res["levels"] = int(level.max().item()) + 1
+    res["level_sets"] = timed(rp2, ci2, v2, x[perm.long()].contiguous())
+    return res
+
+
+def blas1(hz, torch, dev, sizes=(100_000, 209_777, 1_000_000, 5_000_000, 15_000_000), reps=20):
+    """Standalone zdotc / dznrm2 / zaxpy: per-call time of back-to-back calls and algorithmic GB/s."""
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    rng = np.random.default_rng(2)
+    out = []
+    for n in sizes:
+        x = torch.from_numpy(rng.standard_normal(n) + 1j * rng.standard_normal(n)).to(dev)
+        y = torch.from_numpy(rng.standard_normal(n) + 1j * rng.standard_normal(n)).to(dev)
+        d = torch.empty((), dtype=torch.complex128, device=dev)
+        nr = torch.empty((), dtype=torch.float64, device=dev)
+        row = {"n": n}
+        for name, fn, nbytes in (
+            ("zdotc", lambda: hz.zdotc(x, y, out=d), 32 * n),
+            ("dznrm2", lambda: hz.dznrm2(x, out=nr), 16 * n),
+            ("zaxpy", lambda: hz.zaxpy(1e-9 - 1e-9j, x, y), 48 * n),
+        ):
+            for _ in range(3):
+                fn()
+            ev[0].record()
+            for _ in range(reps):
+                fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+            row[name] = {"us": round(us, 2), "GBs": round(nbytes / (us * 1e-6) / 1e9, 1)}
+        out.append(row)
+        del x, y
+    return out
+
+
+def batched_sweep(hz, torch, dev, B=64, tol=1e-10):
+    """64 wavenumbers k ~ U[10, 40] on the cylinder pattern: one shared-pattern call vs 64 sequential solves."""
+    import oracle as O
+    import workloads as W
+
+    A, vals, rhs, ks, _ = W.config_freq_sweep(B=B)
+    n, nnz = A.n, A.nnz
+    rp = torch.from_numpy(A.row_ptr).to(dev)
+    ci = torch.from_numpy(A.col_idx).to(dev)
+    V = torch.from_numpy(np.ascontiguousarray(vals.T)).to(dev)
+    Bm = torch.from_numpy(np.ascontiguousarray(rhs.T)).to(dev)
+    singles = [(torch.from_numpy(vals[j]).to(dev), torch.from_numpy(rhs[j]).to(dev)) for j in range(B)]
+    flags = hz.PRECOND_JACOBI | hz.X0_ZERO
+    X = torch.zeros_like(Bm)
+    wsb = torch.empty(hz.zbicgstab_batched_workspace_bytes(B, n, nnz, flags) + 256, dtype=torch.uint8, device=dev)
+    ws = hz.workspace(n, nnz, flags, dev)
+    xs = [torch.zeros_like(b) for _, b in singles]
+    # warm-up: two iterations of each form
+    hz.zbicgstab_solve_batched(rp, ci, V, Bm, x=X, rtol=tol, maxiter=2, flags=flags, ws=wsb)
+    hz.zbicgstab_solve(rp, ci, singles[0][0], singles[0][1], x=xs[0], rtol=tol, maxiter=2, flags=flags, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, binfo = hz.zbicgstab_solve_batched(rp, ci, V, Bm, x=X, rtol=tol, maxiter=50000, flags=flags, ws=wsb)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sinfo = [hz.zbicgstab_solve(rp, ci, v, b, x=x, rtol=tol, maxiter=50000, flags=flags, ws=ws)[1]
+             for (v, b), x in zip(singles, xs)]
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    Xh = X.cpu().numpy()
+    rr_b = max(float(np.linalg.norm(rhs[j] - O.zspmv(A.with_vals(vals[j]), Xh[:, j])) / np.linalg.norm(rhs[j]))
+               for j in range(B))
+    rr_s = max(float(np.linalg.norm(rhs[j] - O.zspmv(A.with_vals(vals[j]), xs[j].cpu().numpy()))
+                     / np.linalg.norm(rhs[j])) for j in range(B))
+    its = [i["iterations"] for i in binfo]
+    return {
+        "workload": f"{B} wavenumbers k~U[10,40] on the cylinder pattern (n={n}, nnz={nnz}), Jacobi, tol {tol:g}",
+        "batched_ms": round(t_b * 1e3, 3), "sequential_ms": round(t_s * 1e3, 3), "speedup": round(t_s / t_b, 3),
+        "iterations_min_max": [min(its), max(its)],
+        "iterations_sequential_min_max": [min(i["iterations"] for i in sinfo), max(i["iterations"] for i in sinfo)],
+        "all_ok": all(i["status"] == 0 for i in binfo) and all(i["status"] == 0 for i in sinfo),
+        "max_relres_true_oracle_spmv": {"batched": rr_b, "sequential": rr_s},
+        # each system streams its own values and vectors while it runs; indices once per iteration
+        "batched_algorithmic_GBs": round((sum(its) * (32 * nnz + 304 * n) + max(its) * (8 * nnz + 8 * n)) / t_b / 1e9,
+                                         1),
+    }
 
 
 def batched_cubes(hz, torch, dev, B=32, tol=1e-8):
@@ -167,13 +284,13 @@ def batched_cubes(hz, torch, dev, B=32, tol=1e-8):
     ro = row_off.astype(np.int32)
     xb = torch.zeros_like(bb)
     flags = hz.PRECOND_NONE | hz.X0_ZERO
-    wsb = torch.empty(hz.zbicgstab_batched_workspace_bytes(ro, nnz_off, flags) + 256, dtype=torch.uint8, device=dev)
+    wsb = torch.empty(hz.zbicgstab_varbatch_workspace_bytes(ro, nnz_off, flags) + 256, dtype=torch.uint8, device=dev)
     singles = [tuple(torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col_idx, A.vals, b)) for A, b in systems]
     wss = hz.workspace(max(A.n for A, _ in systems), max(A.nnz for A, _ in systems), flags, dev)
     xs = [torch.zeros_like(s[3]) for s in singles]
 
     def run_batched():
-        return hz.zbicgstab_solve_batched(ro, rp, ci, vv, bb, x=xb, rtol=tol, maxiter=50000, flags=flags, ws=wsb)
+        return hz.zbicgstab_solve_varbatch(ro, rp, ci, vv, bb, x=xb, rtol=tol, maxiter=50000, flags=flags, ws=wsb)
 
     def run_sequential():
         return [hz.zbicgstab_solve(*s, x=x, rtol=tol, maxiter=50000, flags=flags, ws=wss) for s, x in zip(singles, xs)]
@@ -223,6 +340,8 @@ def main():
     ap.add_argument("--no-time-to-tol", action="store_true")
     ap.add_argument("--no-cabin", action="store_true", help="skip FP64 vs mixed to 1e-10 on the cabin")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched cube solve")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 64-frequency shared-pattern batch")
+    ap.add_argument("--no-blas1", action="store_true", help="skip the standalone zdotc/dznrm2/zaxpy sizes")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -349,13 +468,17 @@ def main():
         out["time_to_tol"] = [time_to_tol(hz, torch, dev, "cylinder", rp, ci, vals, b, A)]
         if not args.no_cabin:
             Ac, bc, _ = W.config_cabin()
-            t = time_to_tol(
-                hz, torch, dev, "cabin", torch.from_numpy(Ac.row_ptr).to(dev), torch.from_numpy(Ac.col_idx).to(dev),
-                torch.from_numpy(Ac.vals).to(dev), torch.from_numpy(bc).to(dev), Ac
-            )
+            rpc, cic, vc = (torch.from_numpy(a).to(dev) for a in (Ac.row_ptr, Ac.col_idx, Ac.vals))
+            out["spmv_cabin"] = spmv_cabin(hz, torch, dev, Ac, rpc, cic, vc)
+            t = time_to_tol(hz, torch, dev, "cabin", rpc, cic, vc, torch.from_numpy(bc).to(dev), Ac,
+                            caller_order_too=True)
             out["time_to_tol"].append(t)
     if not args.no_batched:
         out["batched"] = batched_cubes(hz, torch, dev)
+    if not args.no_sweep:
+        out["batched_sweep"] = batched_sweep(hz, torch, dev)
+    if not args.no_blas1:
+        out["blas1"] = blas1(hz, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, b_np, x_np)
     print(json.dumps(out), flush=True)

@@ -60,12 +60,14 @@ enum {
 #define HZ_X0_ZERO 0x4        /* ignore x on entry, start from 0 (paper)   */
 #define HZ_VALIDATE 0x8       /* check CSR structure on the device first   */
 #define HZ_SYMMETRIC 0x10     /* caller asserts A = A^T (adjoint shortcut) */
+#define HZ_REORDER 0x20       /* always renumber by level sets first       */
+#define HZ_NO_REORDER 0x40    /* never renumber (smaller workspace)        */
 
 typedef struct {
     int status;              /* HZ_OK / HZ_NOT_CONVERGED / HZ_BREAKDOWN / HZ_NONFINITE */
     int iterations;          /* BiCGStab iterations (inner total for mixed) */
     int outer_steps;         /* refinement corrections (mixed only)         */
-    int reserved;
+    int renumbered;          /* 1 if solved in the level-set numbering      */
     double relres_recursive; /* last ||r||/||b|| of the recursive residual  */
     double relres_true;      /* ||b - A x|| / ||b||, recomputed in FP64     */
 } hz_solve_info;
@@ -102,7 +104,9 @@ int dznrm2(hz_handle *handle, hz_stream stream, int n, const hz_c128 *x, double 
 /* y <- alpha x + y (Section 5, complex axpy); alpha by value. */
 int zaxpy(hz_handle *handle, hz_stream stream, int n, hz_c128 alpha, const hz_c128 *x, hz_c128 *y);
 
-/* Device workspace (bytes) that zbicgstab_solve needs for this n, nnz, flags. */
+/* Device workspace (bytes) that zbicgstab_solve needs for this n, nnz,
+ * flags.  Unless HZ_NO_REORDER is passed it includes room for a renumbered
+ * copy of the matrix (20 nnz + 80 n bytes and sort scratch). */
 size_t zbicgstab_workspace_bytes(int n, int nnz, int flags);
 
 /*
@@ -116,33 +120,63 @@ size_t zbicgstab_workspace_bytes(int n, int nnz, int flags);
  * flags) bytes, 256-byte aligned, owned by the caller.  The call
  * synchronises `stream` and fills *info (host memory).  Returns the solver
  * status (also in info->status) or a negative error.
+ *
+ * Renumbering (not in the paper; a locality step of this library): with
+ * HZ_REORDER, or by default when more than 5 % of the entries lie more than
+ * 32,768 rows from the diagonal, the solve runs on P A P^T (P x) = P b for
+ * the level-set permutation P of csr_level_order and scatters x back.
+ * BiCGStab with Jacobi scaling is invariant under a symmetric permutation,
+ * so this changes only the rounding order.  HZ_NO_REORDER forbids it;
+ * passing both flags is HZ_ERR_INVALID.  Batched solves never renumber.
  */
 int zbicgstab_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
                     const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol, int maxiter, int flags, void *ws,
                     size_t ws_bytes, hz_solve_info *info);
 
 /*
- * Workspace (bytes) for zbicgstab_solve_batched.  row_off is a HOST array of
+ * Workspace (bytes) for zbicgstab_solve_varbatch.  row_off is a HOST array of
  * nsys+1 row offsets (row_off[0] = 0, non-decreasing).
  */
-size_t zbicgstab_batched_workspace_bytes(int nsys, const int *row_off, int nnz, int flags);
+size_t zbicgstab_varbatch_workspace_bytes(int nsys, const int *row_off, int nnz, int flags);
 
 /*
- * Solve nsys independent systems A_j x_j = b_j in one launch sequence: the
- * systems are the diagonal blocks of one block-diagonal CSR matrix (rows
- * row_off[j] .. row_off[j+1]-1 of row_ptr/col_idx/vals, GLOBAL column
- * indices inside the block), b and x are the concatenated vectors.  Every
- * system runs its own preconditioned BiCGStab (Section 7) with its own
- * scalars, convergence test and exit, exactly as zbicgstab_solve would;
- * systems that finish early stop consuming bandwidth.  infos is a HOST array
- * of nsys results.  Returns the largest status over the systems, or a
- * negative error.  Flags, stream and workspace as for zbicgstab_solve.
- * Systems on one sparsity pattern (a frequency sweep) are passed the same
- * way, with the pattern repeated per block.
+ * Solve nsys independent systems A_j x_j = b_j of uneven sizes in one launch
+ * sequence (batching is an extension of Section 7's solve): the systems are
+ * the diagonal blocks of one block-diagonal CSR matrix (rows row_off[j] ..
+ * row_off[j+1]-1 of row_ptr/col_idx/vals, GLOBAL column indices inside the
+ * block), b and x are the concatenated vectors.  Every system runs its own
+ * preconditioned BiCGStab with its own scalars, convergence test and exit,
+ * exactly as zbicgstab_solve would; systems that finish early stop consuming
+ * bandwidth.  infos is a HOST array of nsys results.  Returns the largest
+ * status over the systems, or a negative error.  Flags, stream and
+ * workspace as for zbicgstab_solve; systems are never renumbered.
  */
-int zbicgstab_solve_batched(hz_handle *handle, hz_stream stream, int nsys, const int *row_off, int nnz,
-                            const int *row_ptr, const int *col_idx, const hz_c128 *vals, const hz_c128 *b, hz_c128 *x,
-                            double rtol, int maxiter, int flags, void *ws, size_t ws_bytes, hz_solve_info *infos);
+int zbicgstab_solve_varbatch(hz_handle *handle, hz_stream stream, int nsys, const int *row_off, int nnz,
+                             const int *row_ptr, const int *col_idx, const hz_c128 *vals, const hz_c128 *b,
+                             hz_c128 *x, double rtol, int maxiter, int flags, void *ws, size_t ws_bytes,
+                             hz_solve_info *infos);
+
+/* Workspace (bytes) for zbicgstab_solve_batched: nsys systems of n rows. */
+size_t zbicgstab_batched_workspace_bytes(int nsys, int n, int nnz, int flags);
+
+/*
+ * Solve nsys systems A_j x_j = b_j that share one sparsity pattern (a
+ * frequency sweep K - k_j^2 M + i k_j B on one mesh) in one launch sequence;
+ * batching is an extension of Section 7's solve.  1 <= nsys <= 256 and
+ * n * nsys < 2^31.  Layout is system-minor: vals[p * nsys + j] is entry p
+ * of system j (nnz * nsys values), b[i * nsys + j] and x[i * nsys + j]
+ * element i of system j.  Every system runs its own preconditioned BiCGStab
+ * (HZ_PRECOND_JACOBI scales each system by its own diagonal) with its own
+ * scalars, convergence test and exit; a system's arithmetic does not depend
+ * on the others, so permuting the systems permutes the results bitwise.
+ * row_ptr/col_idx are read once per row for all systems.  infos is a HOST
+ * array of nsys results; returns the largest status or a negative error.
+ * Flags (HZ_X0_ZERO, HZ_VALIDATE, HZ_PRECOND_JACOBI), stream and workspace
+ * as for zbicgstab_solve; systems are never renumbered.
+ */
+int zbicgstab_solve_batched(hz_handle *handle, hz_stream stream, int nsys, int n, int nnz, const int *row_ptr,
+                            const int *col_idx, const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol,
+                            int maxiter, int flags, void *ws, size_t ws_bytes, hz_solve_info *infos);
 
 /* Device workspace (bytes) that zbicgstab_solve_mixed needs. */
 size_t zbicgstab_mixed_workspace_bytes(int n, int nnz, int flags);
@@ -158,8 +192,8 @@ size_t zbicgstab_mixed_workspace_bytes(int n, int nnz, int flags);
  * (Krylov scalars and reductions in FP64).  At most max_outer corrections,
  * each of at most maxiter inner iterations.  info->iterations is the total
  * of inner iterations, info->outer_steps the number of corrections, and
- * info->relres_true the final FP64 residual.  Workspace, stream, x and
- * status conventions as for zbicgstab_solve.
+ * info->relres_true the final FP64 residual.  Workspace, stream, x,
+ * renumbering and status conventions as for zbicgstab_solve.
  */
 int zbicgstab_solve_mixed(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr,
                           const int *col_idx, const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol,
@@ -203,6 +237,38 @@ int zbicgstab_adjoint(hz_handle *handle, hz_stream stream, int n, int nnz, const
                       const hz_c128 *vals, const hz_c128 *x, const hz_c128 *grad_x, hz_c128 *grad_b,
                       hz_c128 *grad_vals, double rtol, int maxiter, int flags, void *ws, size_t ws_bytes,
                       hz_solve_info *info);
+
+/* Device workspace (bytes) for csr_level_order and csr_zpermute. */
+size_t csr_reorder_workspace_bytes(int n, int nnz);
+
+/*
+ * Level-set (breadth-first) ordering of the pattern, a locality analysis of
+ * this library (the paper stores matrices in the order they come, Section
+ * 3.2).  A first search from node 0 picks the smallest index on its deepest
+ * level as start; a second search from there gives each node its level
+ * (distance in the graph of row i -> col_idx entries); perm[k] is the
+ * caller's index of the k-th node in (level, caller's index) order, nodes
+ * the search does not reach last in index order; inv[perm[k]] = k.  level
+ * (nullable, n ints) receives the levels of the second search, -1 where
+ * unreached.  All outputs are device arrays of n ints owned by the caller;
+ * the result is a pure function of row_ptr/col_idx.  ws as returned by
+ * csr_reorder_workspace_bytes, 256-byte aligned.  Synchronises the stream.
+ */
+int csr_level_order(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+                    int *perm, int *inv, int *level, void *ws, size_t ws_bytes);
+
+/*
+ * B = P A P^T for the permutation perm (new -> old) with inverse inv: row k
+ * of B is row perm[k] of A with every column c renumbered inv[c], columns
+ * sorted within each row, values carried along.  Outputs row_ptr_out
+ * (n+1), col_idx_out (nnz), vals_out (nnz) are caller-owned device arrays
+ * that must not overlap the inputs.  Returns HZ_ERR_INVALID unless perm is
+ * a permutation of 0..n-1 and inv its inverse (checked on the device).
+ * ws as for csr_level_order.  Synchronises the stream.
+ */
+int csr_zpermute(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+                 const hz_c128 *vals, const int *perm, const int *inv, int *row_ptr_out, int *col_idx_out,
+                 hz_c128 *vals_out, void *ws, size_t ws_bytes);
 
 #ifdef __cplusplus
 }

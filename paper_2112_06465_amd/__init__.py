@@ -11,10 +11,15 @@ from .binding import (  # noqa: F401
     OK,
     PRECOND_JACOBI,
     PRECOND_NONE,
+    NO_REORDER,
+    REORDER,
     SYMMETRIC,
     VALIDATE,
     X0_ZERO,
     csr_cspmv,
+    csr_level_order,
+    csr_reorder_workspace_bytes,
+    csr_zpermute,
     csr_zgrad_vals,
     csr_zspmv,
     csr_zspmv_rect,
@@ -29,6 +34,8 @@ from .binding import (  # noqa: F401
     zbicgstab_adjoint,
     zbicgstab_batched_workspace_bytes,
     zbicgstab_solve_batched,
+    zbicgstab_varbatch_workspace_bytes,
+    zbicgstab_solve_varbatch,
     zbicgstab_adjoint_workspace_bytes,
     zbicgstab_workspace_bytes,
     zdotc,

@@ -22,7 +22,7 @@ class HzInfo(C.Structure):
         ("status", C.c_int),
         ("iterations", C.c_int),
         ("outer_steps", C.c_int),
-        ("reserved", C.c_int),
+        ("renumbered", C.c_int),
         ("relres_recursive", C.c_double),
         ("relres_true", C.c_double),
     ]
@@ -32,6 +32,7 @@ class HzInfo(C.Structure):
             "status": self.status,
             "iterations": self.iterations,
             "outer_steps": self.outer_steps,
+            "renumbered": self.renumbered,
             "relres_recursive": self.relres_recursive,
             "relres_true": self.relres_true,
         }
@@ -55,13 +56,18 @@ SIGNATURES = {
     "zbicgstab_workspace_bytes": (SZ, [I, I, I]),
     "zbicgstab_solve": (I, [P, P, I, I, P, P, P, P, P, D, I, I, P, SZ, C.POINTER(HzInfo)]),
     "zbicgstab_mixed_workspace_bytes": (SZ, [I, I, I]),
-    "zbicgstab_batched_workspace_bytes": (SZ, [I, P, I, I]),
-    "zbicgstab_solve_batched": (I, [P, P, I, P, I, P, P, P, P, P, D, I, I, P, SZ, P]),
+    "zbicgstab_varbatch_workspace_bytes": (SZ, [I, P, I, I]),
+    "zbicgstab_solve_varbatch": (I, [P, P, I, P, I, P, P, P, P, P, D, I, I, P, SZ, P]),
+    "zbicgstab_batched_workspace_bytes": (SZ, [I, I, I, I]),
+    "zbicgstab_solve_batched": (I, [P, P, I, I, I, P, P, P, P, P, D, I, I, P, SZ, P]),
     "csr_zspmv_rect": (I, [P, P, I, I, I, P, P, P, P, P]),
     "csr_zgrad_vals": (I, [P, P, I, I, P, P, P, P, P]),
     "zbicgstab_adjoint_workspace_bytes": (SZ, [I, I, I]),
     "zbicgstab_adjoint": (I, [P, P, I, I, P, P, P, P, P, P, P, D, I, I, P, SZ, C.POINTER(HzInfo)]),
     "zbicgstab_solve_mixed": (I, [P, P, I, I, P, P, P, P, P, D, D, I, I, I, P, SZ, C.POINTER(HzInfo)]),
+    "csr_reorder_workspace_bytes": (SZ, [I, I]),
+    "csr_level_order": (I, [P, P, I, I, P, P, P, P, P, P, SZ]),
+    "csr_zpermute": (I, [P, P, I, I, P, P, P, P, P, P, P, P, P, SZ]),
 }
 
 

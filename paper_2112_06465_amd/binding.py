@@ -16,6 +16,7 @@ from ._lib import HelmzError, HzC128, HzInfo, load
 
 OK, NOT_CONVERGED, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 PRECOND_NONE, PRECOND_JACOBI, X0_ZERO, VALIDATE, SYMMETRIC = 0x0, 0x1, 0x4, 0x8, 0x10
+REORDER, NO_REORDER = 0x20, 0x40
 
 _handles: dict[int, int] = {}
 _hlock = threading.Lock()
@@ -312,14 +313,14 @@ def _row_off_array(row_off):
     return ro
 
 
-def zbicgstab_batched_workspace_bytes(row_off, nnz: int, flags: int = 0) -> int:
+def zbicgstab_varbatch_workspace_bytes(row_off, nnz: int, flags: int = 0) -> int:
     ro = _row_off_array(row_off)
-    return int(load().zbicgstab_batched_workspace_bytes(ro.size - 1, ro.ctypes.data, int(nnz), int(flags)))
+    return int(load().zbicgstab_varbatch_workspace_bytes(ro.size - 1, ro.ctypes.data, int(nnz), int(flags)))
 
 
-def zbicgstab_solve_batched(row_off, row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxiter=20000,
-                            flags=PRECOND_NONE | X0_ZERO, ws=None):
-    """Solve the diagonal blocks of a block-diagonal system independently (zbicgstab_solve_batched).
+def zbicgstab_solve_varbatch(row_off, row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxiter=20000,
+                             flags=PRECOND_NONE | X0_ZERO, ws=None):
+    """Solve the diagonal blocks of a block-diagonal system independently (zbicgstab_solve_varbatch).
 
     ``row_off`` (host, nsys + 1 offsets) delimits the systems.  Returns
     (x, [info per system]).
@@ -334,14 +335,113 @@ def zbicgstab_solve_batched(row_off, row_ptr, col_idx, vals, b, x=None, rtol=1e-
         x = torch.zeros(n, dtype=torch.complex128, device=dev)
         flags |= X0_ZERO
     _need(x, "x", torch.complex128, dev)
-    need = zbicgstab_batched_workspace_bytes(ro, nnz, flags)
+    need = zbicgstab_varbatch_workspace_bytes(ro, nnz, flags)
     if ws is None:
         ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
     _need(ws, "ws", torch.uint8, dev)
     wp, wbytes = _aligned_ptr(ws, need)
     infos = (HzInfo * nsys)()
-    rc = load().zbicgstab_solve_batched(handle(dev), _stream(dev), nsys, ro.ctypes.data, nnz, row_ptr.data_ptr(),
+    rc = load().zbicgstab_solve_varbatch(handle(dev), _stream(dev), nsys, ro.ctypes.data, nnz, row_ptr.data_ptr(),
+                                         col_idx.data_ptr(), vals.data_ptr(), b.data_ptr(), x.data_ptr(), float(rtol),
+                                         int(maxiter), int(flags), wp, wbytes, C.cast(infos, C.c_void_p))
+    _check("zbicgstab_solve_varbatch", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
+    return x, [i.as_dict() for i in infos]
+
+
+def zbicgstab_batched_workspace_bytes(nsys: int, n: int, nnz: int, flags: int = 0) -> int:
+    return int(load().zbicgstab_batched_workspace_bytes(int(nsys), int(n), int(nnz), int(flags)))
+
+
+def zbicgstab_solve_batched(row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxiter=20000, flags=PRECOND_NONE | X0_ZERO,
+                            ws=None):
+    """Solve B systems on one sparsity pattern (zbicgstab_solve_batched).
+
+    ``vals`` is (nnz, B) complex128 (column j = system j's values), ``b`` and
+    ``x`` are (n, B).  Returns (x, [info per system]).
+    """
+    dev = vals.device
+    _need(row_ptr, "row_ptr", torch.int32, dev)
+    _need(col_idx, "col_idx", torch.int32, dev)
+    _need(vals, "vals", torch.complex128, dev)
+    n, nnz = row_ptr.numel() - 1, col_idx.numel()
+    if vals.dim() != 2 or vals.shape[0] != nnz:
+        raise ValueError("vals must be (nnz, B)")
+    nsys = vals.shape[1]
+    _need(b, "b", torch.complex128, dev)
+    if tuple(b.shape) != (n, nsys):
+        raise ValueError("b must be (n, B)")
+    if x is None:
+        x = torch.zeros(n, nsys, dtype=torch.complex128, device=dev)
+        flags |= X0_ZERO
+    _need(x, "x", torch.complex128, dev)
+    if tuple(x.shape) != (n, nsys):
+        raise ValueError("x must be (n, B)")
+    need = zbicgstab_batched_workspace_bytes(nsys, n, nnz, flags)
+    if need == 0:
+        raise ValueError("unsupported batch size")
+    if ws is None:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    _need(ws, "ws", torch.uint8, dev)
+    wp, wbytes = _aligned_ptr(ws, need)
+    infos = (HzInfo * nsys)()
+    rc = load().zbicgstab_solve_batched(handle(dev), _stream(dev), nsys, n, nnz, row_ptr.data_ptr(),
                                         col_idx.data_ptr(), vals.data_ptr(), b.data_ptr(), x.data_ptr(), float(rtol),
                                         int(maxiter), int(flags), wp, wbytes, C.cast(infos, C.c_void_p))
     _check("zbicgstab_solve_batched", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
     return x, [i.as_dict() for i in infos]
+
+
+def csr_reorder_workspace_bytes(n: int, nnz: int) -> int:
+    return int(load().csr_reorder_workspace_bytes(int(n), int(nnz)))
+
+
+def _reorder_ws(n: int, nnz: int, dev, ws):
+    need = csr_reorder_workspace_bytes(n, nnz)
+    if ws is None:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    _need(ws, "ws", torch.uint8, dev)
+    return _aligned_ptr(ws, need), ws
+
+
+def csr_level_order(row_ptr, col_idx, ws=None):
+    """Level-set (breadth-first) ordering of a CSR pattern (csr_level_order).
+
+    Returns (perm, inv, level) as int32 GPU tensors: perm[k] = the caller's
+    index of new row k, inv its inverse, level the breadth-first level of
+    each caller index (-1 if unreached).
+    """
+    dev = row_ptr.device
+    _need(row_ptr, "row_ptr", torch.int32, dev)
+    _need(col_idx, "col_idx", torch.int32, dev)
+    n, nnz = row_ptr.numel() - 1, col_idx.numel()
+    if n < 0:
+        raise ValueError("row_ptr must hold n + 1 entries")
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    inv = torch.empty(n, dtype=torch.int32, device=dev)
+    level = torch.empty(n, dtype=torch.int32, device=dev)
+    (wp, wbytes), _ws = _reorder_ws(n, nnz, dev, ws)
+    rc = load().csr_level_order(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                                perm.data_ptr(), inv.data_ptr(), level.data_ptr(), wp, wbytes)
+    _check("csr_level_order", rc)
+    return perm, inv, level
+
+
+def csr_zpermute(row_ptr, col_idx, vals, perm, inv, ws=None):
+    """P A P^T in CSR for perm (new -> old) with inverse inv (csr_zpermute).
+
+    Returns (row_ptr, col_idx, vals) of the renumbered matrix.
+    """
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    _need(perm, "perm", torch.int32, dev)
+    _need(inv, "inv", torch.int32, dev)
+    if perm.numel() != n or inv.numel() != n:
+        raise ValueError("perm and inv must hold n entries")
+    rp2 = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    ci2 = torch.empty(nnz, dtype=torch.int32, device=dev)
+    v2 = torch.empty(nnz, dtype=torch.complex128, device=dev)
+    (wp, wbytes), _ws = _reorder_ws(n, nnz, dev, ws)
+    rc = load().csr_zpermute(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                             vals.data_ptr(), perm.data_ptr(), inv.data_ptr(), rp2.data_ptr(), ci2.data_ptr(),
+                             v2.data_ptr(), wp, wbytes)
+    _check("csr_zpermute", rc)
+    return rp2, ci2, v2

@@ -10,9 +10,14 @@
 #include <new>
 #include <vector>
 
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
 #include "helmz.h"
 #include "hz_kernels.hpp"
 #include "hz_adjoint.hpp"
+#include "hz_reorder.hpp"
+#include "hz_multi.hpp"
 
 using hz::cx;
 using hz::Geom;
@@ -403,6 +408,379 @@ int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nn
     return worst;
 }
 
+// ------------------------------------------------------------------ level-set reordering
+
+// Scratch of the ordering: BFS levels (later the permuted row lengths),
+// non-empty-level flags, two device words (start node, last level), sort
+// keys and values, and the rocPRIM sort/scan scratch.
+struct LevelWs {
+    int* level;  // n + 1
+    int* active; // n + 1
+    int* scal;   // [0] start node, [1] last level found
+    unsigned* key;
+    unsigned* key2;
+    int* idx;
+    void* tmp;
+    size_t tmp_bytes;
+};
+
+size_t prim_tmp_bytes(int n, unsigned end_bit) {
+    size_t a = 0, b = 0;
+    const unsigned* ku = nullptr;
+    unsigned* ko = nullptr;
+    const int* vi = nullptr;
+    int* vo = nullptr;
+    if (rocprim::radix_sort_pairs(nullptr, a, ku, ko, vi, vo, unsigned(n), 0u, end_bit) != hipSuccess) return 0;
+    if (rocprim::inclusive_scan(nullptr, b, vi, vo, size_t(n) + 1, rocprim::plus<int>()) != hipSuccess) return 0;
+    return std::max<size_t>(std::max(a, b), 1);
+}
+
+size_t level_layout(int n, char* base, LevelWs* out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const size_t nn = size_t(n > 0 ? n : 1);
+    LevelWs w{};
+    w.level = static_cast<int*>(take(sizeof(int) * (nn + 1)));
+    w.active = static_cast<int*>(take(sizeof(int) * (nn + 1)));
+    w.scal = static_cast<int*>(take(sizeof(int) * 4));
+    w.key = static_cast<unsigned*>(take(sizeof(unsigned) * nn));
+    w.key2 = static_cast<unsigned*>(take(sizeof(unsigned) * nn));
+    w.idx = static_cast<int*>(take(sizeof(int) * nn));
+    w.tmp_bytes = prim_tmp_bytes(int(nn), 32u);
+    w.tmp = take(w.tmp_bytes);
+    if (out) *out = w;
+    return off;
+}
+
+// Breadth-first levels from the node in w.scal[0]; *last = the deepest
+// non-empty level.  Level steps are enqueued in chunks (16, 32, ..., 256)
+// with one host read of the last level found between chunks; steps past the
+// end return at entry.
+int bfs(hz_handle* h, hipStream_t s, int n, const int* rp, const int* ci, const LevelWs& w, int* last) {
+    hipLaunchKernelGGL(hz::k_bfs_seed, grid1(int64_t(n) + 1), dim3(kBlock), 0, s, n,
+                       static_cast<const int*>(w.scal), w.level, w.active, w.scal + 1);
+    const dim3 G(unsigned(std::min<int64_t>((int64_t(n) + kBlock - 1) / kBlock, 2 * kMaxGrid)));
+    int L = 0, chunk = 16;
+    for (;;) {
+        for (int k = 0; k < chunk && L < n; ++k, ++L)
+            hipLaunchKernelGGL(hz::k_bfs_level, G, dim3(kBlock), 0, s, n, rp, ci, w.level, w.active, w.scal + 1, L);
+        HZ_HIP(hipGetLastError());
+        HZ_HIP(hipMemcpyAsync(h->hflag, w.scal + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipStreamSynchronize(s));
+        if (*h->hflag < L || L >= n) break;  // level L is empty: the search is complete
+        if (chunk < 256) chunk *= 2;
+    }
+    *last = *h->hflag;
+    return HZ_OK;
+}
+
+// Level-set ordering: a first search from node 0 finds a far node (the
+// smallest index on its deepest level), a second search from there gives the
+// levels; perm lists the nodes by (level, caller's index), unreached nodes
+// last, and inv is its inverse.  level_out (nullable) receives the levels.
+int level_order(hz_handle* h, hipStream_t s, int n, const int* rp, const int* ci, const LevelWs& w, int* perm,
+                int* inv, int* level_out) {
+    HZ_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(w.scal), 0, 1, s));
+    int last = 0;
+    int rc = bfs(h, s, n, rp, ci, w, &last);
+    if (rc) return rc;
+    HZ_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(w.scal), n, 1, s));
+    hipLaunchKernelGGL(hz::k_bfs_far, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(w.level), last, w.scal);
+    rc = bfs(h, s, n, rp, ci, w, &last);
+    if (rc) return rc;
+    if (level_out) HZ_HIP(hipMemcpyAsync(level_out, w.level, sizeof(int) * size_t(n), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(hz::k_order_keys, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(w.level), last, w.key,
+                       w.idx);
+    const unsigned top = unsigned(last) + 1;  // largest key
+    unsigned end_bit = 1;
+    while (end_bit < 32 && (top >> end_bit) != 0) ++end_bit;
+    size_t tb = prim_tmp_bytes(n, end_bit);
+    if (tb == 0 || tb > w.tmp_bytes) return HZ_ERR_WORKSPACE;
+    tb = w.tmp_bytes;
+    HZ_HIP(rocprim::radix_sort_pairs(w.tmp, tb, static_cast<const unsigned*>(w.key), w.key2,
+                                     static_cast<const int*>(w.idx), perm, unsigned(n), 0u, end_bit, s));
+    hipLaunchKernelGGL(hz::k_invert, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(perm), inv);
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+// P A P^T in CSR: row lengths in the new order, scan, copy with renumbered
+// columns, per-row sort by column.
+int permute_csr(hipStream_t s, int n, int nnz, const int* rp, const int* ci, const double2* v, const int* perm,
+                const int* inv, const LevelWs& w, int* rp2, int* ci2, double2* v2) {
+    hipLaunchKernelGGL(hz::k_perm_rowlen, grid1(n), dim3(kBlock), 0, s, n, rp, perm, w.level);
+    size_t tb = w.tmp_bytes;
+    HZ_HIP(rocprim::inclusive_scan(w.tmp, tb, static_cast<const int*>(w.level), rp2, size_t(n) + 1,
+                                   rocprim::plus<int>(), s));
+    if (nnz > 0) {
+        hipLaunchKernelGGL(hz::k_perm_fill, grid1(int64_t(n) * 8), dim3(kBlock), 0, s, n, rp, ci, v, perm, inv,
+                           static_cast<const int*>(rp2), ci2, v2);
+        hipLaunchKernelGGL(hz::k_row_sort, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(rp2), ci2, v2);
+    }
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+// A solve in the level-set numbering: the ordering scratch, the permutation
+// and its inverse, P A P^T, and P b, P x.
+struct ReorderWs {
+    LevelWs lv;
+    int* perm;
+    int* inv;
+    int* rp;
+    int* ci;
+    double2* vals;
+    double2* b;
+    double2* x;
+};
+
+size_t reorder_layout(int n, int64_t nnz, char* base, ReorderWs* out) {
+    ReorderWs r{};
+    size_t off = level_layout(n, base, &r.lv);
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const size_t nn = size_t(n > 0 ? n : 1), nz = size_t(nnz > 0 ? nnz : 1);
+    r.perm = static_cast<int*>(take(sizeof(int) * nn));
+    r.inv = static_cast<int*>(take(sizeof(int) * nn));
+    r.rp = static_cast<int*>(take(sizeof(int) * (nn + 1)));
+    r.ci = static_cast<int*>(take(sizeof(int) * nz));
+    r.vals = static_cast<double2*>(take(sizeof(double2) * nz));
+    r.b = static_cast<double2*>(take(sizeof(double2) * nn));
+    r.x = static_cast<double2*>(take(sizeof(double2) * nn));
+    if (out) *out = r;
+    return off;
+}
+
+// Renumber when HZ_REORDER is passed, never under HZ_NO_REORDER, otherwise
+// when more than 5 % of the entries lie more than kFarRows off the diagonal
+// (the same locality test that selects the gather-light iteration).
+int want_reorder(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci, int flags, bool* yes) {
+    *yes = false;
+    if (flags & HZ_NO_REORDER) return HZ_OK;
+    if (flags & HZ_REORDER) {
+        *yes = true;
+        return HZ_OK;
+    }
+    int rc = enqueue_far_count(h, s, n, rp, ci);
+    if (rc) return rc;
+    HZ_HIP(hipStreamSynchronize(s));
+    *yes = double(*h->hcount) > 0.05 * double(nnz);
+    return HZ_OK;
+}
+
+// Workspace of a single-system solve: the ordering part (unless renumbering
+// is ruled out) followed by the solver's own.
+size_t single_ws_bytes(int n, int64_t nnz, int flags) {
+    const size_t inner = ws_bytes_single<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0);
+    return (flags & HZ_NO_REORDER) ? inner : reorder_layout(n, nnz, nullptr, nullptr) + inner;
+}
+
+// Single-system FP64 solve, renumbered by level sets when want_reorder says
+// so: P A P^T (P x) = P b is solved and x is scattered back.
+int solve_single(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci, const double2* A,
+                 const double2* b, double2* x, double rtol, int maxiter, int flags, char* ws, hz_solve_info* info) {
+    const int row_off[2] = {0, n};
+    bool re = false;
+    int rc = want_reorder(h, s, n, nnz, rp, ci, flags, &re);
+    if (rc) return rc;
+    if (!re) return solve_fp64(h, s, 1, row_off, nnz, rp, ci, A, b, x, rtol, maxiter, flags, ws, &info[0]);
+    ReorderWs r;
+    const size_t off = reorder_layout(n, nnz, ws, &r);
+    rc = level_order(h, s, n, rp, ci, r.lv, r.perm, r.inv, nullptr);
+    if (rc) return rc;
+    rc = permute_csr(s, n, nnz, rp, ci, A, r.perm, r.inv, r.lv, r.rp, r.ci, r.vals);
+    if (rc) return rc;
+    hipLaunchKernelGGL(hz::k_gather_perm<double>, grid1(n), dim3(kBlock), 0, s, n, r.perm, b, r.b);
+    if (!(flags & HZ_X0_ZERO))
+        hipLaunchKernelGGL(hz::k_gather_perm<double>, grid1(n), dim3(kBlock), 0, s, n, r.perm,
+                           static_cast<const double2*>(x), r.x);
+    HZ_HIP(hipGetLastError());
+    rc = solve_fp64(h, s, 1, row_off, nnz, r.rp, r.ci, r.vals, r.b, r.x, rtol, maxiter, flags, ws + off, info);
+    if (rc < 0) return rc;
+    info->renumbered = 1;
+    hipLaunchKernelGGL(hz::k_scatter_perm<double>, grid1(n), dim3(kBlock), 0, s, n, r.perm,
+                       static_cast<const double2*>(r.x), x);
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipStreamSynchronize(s));
+    return rc;
+}
+
+// ------------------------------------------------------------------ shared-pattern batches
+
+// Lanes reserved per row for B systems: 16, 64 or 256.
+int multi_lanes(int B) { return B <= 16 ? 16 : (B <= 64 ? 64 : hz::kMultiMax); }
+
+template <typename F> void with_multi(int BL, F&& f) {
+    switch (BL) {
+        case 16: f.template operator()<16>(); break;
+        case 64: f.template operator()<64>(); break;
+        default: f.template operator()<hz::kMultiMax>(); break;
+    }
+}
+
+constexpr int kMultiU = 4;  // entries in flight per lane in the batched row product (v = A p)
+constexpr int kMultiUt = 3;  // the same for t = A s, whose epilogue holds more registers
+
+// Workspace of a shared-pattern batch: per-system scalars, partials
+// [kParts][G][BL], the done counter, six [n][B] vectors (r, rhat, p, v, s,
+// t) and, under Jacobi, D^{-1} [n][B] and the column-scaled values [nnz][B].
+struct MultiWs {
+    SolverScal* sc;
+    double* part;
+    int* ndone;
+    double2* vec[6];
+    double2* dinv;
+    double2* ahat;
+};
+
+size_t multi_layout(int B, int n, int64_t nnz, bool jacobi, char* base, MultiWs* out) {
+    const int BL = multi_lanes(B);
+    const Geom geo = geom_for(n, kBlock / BL);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const size_t nb = size_t(n > 0 ? n : 1) * size_t(B), zb = size_t(nnz > 0 ? nnz : 1) * size_t(B);
+    MultiWs w{};
+    w.sc = static_cast<SolverScal*>(take(sizeof(SolverScal) * size_t(B)));
+    w.part = static_cast<double*>(take(sizeof(double) * size_t(hz::kParts) * size_t(geo.G) * size_t(BL)));
+    w.ndone = static_cast<int*>(take(sizeof(int)));
+    for (auto& v : w.vec) v = static_cast<double2*>(take(sizeof(double2) * nb));
+    w.dinv = jacobi ? static_cast<double2*>(take(sizeof(double2) * nb)) : nullptr;
+    w.ahat = jacobi ? static_cast<double2*>(take(sizeof(double2) * zb)) : nullptr;
+    if (out) *out = w;
+    return off;
+}
+
+// The five-kernel iteration for every system of the batch, in chunks of 8,
+// 16, ..., 64 iterations with a poll of the done counter between chunks; one
+// more P-kernel after maxiter concludes the last iteration.
+int iterate_multi(hz_handle* h, hipStream_t s, const hz::MultiArgs& a, int BL, int maxiter) {
+    const dim3 G(a.geo.G), Bk(kBlock);
+    int launched = 0, poll = 8, err = 0;
+    with_multi(BL, [&]<int BB>() {
+        while (launched < maxiter) {
+            const int k_n = (maxiter - launched) < poll ? (maxiter - launched) : poll;
+            for (int k = 0; k < k_n; ++k) {
+                hipLaunchKernelGGL((hz::k_m_P<BB>), G, Bk, 0, s, a);
+                hipLaunchKernelGGL((hz::k_m_A1<BB, kMultiU>), G, Bk, 0, s, a);
+                hipLaunchKernelGGL((hz::k_m_S<BB>), G, Bk, 0, s, a);
+                hipLaunchKernelGGL((hz::k_m_B1<BB, kMultiUt>), G, Bk, 0, s, a);
+                hipLaunchKernelGGL((hz::k_m_C<BB>), G, Bk, 0, s, a);
+            }
+            launched += k_n;
+            if (launched == maxiter) hipLaunchKernelGGL((hz::k_m_P<BB>), G, Bk, 0, s, a);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(h->hflag, a.ndone, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                err = 1;
+                return;
+            }
+            if (*h->hflag >= a.B) break;
+            if (poll < 64) poll *= 2;
+        }
+    });
+    return err ? HZ_ERR_HIP : HZ_OK;
+}
+
+// B systems on one pattern (values [nnz][B], vectors [n][B]) after argument
+// checks.  infos[j] receives system j's result; returns the largest status.
+int solve_multi(hz_handle* h, hipStream_t s, int B, int n, int nnz, const int* rp, const int* ci, const double2* A,
+                const double2* bd, double2* xd, double rtol, int maxiter, int flags, char* ws, hz_solve_info* infos) {
+    const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
+    const int BL = multi_lanes(B);
+    const Geom geo = geom_for(n, kBlock / BL);
+    MultiWs w;
+    multi_layout(B, n, nnz, jacobi, ws, &w);
+    const int64_t nB = int64_t(n) * B;
+    HZ_HIP(hipMemsetAsync(w.ndone, 0, sizeof(int), s));
+    hipLaunchKernelGGL(hz::k_sc_init, dim3((B + 255) / 256), dim3(256), 0, s, w.sc, B, rtol, maxiter);
+    const double2* Aop = A;
+    if (jacobi) {
+        hipLaunchKernelGGL(hz::k_m_jacobi, grid1(nB), dim3(kBlock), 0, s, n, B, rp, ci, A, w.dinv, w.sc);
+        if (nnz > 0)
+            hipLaunchKernelGGL(hz::k_m_colscale, grid1(int64_t(nnz) * B), dim3(kBlock), 0, s, int64_t(nnz), B, ci,
+                               A, static_cast<const double2*>(w.dinv), w.ahat);
+        Aop = w.ahat;
+    }
+    hz::MultiArgs a;
+    a.n = n;
+    a.B = B;
+    a.geo = geo;
+    a.row_ptr = rp;
+    a.col_idx = ci;
+    a.vals = Aop;
+    a.b = bd;
+    a.r = w.vec[0];
+    a.rh = w.vec[1];
+    a.p = w.vec[2];
+    a.v = w.vec[3];
+    a.s = w.vec[4];
+    a.t = w.vec[5];
+    a.x = xd;
+    a.part = w.part;
+    a.sc = w.sc;
+    a.ndone = w.ndone;
+    const dim3 G(geo.G), Bk(kBlock);
+    const double2* rsrc = bd;
+    if (flags & HZ_X0_ZERO) HZ_HIP(hipMemsetAsync(xd, 0, sizeof(double2) * size_t(nB), s));
+    with_multi(BL, [&]<int BB>() {
+        if (!(flags & HZ_X0_ZERO)) {
+            if (jacobi)
+                hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(nB), Bk, 0, s, int(nB),
+                                   static_cast<const double2*>(w.dinv), xd, 1);
+            hipLaunchKernelGGL((hz::k_m_resid<BB, kMultiU>), G, Bk, 0, s, a, Aop, static_cast<const double2*>(xd),
+                               a.r);
+            rsrc = a.r;
+        }
+        hipLaunchKernelGGL((hz::k_m_init<BB>), G, Bk, 0, s, a, rsrc);
+        hipLaunchKernelGGL((hz::k_m_fin_init<BB>), dim3(1), Bk, 0, s, a);
+    });
+    HZ_HIP(hipGetLastError());
+    std::vector<SolverScal> hs(B);
+    HZ_HIP(hipMemcpyAsync(hs.data(), w.sc, sizeof(SolverScal) * size_t(B), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipMemcpyAsync(h->hflag, w.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < B; ++j)
+        if (hs[j].bad_diag) return HZ_ERR_INVALID;
+    if (*h->hflag < B) {
+        int rc = iterate_multi(h, s, a, BL, maxiter);
+        if (rc) return rc;
+    }
+    with_multi(BL, [&]<int BB>() {
+        hipLaunchKernelGGL((hz::k_m_zero_if<BB>), G, Bk, 0, s, a);
+        if (jacobi)
+            hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(nB), Bk, 0, s, int(nB),
+                               static_cast<const double2*>(w.dinv), xd, 0);
+        // true residual with the caller's values
+        hipLaunchKernelGGL((hz::k_m_resid<BB, kMultiU>), G, Bk, 0, s, a, A, static_cast<const double2*>(xd), a.t);
+        hipLaunchKernelGGL((hz::k_m_fin_true<BB>), dim3(1), Bk, 0, s, a);
+    });
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipMemcpyAsync(hs.data(), w.sc, sizeof(SolverScal) * size_t(B), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    int worst = HZ_OK;
+    for (int j = 0; j < B; ++j) {
+        infos[j].status = hs[j].status;
+        infos[j].iterations = hs[j].iters;
+        infos[j].outer_steps = 0;
+        infos[j].renumbered = 0;
+        infos[j].relres_recursive = hs[j].relres;
+        infos[j].relres_true = hs[j].relres_true;
+        worst = std::max(worst, hs[j].status);
+    }
+    return worst;
+}
+
 // Mixed refinement workspace: outer scalars, the complex64 solver's own
 // workspace (vectors, partials, scalars, map, D^{-1}, demoted matrix), the
 // FP64 residual and the complex64 right-hand side and correction.
@@ -457,7 +835,7 @@ size_t adjoint_layout(int n, int64_t nnz, int flags, char* base, AdjWs* out) {
     };
     const size_t nn = size_t(n > 0 ? n : 1), nz = size_t(nnz > 0 ? nnz : 1);
     AdjWs a{};
-    a.solve = static_cast<char*>(take(ws_bytes_single<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0)));
+    a.solve = static_cast<char*>(take(single_ws_bytes(n, nnz, flags)));
     a.gconj = static_cast<double2*>(take(sizeof(double2) * nn));
     if (!(flags & HZ_SYMMETRIC)) {
         a.t_rp = static_cast<int*>(take(sizeof(int) * (nn + 1)));
@@ -615,7 +993,7 @@ int zaxpy(hz_handle* h, hz_stream stream, int n, hz_c128 alpha, const hz_c128* x
 
 size_t zbicgstab_workspace_bytes(int n, int nnz, int flags) {
     if (n < 0 || nnz < 0) return 0;
-    return ws_bytes_single<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0);
+    return single_ws_bytes(n, nnz, flags);
 }
 
 int zbicgstab_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c128* vals,
@@ -630,17 +1008,17 @@ int zbicgstab_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* r
     if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
         return HZ_ERR_INVALID;
     if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
-    const size_t need = ws_bytes_single<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0);
+    if ((flags & HZ_REORDER) && (flags & HZ_NO_REORDER)) return HZ_ERR_INVALID;
+    const size_t need = single_ws_bytes(n, nnz, flags);
     if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (flags & HZ_VALIDATE) {
         rc = validate_csr(h, s, n, nnz, rp, ci);
         if (rc) return rc;
     }
-    const int row_off[2] = {0, n};
-    return solve_fp64(h, s, 1, row_off, nnz, rp, ci, reinterpret_cast<const double2*>(vals),
-                      reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxiter, flags,
-                      static_cast<char*>(ws), info);
+    return solve_single(h, s, n, nnz, rp, ci, reinterpret_cast<const double2*>(vals),
+                        reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxiter, flags,
+                        static_cast<char*>(ws), info);
 }
 
 static int check_row_off(int nsys, const int* row_off, int* n_total) {
@@ -651,7 +1029,7 @@ static int check_row_off(int nsys, const int* row_off, int* n_total) {
     return HZ_OK;
 }
 
-size_t zbicgstab_batched_workspace_bytes(int nsys, const int* row_off, int nnz, int flags) {
+size_t zbicgstab_varbatch_workspace_bytes(int nsys, const int* row_off, int nnz, int flags) {
     int n = 0;
     if (nnz < 0 || check_row_off(nsys, row_off, &n) != HZ_OK) return 0;
     const int L = pick_lanes(n, nnz);
@@ -659,9 +1037,9 @@ size_t zbicgstab_batched_workspace_bytes(int nsys, const int* row_off, int nnz, 
     return ws_layout<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nsys, m.G, nullptr, nullptr);
 }
 
-int zbicgstab_solve_batched(hz_handle* h, hz_stream stream, int nsys, const int* row_off, int nnz, const int* rp,
-                            const int* ci, const hz_c128* vals, const hz_c128* b, hz_c128* x, double rtol, int maxiter,
-                            int flags, void* ws, size_t ws_bytes, hz_solve_info* infos) {
+int zbicgstab_solve_varbatch(hz_handle* h, hz_stream stream, int nsys, const int* row_off, int nnz, const int* rp,
+                             const int* ci, const hz_c128* vals, const hz_c128* b, hz_c128* x, double rtol,
+                             int maxiter, int flags, void* ws, size_t ws_bytes, hz_solve_info* infos) {
     if (h == nullptr || infos == nullptr || nsys < 1) return HZ_ERR_INVALID;
     std::memset(infos, 0, sizeof(hz_solve_info) * size_t(nsys));
     int n = 0;
@@ -674,7 +1052,7 @@ int zbicgstab_solve_batched(hz_handle* h, hz_stream stream, int nsys, const int*
     if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
         return HZ_ERR_INVALID;
     if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
-    const size_t need = zbicgstab_batched_workspace_bytes(nsys, row_off, nnz, flags);
+    const size_t need = zbicgstab_varbatch_workspace_bytes(nsys, row_off, nnz, flags);
     if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (flags & HZ_VALIDATE) {
@@ -686,42 +1064,25 @@ int zbicgstab_solve_batched(hz_handle* h, hz_stream stream, int nsys, const int*
                       static_cast<char*>(ws), infos);
 }
 
-size_t zbicgstab_mixed_workspace_bytes(int n, int nnz, int flags) {
-    if (n < 0 || nnz < 0) return 0;
-    return mixed_layout(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr);
+size_t mixed_ws_bytes(int n, int64_t nnz, int flags) {
+    const size_t inner = mixed_layout(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr);
+    return (flags & HZ_NO_REORDER) ? inner : reorder_layout(n, nnz, nullptr, nullptr) + inner;
 }
 
-int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci,
-                          const hz_c128* vals, const hz_c128* b, hz_c128* x, double rtol, double inner_rtol,
-                          int maxiter, int max_outer, int flags, void* ws, size_t ws_bytes, hz_solve_info* info) {
-    if (info) std::memset(info, 0, sizeof(*info));
-    if (h == nullptr || info == nullptr) return HZ_ERR_INVALID;
-    int rc = check_csr_args(n, nnz, rp, ci, vals);
-    if (rc) return rc;
-    if (!(rtol >= 0.0) || !(inner_rtol > 0.0) || maxiter < 0 || max_outer < 0) return HZ_ERR_INVALID;
-    if (n == 0) return HZ_OK;
-    if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
-        return HZ_ERR_INVALID;
-    if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
+// Mixed-precision refinement of one system after argument checks; ws holds
+// mixed_layout's workspace.
+int solve_mixed(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci, const double2* A,
+                const double2* bd, double2* xd, double rtol, double inner_rtol, int maxiter, int max_outer, int flags,
+                char* ws, hz_solve_info* info) {
     const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
     MixedWs mw;
-    const size_t need = mixed_layout(n, nnz, jacobi, static_cast<char*>(ws), &mw);
-    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
-
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (flags & HZ_VALIDATE) {
-        rc = validate_csr(h, s, n, nnz, rp, ci);
-        if (rc) return rc;
-    }
+    mixed_layout(n, nnz, jacobi, ws, &mw);
     const int L = pick_lanes(n, nnz);
     const Geom geo = geom_for(n, kBlock / L);
     const int row_off[2] = {0, n};
     const WorkMap m = build_map(1, row_off, L);
-    rc = upload_map(s, m, mw.in);
+    int rc = upload_map(s, m, mw.in);
     if (rc) return rc;
-    const double2* A = reinterpret_cast<const double2*>(vals);
-    const double2* bd = reinterpret_cast<const double2*>(b);
-    double2* xd = reinterpret_cast<double2*>(x);
     const dim3 one(1), B(kBlock);
     double* partI = mw.in.part + hz::kPartI * m.stride;
 
@@ -797,6 +1158,93 @@ int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const 
     return ho->status;
 }
 
+size_t zbicgstab_batched_workspace_bytes(int nsys, int n, int nnz, int flags) {
+    if (nsys < 1 || nsys > hz::kMultiMax || n < 0 || nnz < 0) return 0;
+    return multi_layout(nsys, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr);
+}
+
+int zbicgstab_solve_batched(hz_handle* h, hz_stream stream, int nsys, int n, int nnz, const int* rp, const int* ci,
+                            const hz_c128* vals, const hz_c128* b, hz_c128* x, double rtol, int maxiter, int flags,
+                            void* ws, size_t ws_bytes, hz_solve_info* infos) {
+    if (h == nullptr || infos == nullptr || nsys < 1 || nsys > hz::kMultiMax) return HZ_ERR_INVALID;
+    std::memset(infos, 0, sizeof(hz_solve_info) * size_t(nsys));
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (!(rtol >= 0.0) || maxiter < 0) return HZ_ERR_INVALID;
+    if (int64_t(n) * nsys >= (int64_t(1) << 31)) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
+        return HZ_ERR_INVALID;
+    const size_t vb = 16 * size_t(n) * size_t(nsys);
+    if (overlap(b, vb, x, vb)) return HZ_ERR_INVALID;
+    const size_t need = zbicgstab_batched_workspace_bytes(nsys, n, nnz, flags);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (flags & HZ_VALIDATE) {
+        rc = validate_csr(h, s, n, nnz, rp, ci);
+        if (rc) return rc;
+    }
+    return solve_multi(h, s, nsys, n, nnz, rp, ci, reinterpret_cast<const double2*>(vals),
+                       reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxiter, flags,
+                       static_cast<char*>(ws), infos);
+}
+
+size_t zbicgstab_mixed_workspace_bytes(int n, int nnz, int flags) {
+    if (n < 0 || nnz < 0) return 0;
+    return mixed_ws_bytes(n, nnz, flags);
+}
+
+int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci,
+                          const hz_c128* vals, const hz_c128* b, hz_c128* x, double rtol, double inner_rtol,
+                          int maxiter, int max_outer, int flags, void* ws, size_t ws_bytes, hz_solve_info* info) {
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (h == nullptr || info == nullptr) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (!(rtol >= 0.0) || !(inner_rtol > 0.0) || maxiter < 0 || max_outer < 0) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
+        return HZ_ERR_INVALID;
+    if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
+    if ((flags & HZ_REORDER) && (flags & HZ_NO_REORDER)) return HZ_ERR_INVALID;
+    const size_t need = mixed_ws_bytes(n, nnz, flags);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (flags & HZ_VALIDATE) {
+        rc = validate_csr(h, s, n, nnz, rp, ci);
+        if (rc) return rc;
+    }
+    const double2* A = reinterpret_cast<const double2*>(vals);
+    const double2* bd = reinterpret_cast<const double2*>(b);
+    double2* xd = reinterpret_cast<double2*>(x);
+    char* w = static_cast<char*>(ws);
+    bool re = false;
+    rc = want_reorder(h, s, n, nnz, rp, ci, flags, &re);
+    if (rc) return rc;
+    if (!re) return solve_mixed(h, s, n, nnz, rp, ci, A, bd, xd, rtol, inner_rtol, maxiter, max_outer, flags, w, info);
+    // P A P^T (P x) = P b in the level-set numbering, then x scattered back
+    ReorderWs r;
+    const size_t off = reorder_layout(n, nnz, w, &r);
+    rc = level_order(h, s, n, rp, ci, r.lv, r.perm, r.inv, nullptr);
+    if (rc) return rc;
+    rc = permute_csr(s, n, nnz, rp, ci, A, r.perm, r.inv, r.lv, r.rp, r.ci, r.vals);
+    if (rc) return rc;
+    hipLaunchKernelGGL(hz::k_gather_perm<double>, grid1(n), dim3(kBlock), 0, s, n, r.perm, bd, r.b);
+    if (!(flags & HZ_X0_ZERO))
+        hipLaunchKernelGGL(hz::k_gather_perm<double>, grid1(n), dim3(kBlock), 0, s, n, r.perm,
+                           static_cast<const double2*>(xd), r.x);
+    HZ_HIP(hipGetLastError());
+    rc = solve_mixed(h, s, n, nnz, r.rp, r.ci, r.vals, r.b, r.x, rtol, inner_rtol, maxiter, max_outer, flags,
+                     w + off, info);
+    if (rc < 0) return rc;
+    info->renumbered = 1;
+    hipLaunchKernelGGL(hz::k_scatter_perm<double>, grid1(n), dim3(kBlock), 0, s, n, r.perm,
+                       static_cast<const double2*>(r.x), xd);
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipStreamSynchronize(s));
+    return rc;
+}
+
 
 
 int csr_zspmv_rect(hz_handle* h, hz_stream stream, int m, int ncols, int nnz, const int* rp, const int* ci,
@@ -850,6 +1298,7 @@ int zbicgstab_adjoint(hz_handle* h, hz_stream stream, int n, int nnz, const int*
         return HZ_ERR_INVALID;
     if (grad_vals != nullptr && (x == nullptr || misaligned(x, 16) || misaligned(grad_vals, 16))) return HZ_ERR_INVALID;
     if (overlap(grad_x, 16 * size_t(n), grad_b, 16 * size_t(n))) return HZ_ERR_INVALID;
+    if ((flags & HZ_REORDER) && (flags & HZ_NO_REORDER)) return HZ_ERR_INVALID;
     AdjWs a;
     const size_t need = adjoint_layout(n, nnz, flags, static_cast<char*>(ws), &a);
     if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
@@ -861,13 +1310,12 @@ int zbicgstab_adjoint(hz_handle* h, hz_stream stream, int n, int nnz, const int*
     const double2* A = reinterpret_cast<const double2*>(vals);
     const double2* g = reinterpret_cast<const double2*>(grad_x);
     double2* lam = reinterpret_cast<double2*>(grad_b);
-    const int sflags = (flags & HZ_PRECOND_JACOBI) | HZ_X0_ZERO;
-    const int row_off[2] = {0, n};
+    const int sflags = (flags & (HZ_PRECOND_JACOBI | HZ_REORDER | HZ_NO_REORDER)) | HZ_X0_ZERO;
     if (flags & HZ_SYMMETRIC) {
         // A^H lambda = g  <=>  A conj(lambda) = conj(g)  when A = A^T
         hipLaunchKernelGGL(hz::k_conj, grid1(n), dim3(kBlock), 0, s, n, g, a.gconj);
         HZ_HIP(hipGetLastError());
-        rc = solve_fp64(h, s, 1, row_off, nnz, rp, ci, A, a.gconj, lam, rtol, maxiter, sflags, a.solve, info);
+        rc = solve_single(h, s, n, nnz, rp, ci, A, a.gconj, lam, rtol, maxiter, sflags, a.solve, info);
         if (rc < 0) return rc;
         hipLaunchKernelGGL(hz::k_conj, grid1(n), dim3(kBlock), 0, s, n, static_cast<const double2*>(lam), lam);
     } else {
@@ -877,10 +1325,10 @@ int zbicgstab_adjoint(hz_handle* h, hz_stream stream, int n, int nnz, const int*
         hipLaunchKernelGGL(hz::k_scan_1block, dim3(1), dim3(1024), 0, s, n + 1, a.t_rp);
         HZ_HIP(hipMemcpyAsync(a.fill, a.t_rp, sizeof(int) * size_t(n), hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL(hz::k_tr_scatter, grid1(n), dim3(kBlock), 0, s, n, rp, ci, A, a.fill, a.t_ci, a.t_vals);
-        hipLaunchKernelGGL(hz::k_tr_sort, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(a.t_rp), a.t_ci,
+        hipLaunchKernelGGL(hz::k_row_sort, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(a.t_rp), a.t_ci,
                            a.t_vals);
         HZ_HIP(hipGetLastError());
-        rc = solve_fp64(h, s, 1, row_off, nnz, a.t_rp, a.t_ci, a.t_vals, g, lam, rtol, maxiter, sflags, a.solve, info);
+        rc = solve_single(h, s, n, nnz, a.t_rp, a.t_ci, a.t_vals, g, lam, rtol, maxiter, sflags, a.solve, info);
         if (rc < 0) return rc;
     }
     if (grad_vals != nullptr && nnz > 0)
@@ -889,6 +1337,67 @@ int zbicgstab_adjoint(hz_handle* h, hz_stream stream, int n, int nnz, const int*
     HZ_HIP(hipGetLastError());
     HZ_HIP(hipStreamSynchronize(s));
     return info->status;
+}
+
+size_t csr_reorder_workspace_bytes(int n, int nnz) {
+    if (n < 0 || nnz < 0) return 0;
+    return level_layout(n, nullptr, nullptr);
+}
+
+int csr_level_order(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, int* perm, int* inv,
+                    int* level, void* ws, size_t ws_bytes) {
+    if (h == nullptr) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, reinterpret_cast<const void*>(ci));
+    if (rc) return rc;
+    if (n == 0) return HZ_OK;
+    if (perm == nullptr || inv == nullptr || misaligned(perm, 4) || misaligned(inv, 4) || misaligned(level, 4))
+        return HZ_ERR_INVALID;
+    if (overlap(perm, 4 * size_t(n), inv, 4 * size_t(n))) return HZ_ERR_INVALID;
+    LevelWs w;
+    const size_t need = level_layout(n, static_cast<char*>(ws), &w);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = level_order(h, s, n, rp, ci, w, perm, inv, level);
+    if (rc) return rc;
+    HZ_HIP(hipStreamSynchronize(s));
+    return HZ_OK;
+}
+
+int csr_zpermute(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c128* vals,
+                 const int* perm, const int* inv, int* rp_out, int* ci_out, hz_c128* vals_out, void* ws,
+                 size_t ws_bytes) {
+    if (h == nullptr) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (n == 0) return HZ_OK;
+    if (perm == nullptr || inv == nullptr || rp_out == nullptr || misaligned(perm, 4) || misaligned(inv, 4) ||
+        misaligned(rp_out, 4))
+        return HZ_ERR_INVALID;
+    if (nnz > 0 && (ci_out == nullptr || vals_out == nullptr || misaligned(ci_out, 4) || misaligned(vals, 16) ||
+                    misaligned(vals_out, 16)))
+        return HZ_ERR_INVALID;
+    const size_t rb = 4 * (size_t(n) + 1), cb = 4 * size_t(nnz), vb = 16 * size_t(nnz);
+    if (overlap(rp_out, rb, rp, rb) || overlap(rp_out, rb, ci, cb) || overlap(rp_out, rb, vals, vb) ||
+        (nnz > 0 && (overlap(ci_out, cb, rp, rb) || overlap(ci_out, cb, ci, cb) || overlap(ci_out, cb, vals, vb) ||
+                     overlap(vals_out, vb, rp, rb) || overlap(vals_out, vb, ci, cb) ||
+                     overlap(vals_out, vb, vals, vb))))
+        return HZ_ERR_INVALID;
+    LevelWs w;
+    const size_t need = level_layout(n, static_cast<char*>(ws), &w);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // perm must be a permutation with inverse inv (every index in range)
+    HZ_HIP(hipMemsetAsync(h->dflag, 0, sizeof(int), s));
+    hipLaunchKernelGGL(hz::k_check_perm, grid1(n), dim3(kBlock), 0, s, n, perm, inv, h->dflag);
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipMemcpyAsync(h->hflag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    if (*h->hflag) return HZ_ERR_INVALID;
+    rc = permute_csr(s, n, nnz, rp, ci, reinterpret_cast<const double2*>(vals), perm, inv, w, rp_out, ci_out,
+                     reinterpret_cast<double2*>(vals_out));
+    if (rc) return rc;
+    HZ_HIP(hipStreamSynchronize(s));
+    return HZ_OK;
 }
 
 }  // extern "C"

@@ -64,8 +64,9 @@ __global__ __launch_bounds__(kBlock) void k_tr_scatter(int n, const int* __restr
     }
 }
 
-// sort each row of the transpose by column (insertion sort; rows are short)
-__global__ __launch_bounds__(kBlock) void k_tr_sort(int n, const int* __restrict__ trp, int* __restrict__ tci,
+// sort each row of a CSR matrix by column, carrying the values (insertion
+// sort; rows are short).  Used for the transpose and for P A P^T.
+__global__ __launch_bounds__(kBlock) void k_row_sort(int n, const int* __restrict__ trp, int* __restrict__ tci,
                                                     double2* __restrict__ tv) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;

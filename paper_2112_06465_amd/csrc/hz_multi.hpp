@@ -1,0 +1,486 @@
+// Shared-pattern batched BiCGStab: B systems A_j x_j = b_j with one sparsity
+// pattern, e.g. a frequency sweep A(k_j) = K - k_j^2 M + i k_j B on one mesh.
+// Each system runs Section 7's preconditioned BiCGStab with its own scalars,
+// convergence test and exit; the systems share the launches, the row_ptr /
+// col_idx reads and the gathers' cache lines.
+//
+// Layout (system-minor): entry p of system j is vals[p*B + j]; element i of
+// a vector of system j is v[i*B + j].  A block owns a contiguous row chunk
+// (XCD-aware mapping as in the single solve) and takes kBlock/BL rows per
+// step with one lane per system (BL = a power of two >= B; lanes j >= B
+// idle).  A row's values and gathered x of all systems are then contiguous
+// B*16-byte runs: every load is coalesced, col_idx is read once for all
+// systems, and no cross-lane row reduction is needed.
+//
+// Iteration (gather-light, five kernels, as for randomly numbered single
+// systems):
+//   P:  conclude iteration i-1 per system (<rhat,r>, ||r||), beta;
+//       p = r + beta (p - omega v)
+//   A1: v = A p; partial <rhat, v>
+//   S:  alpha = rho / <rhat, v>; s = r - alpha v; partial ||s||^2
+//   B1: t = A s; partials <t, s>, ||t||^2
+//   C:  half-step test; omega = <t,s>/<t,t>; x += alpha p + omega s;
+//       r = s - omega t; partials <rhat, r>, ||r||^2
+// Partials are per (component, block, lane), reduced over the row slots of a
+// block by a fixed tree and finished at the consumer's head by every block
+// in a fixed order: reruns are bitwise identical, and system j's arithmetic
+// does not depend on the other systems (permuting the batch permutes the
+// results bitwise).
+#pragma once
+
+#include "hz_kernels.hpp"
+
+namespace hz {
+
+constexpr int kMultiMax = 256;  // most systems per shared-pattern launch
+
+struct MultiArgs {
+    int n;     // rows of the shared pattern
+    int B;     // systems
+    Geom geo;  // row chunks of the geo.G blocks
+    const int* __restrict__ row_ptr;
+    const int* __restrict__ col_idx;
+    const double2* __restrict__ vals;  // [nnz][B], column-scaled under Jacobi
+    const double2* b;                  // [n][B]
+    double2* r;
+    double2* rh;
+    double2* p;
+    double2* v;
+    double2* s;
+    double2* t;
+    double2* x;
+    double* part;    // [kParts][G][BL]
+    SolverScal* sc;  // [B]
+    int* ndone;      // systems finished so far
+};
+
+// Sum v[k] over the row slots of the block separately for every lane, by a
+// fixed tree over slots; every thread receives the sums of its lane.
+template <int BL, int K>
+__device__ __forceinline__ void slot_sum(double (&v)[K]) {
+    constexpr int S = kBlock / BL;
+    __shared__ double red[K][kBlock];
+    const int t = threadIdx.x;
+    __syncthreads();  // a previous use of red has been read
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k][t] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int s = S / 2; s >= 1; s /= 2) {
+        if (t < s * BL) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) red[k][t] += red[k][t + s * BL];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = red[k][t % BL];
+}
+
+// The block's partials of K components: region[(k*G + lb)*BL + lane].
+template <int BL, int K>
+__device__ __forceinline__ void mstore(double* region, int G, int lb, double (&e)[K]) {
+    slot_sum<BL, K>(e);
+    if (threadIdx.x < BL) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) region[((size_t)k * G + lb) * BL + threadIdx.x] = e[k];
+    }
+}
+
+// Totals of K components over all G blocks for the thread's lane.
+template <int BL, int K>
+__device__ __forceinline__ void mhead(const double* region, int G, double (&out)[K]) {
+    constexpr int S = kBlock / BL;
+    const int g = threadIdx.x / BL, j = threadIdx.x % BL;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int b = g; b < G; b += S) s += region[((size_t)k * G + b) * BL + j];
+        out[k] = s;
+    }
+    slot_sum<BL, K>(out);
+}
+
+// True when every system has ended.  One read per block, broadcast through
+// LDS, so all waves of the block take the same branch (the counter may grow
+// while the kernel runs: leaders of P, S and C finish systems).
+__device__ __forceinline__ bool all_done(const MultiArgs& a) {
+    __shared__ int flag;
+    if (threadIdx.x == 0) flag = *a.ndone >= a.B;
+    __syncthreads();
+    return flag != 0;
+}
+
+template <int BL> __device__ __forceinline__ double* mregion(const MultiArgs& a, int comp) {
+    return a.part + (size_t)comp * a.geo.G * BL;
+}
+
+// The leader of system j: lane j of row slot 0 in logical block 0.
+template <int BL> __device__ __forceinline__ bool mleader(int lb) { return lb == 0 && threadIdx.x < BL; }
+
+// Row i of A times X for lane j: entries in order, U loads of each kind in flight.
+template <int U>
+__device__ __forceinline__ double2 mrow(const MultiArgs& a, int64_t i, int j, const double2* __restrict__ X) {
+    const size_t B = (size_t)a.B;
+    const int beg = a.row_ptr[i], end = a.row_ptr[i + 1];
+    double2 acc = mk<double>(0.0, 0.0);
+    int p = beg;
+    for (; p + U <= end; p += U) {
+        int c[U];
+        double2 av[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = a.col_idx[p + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) av[u] = a.vals[(size_t)(p + u) * B + j];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = X[(size_t)c[u] * B + j];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc = cfma<double>(av[u], xv[u], acc);
+    }
+    for (; p < end; ++p) acc = cfma<double>(a.vals[(size_t)p * B + j], X[(size_t)a.col_idx[p] * B + j], acc);
+    return acc;
+}
+
+#define HZ_MULTI_ROWS                                       \
+    constexpr int S = kBlock / BL;                          \
+    const RowRange rr = rows_of_block(a.n, a.geo);          \
+    const int g = threadIdx.x / BL, j = threadIdx.x % BL;   \
+    const size_t Bz = (size_t)a.B;                          \
+    (void)Bz
+
+// Solve set-up: r = src, rhat = src; partials <rhat,r>, ||r||^2 (C), ||b||^2 (I).
+template <int BL>
+__global__ HZ_STREAM_BOUNDS void k_m_init(const MultiArgs a, const double2* src) {
+    HZ_MULTI_ROWS;
+    double e[3] = {0.0, 0.0, 0.0}, eb[1] = {0.0};
+    if (j < a.B)
+        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+            const size_t q = (size_t)i * Bz + j;
+            const double2 bv = a.b[q], rv = src[q];
+            if (a.r != src) a.r[q] = rv;
+            a.rh[q] = rv;
+            eb[0] = __builtin_fma(bv.x, bv.x, eb[0]);
+            eb[0] = __builtin_fma(bv.y, bv.y, eb[0]);
+            const double2 c = cdotacc(rv.x, rv.y, rv.x, rv.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+            e[2] = __builtin_fma(rv.x, rv.x, e[2]);
+            e[2] = __builtin_fma(rv.y, rv.y, e[2]);
+        }
+    mstore<BL, 3>(mregion<BL>(a, kPartC), a.geo.G, rr.lb, e);
+    mstore<BL, 1>(mregion<BL>(a, kPartI), a.geo.G, rr.lb, eb);
+}
+
+// ||b||, initial convergence test of every system (one block).
+template <int BL>
+__global__ HZ_STREAM_BOUNDS void k_m_fin_init(const MultiArgs a) {
+    double hb[1], hr[3];
+    mhead<BL, 1>(mregion<BL>(a, kPartI), a.geo.G, hb);
+    mhead<BL, 3>(mregion<BL>(a, kPartC), a.geo.G, hr);
+    const int j = threadIdx.x;
+    if (j >= a.B) return;  // lanes of slot 0 only (B <= BL)
+    SolverScal* sc = a.sc + j;
+    const double bn = __builtin_sqrt(hb[0]);
+    sc->bnorm = bn;
+    sc->iter = 1;
+    sc->cur = 0;
+    sc->done = 0;
+    sc->zero_x = 0;
+    sc->iters = 0;
+    sc->pending = 0;
+    sc->status = ST_NOT_CONVERGED;
+    sc->alpha = sc->omega = sc->beta = mk<double>(1.0, 0.0);
+    if (!__builtin_isfinite(bn) || !__builtin_isfinite(hr[2])) return finish(sc, a.ndone, ST_NONFINITE, 0);
+    if (bn == 0.0) {
+        sc->zero_x = 1;
+        sc->relres = 0.0;
+        return finish(sc, a.ndone, ST_OK, 0);
+    }
+    const double rel = __builtin_sqrt(hr[2]) / bn;
+    sc->relres = rel;
+    if (rel <= sc->rtol) finish(sc, a.ndone, ST_OK, 0);
+    else if (sc->maxiter <= 0) finish(sc, a.ndone, ST_NOT_CONVERGED, 0);
+}
+
+// P-kernel: end of iteration i-1 and beta per system (as in the single
+// solve), then p = r + beta (p - omega v) on the system's lanes.
+template <int BL>
+__global__ HZ_STREAM_BOUNDS void k_m_P(const MultiArgs a) {
+    if (all_done(a)) return;
+    HZ_MULTI_ROWS;
+    double h[3];
+    mhead<BL, 3>(mregion<BL>(a, kPartC), a.geo.G, h);
+    if (j >= a.B) return;
+    SolverScal* sc = a.sc + j;
+    const bool lead = mleader<BL>(rr.lb);
+    if (sc->done) return;
+    if (sc->pending) {  // the half step's x += alpha p is complete everywhere
+        if (lead) finish(sc, a.ndone, ST_OK, sc->pending);
+        return;
+    }
+    const int it = sc->iter;
+    const double2 rho = mk<double>(h[0], h[1]);
+    double2 beta = mk<double>(0.0, 0.0), om = mk<double>(0.0, 0.0);
+    if (it > 1) {
+        const double rel = __builtin_sqrt(h[2]) / sc->bnorm;
+        om = sc->omega;
+        int stt = -1, sit = 0;
+        if (!__builtin_isfinite(rel)) stt = ST_NONFINITE, sit = it - 1;
+        else if (rel <= sc->rtol) stt = ST_OK, sit = it - 1;
+        else if (zzero(om)) stt = ST_BREAKDOWN, sit = it - 1;
+        else if (it - 1 >= sc->maxiter) stt = ST_NOT_CONVERGED, sit = sc->maxiter;
+        else if (!zfinite(rho)) stt = ST_NONFINITE, sit = it;
+        else if (zzero(rho)) stt = ST_BREAKDOWN, sit = it;
+        else {
+            beta = zmul(zdiv(rho, sc->rho2[(it - 1) & 1]), zdiv(sc->alpha, om));
+            if (!zfinite(beta)) stt = ST_NONFINITE, sit = it;
+        }
+        if (lead) sc->relres = rel;
+        if (stt >= 0) {
+            if (lead) finish(sc, a.ndone, stt, sit);
+            return;
+        }
+    }
+    if (lead) {
+        sc->rho2[it & 1] = rho;
+        sc->beta = beta;
+        sc->cur = it;
+    }
+    for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+        const size_t q = (size_t)i * Bz + j;
+        const double2 rv = a.r[q];
+        if (it == 1) {
+            a.p[q] = rv;
+        } else {
+            const double2 pv = a.p[q], vv = a.v[q];
+            const double2 d = mk<double>(pv.x - __builtin_fma(om.x, vv.x, -om.y * vv.y),
+                                         pv.y - __builtin_fma(om.x, vv.y, om.y * vv.x));
+            a.p[q] = cfma<double>(beta, d, rv);
+        }
+    }
+}
+
+// A1-kernel: v = A p; partial <rhat, v>.
+template <int BL, int U>
+__global__ HZ_STREAM_BOUNDS void k_m_A1(const MultiArgs a) {
+    if (all_done(a)) return;
+    HZ_MULTI_ROWS;
+    double e[2] = {0.0, 0.0};
+    if (j < a.B && !a.sc[j].done && !a.sc[j].pending)
+        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+            const double2 acc = mrow<U>(a, i, j, a.p);
+            const size_t q = (size_t)i * Bz + j;
+            a.v[q] = acc;
+            const double2 w = a.rh[q];
+            const double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+        }
+    mstore<BL, 2>(mregion<BL>(a, kPartA), a.geo.G, rr.lb, e);
+}
+
+// S-kernel: alpha = rho / <rhat, v>; s = r - alpha v; partial ||s||^2.
+template <int BL>
+__global__ HZ_STREAM_BOUNDS void k_m_S(const MultiArgs a) {
+    if (all_done(a)) return;
+    HZ_MULTI_ROWS;
+    double h[2], e[1] = {0.0};
+    mhead<BL, 2>(mregion<BL>(a, kPartA), a.geo.G, h);
+    bool go = j < a.B;
+    double2 alpha = mk<double>(0.0, 0.0);
+    if (go) {
+        SolverScal* sc = a.sc + j;
+        go = !sc->done && !sc->pending;
+        if (go) {
+            const int it = sc->cur;
+            const double2 sigma = mk<double>(h[0], h[1]);
+            if (!zfinite(sigma) || zzero(sigma)) {
+                if (mleader<BL>(rr.lb)) finish(sc, a.ndone, zzero(sigma) ? ST_BREAKDOWN : ST_NONFINITE, it);
+                go = false;
+            } else {
+                alpha = zdiv(sc->rho2[it & 1], sigma);
+                if (mleader<BL>(rr.lb)) sc->alpha = alpha;
+            }
+        }
+    }
+    if (go) {
+        const double2 nal = mk<double>(-alpha.x, -alpha.y);
+        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+            const size_t q = (size_t)i * Bz + j;
+            const double2 sv = cfma<double>(nal, a.v[q], a.r[q]);
+            a.s[q] = sv;
+            e[0] = __builtin_fma(sv.x, sv.x, e[0]);
+            e[0] = __builtin_fma(sv.y, sv.y, e[0]);
+        }
+    }
+    mstore<BL, 1>(mregion<BL>(a, kPartB), a.geo.G, rr.lb, e);
+}
+
+// B1-kernel: t = A s; partials <t, s>, ||t||^2.
+template <int BL, int U>
+__global__ HZ_STREAM_BOUNDS void k_m_B1(const MultiArgs a) {
+    if (all_done(a)) return;
+    HZ_MULTI_ROWS;
+    double e[3] = {0.0, 0.0, 0.0};
+    if (j < a.B && !a.sc[j].done)
+        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+            const double2 acc = mrow<U>(a, i, j, a.s);
+            const size_t q = (size_t)i * Bz + j;
+            a.t[q] = acc;
+            const double2 sv = a.s[q];
+            const double2 c = cdotacc(acc.x, acc.y, sv.x, sv.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+            e[2] = __builtin_fma(acc.x, acc.x, e[2]);
+            e[2] = __builtin_fma(acc.y, acc.y, e[2]);
+        }
+    mstore<BL, 3>(mregion<BL>(a, kPartB + 1), a.geo.G, rr.lb, e);
+}
+
+// C-kernel: half-step test on ||s||; omega; x += alpha p + omega s;
+// r = s - omega t; partials <rhat, r>, ||r||^2.
+template <int BL>
+__global__ HZ_STREAM_BOUNDS void k_m_C(const MultiArgs a) {
+    if (all_done(a)) return;
+    HZ_MULTI_ROWS;
+    double h[4], e[3] = {0.0, 0.0, 0.0};
+    mhead<BL, 4>(mregion<BL>(a, kPartB), a.geo.G, h);
+    int mode = 0;  // 0: nothing, 1: half-step exit, 2: full step
+    double2 al = mk<double>(0.0, 0.0), om = mk<double>(0.0, 0.0);
+    if (j < a.B) {
+        SolverScal* sc = a.sc + j;
+        const bool lead = mleader<BL>(rr.lb);
+        // pending is written by this kernel's leader, so only done is read
+        // here (a pending exit of the previous iteration was concluded by P)
+        if (!sc->done) {
+            const int it = sc->cur;
+            const double rel = __builtin_sqrt(h[0]) / sc->bnorm;
+            al = sc->alpha;
+            if (!__builtin_isfinite(rel)) {
+                if (lead) finish(sc, a.ndone, ST_NONFINITE, it);
+            } else if (rel <= sc->rtol) {  // concluded by the next P-kernel
+                mode = 1;
+                if (lead) {
+                    sc->relres = rel;
+                    sc->pending = it;
+                }
+            } else {
+                const double2 ts = mk<double>(h[1], h[2]);
+                const double tt = h[3];
+                int st = -1;
+                if (!zfinite(ts) || !__builtin_isfinite(tt)) st = ST_NONFINITE;
+                else if (tt == 0.0) st = ST_BREAKDOWN;
+                else {
+                    om = zdiv(ts, mk<double>(tt, 0.0));
+                    if (!zfinite(om)) st = ST_NONFINITE;
+                }
+                if (st >= 0) {
+                    if (lead) finish(sc, a.ndone, st, it);
+                } else {
+                    mode = 2;
+                    if (lead) {
+                        sc->omega = om;
+                        sc->iter = it + 1;
+                    }
+                }
+            }
+        }
+    }
+    if (mode == 1) {
+        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+            const size_t q = (size_t)i * Bz + j;
+            a.x[q] = cfma<double>(al, a.p[q], a.x[q]);
+        }
+    } else if (mode == 2) {
+        const double2 nom = mk<double>(-om.x, -om.y);
+        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+            const size_t q = (size_t)i * Bz + j;
+            const double2 sv = a.s[q], tv = a.t[q], rh = a.rh[q];
+            double2 x = a.x[q];
+            x = cfma<double>(al, a.p[q], x);
+            x = cfma<double>(om, sv, x);
+            a.x[q] = x;
+            const double2 r = cfma<double>(nom, tv, sv);
+            a.r[q] = r;
+            const double2 c = cdotacc(rh.x, rh.y, r.x, r.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+            e[2] = __builtin_fma(r.x, r.x, e[2]);
+            e[2] = __builtin_fma(r.y, r.y, e[2]);
+        }
+    }
+    mstore<BL, 3>(mregion<BL>(a, kPartC), a.geo.G, rr.lb, e);
+}
+
+// y = b - A xin for every system (values `vals`); partial ||y||^2 (I).
+template <int BL, int U>
+__global__ HZ_STREAM_BOUNDS void k_m_resid(const MultiArgs a, const double2* __restrict__ vals,
+                                           const double2* __restrict__ xin, double2* __restrict__ y) {
+    HZ_MULTI_ROWS;
+    MultiArgs a2 = a;
+    a2.vals = vals;
+    double e[1] = {0.0};
+    if (j < a.B)
+        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+            const double2 acc = mrow<U>(a2, i, j, xin);
+            const size_t q = (size_t)i * Bz + j;
+            const double2 bv = a.b[q];
+            const double2 d = mk<double>(bv.x - acc.x, bv.y - acc.y);
+            y[q] = d;
+            e[0] = __builtin_fma(d.x, d.x, e[0]);
+            e[0] = __builtin_fma(d.y, d.y, e[0]);
+        }
+    mstore<BL, 1>(mregion<BL>(a, kPartI), a.geo.G, rr.lb, e);
+}
+
+// relres_true of every system from region I (one block).
+template <int BL>
+__global__ HZ_STREAM_BOUNDS void k_m_fin_true(const MultiArgs a) {
+    double h[1];
+    mhead<BL, 1>(mregion<BL>(a, kPartI), a.geo.G, h);
+    const int j = threadIdx.x;
+    if (j >= a.B) return;
+    SolverScal* sc = a.sc + j;
+    sc->relres_true = sc->bnorm > 0.0 ? __builtin_sqrt(h[0]) / sc->bnorm : 0.0;
+}
+
+// x = 0 for the systems whose right-hand side is zero.
+template <int BL>
+__global__ HZ_STREAM_BOUNDS void k_m_zero_if(const MultiArgs a) {
+    HZ_MULTI_ROWS;
+    if (j >= a.B || !a.sc[j].zero_x) return;
+    for (int64_t i = rr.r0 + g; i < rr.r1; i += S) a.x[(size_t)i * Bz + j] = mk<double>(0.0, 0.0);
+}
+
+// dinv[i*B + j] = 1 / A_j(i, i); a missing or zero diagonal flags sc[j].bad_diag.
+__global__ __launch_bounds__(kBlock) void k_m_jacobi(int n, int B, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci, const double2* __restrict__ vals,
+                                                     double2* __restrict__ dinv, SolverScal* sc) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f >= (int64_t)n * B) return;
+    const int64_t i = f / B;
+    const int j = (int)(f % B);
+    double2 d = mk<double>(0.0, 0.0);
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (ci[p] == i) d = vals[(size_t)p * B + j];
+    if (d.x == 0.0 && d.y == 0.0) {
+        sc[j].bad_diag = 1;  // every writer stores 1
+        dinv[f] = mk<double>(0.0, 0.0);
+        return;
+    }
+    const double q = d.x * d.x + d.y * d.y;
+    dinv[f] = mk<double>(d.x / q, -d.y / q);
+}
+
+// out[p*B + j] = vals[p*B + j] * dinv[col_p*B + j]   (A_j D_j^{-1})
+__global__ __launch_bounds__(kBlock) void k_m_colscale(int64_t nnz, int B, const int* __restrict__ ci,
+                                                       const double2* __restrict__ vals,
+                                                       const double2* __restrict__ dinv, double2* __restrict__ out) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f >= nnz * B) return;
+    const int64_t p = f / B;
+    const int j = (int)(f % B);
+    out[f] = cmul<double>(vals[f], dinv[(size_t)ci[p] * B + j]);
+}
+
+}  // namespace hz

@@ -47,7 +47,7 @@ def block_diag(systems):
 
 def solve_batch(hz, systems, tol, flags, maxiter=20000):
     row_off, A, b = block_diag(systems)
-    x, infos = hz.zbicgstab_solve_batched(row_off, dev(A.row_ptr), dev(A.col_idx), dev(A.vals), dev(b), rtol=tol,
+    x, infos = hz.zbicgstab_solve_varbatch(row_off, dev(A.row_ptr), dev(A.col_idx), dev(A.vals), dev(b), rtol=tol,
                                           maxiter=maxiter, flags=flags)
     x = x.cpu().numpy()
     return [x[row_off[j]:row_off[j + 1]] for j in range(len(systems))], infos

@@ -342,6 +342,7 @@ def test_solve_cabin_full_size_permuted(hz):
     rp, ci, v = dev_csr(A)
     x, sinfo = hz.zbicgstab_solve(rp, ci, v, dev(b), rtol=1e-8, maxiter=50000, flags=hz.PRECOND_JACOBI)
     assert sinfo["status"] == hz.OK, sinfo
+    assert sinfo["renumbered"] == 1  # the random numbering is replaced by level sets
     x = x.cpu().numpy()
     rr = true_relres(A, x, b)
     print(f"cabin n={A.n} nnz={A.nnz} iterations={sinfo['iterations']} true relres={rr:.3e}")
