@@ -87,6 +87,22 @@ const char *hz_strerror(int code);
 int csr_zspmv(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
               const hz_c128 *vals, const hz_c128 *x, hz_c128 *y);
 
+/*
+ * Autotuner of the product's launch shape (rows per wavefront).  Every
+ * product and solve kernel gives a row L lanes (L = 2 ... 64, so 64/L rows
+ * per wavefront); the built-in rule takes the smallest power of two not
+ * below half the mean row length.  This call times csr_zspmv with each L on
+ * the caller's matrix and vectors (two rounds of 5 launches after 2 warm-up
+ * launches, HIP events on `stream`), writes the fastest L to *lanes (host)
+ * and records it in the handle for this (row_ptr, col_idx, n, nnz): later
+ * products and solves on the same handle with the same index arrays use
+ * it (results change only by summation order).  y is overwritten with A x.
+ * Synchronises the stream.  The environment variable HZ_SPMV_LANES, when
+ * set, overrides both the rule and the tuned choice.
+ */
+int hz_autotune_spmv(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+                     const hz_c128 *vals, const hz_c128 *x, hz_c128 *y, int *lanes);
+
 /* Same product with complex64 values, vectors and arithmetic. */
 int csr_cspmv(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
               const hz_c64 *vals, const hz_c64 *x, hz_c64 *y);
@@ -237,6 +253,26 @@ int zbicgstab_adjoint(hz_handle *handle, hz_stream stream, int n, int nnz, const
                       const hz_c128 *vals, const hz_c128 *x, const hz_c128 *grad_x, hz_c128 *grad_b,
                       hz_c128 *grad_vals, double rtol, int maxiter, int flags, void *ws, size_t ws_bytes,
                       hz_solve_info *info);
+
+/* Device workspace (bytes) that zbicgstab_adjoint_batched needs. */
+size_t zbicgstab_adjoint_batched_workspace_bytes(int nsys, int n, int nnz, int flags);
+
+/*
+ * Backward of a shared-pattern batch x_j = A_j^{-1} b_j (zbicgstab_solve_batched,
+ * same layout: vals [nnz][nsys], vectors [n][nsys]): for every system solve
+ * A_j^H lambda_j = grad_x_j by the batched BiCGStab (rtol, maxiter,
+ * HZ_PRECOND_JACOBI; zero initial guess), write grad_b = lambda and, if
+ * grad_vals is not NULL, grad_vals[p*nsys + j] = -lambda_j[i] conj(x_j[c])
+ * for entry p = (i, c).  With HZ_SYMMETRIC every A_j = A_j^T is asserted
+ * and the solves run on conjugated right-hand sides; otherwise the
+ * transposed pattern and each system's conjugate-transposed values are
+ * formed in the workspace.  infos is a HOST array of nsys results of the
+ * adjoint solves; returns the largest status.  Synchronises the stream.
+ */
+int zbicgstab_adjoint_batched(hz_handle *handle, hz_stream stream, int nsys, int n, int nnz, const int *row_ptr,
+                              const int *col_idx, const hz_c128 *vals, const hz_c128 *x, const hz_c128 *grad_x,
+                              hz_c128 *grad_b, hz_c128 *grad_vals, double rtol, int maxiter, int flags, void *ws,
+                              size_t ws_bytes, hz_solve_info *infos);
 
 /* Device workspace (bytes) for csr_level_order and csr_zpermute. */
 size_t csr_reorder_workspace_bytes(int n, int nnz);

@@ -16,6 +16,7 @@ from .binding import (  # noqa: F401
     SYMMETRIC,
     VALIDATE,
     X0_ZERO,
+    autotune_spmv,
     csr_cspmv,
     csr_level_order,
     csr_reorder_workspace_bytes,
@@ -32,6 +33,8 @@ from .binding import (  # noqa: F401
     zbicgstab_solve,
     zbicgstab_solve_mixed,
     zbicgstab_adjoint,
+    zbicgstab_adjoint_batched,
+    zbicgstab_adjoint_batched_workspace_bytes,
     zbicgstab_batched_workspace_bytes,
     zbicgstab_solve_batched,
     zbicgstab_varbatch_workspace_bytes,
@@ -40,5 +43,13 @@ from .binding import (  # noqa: F401
     zbicgstab_workspace_bytes,
     zdotc,
 )
-from .autograd import EntryMap, HelmholtzSolve, SolveOptions, entry_map, helmholtz_solve  # noqa: F401
+from .autograd import (  # noqa: F401
+    EntryMap,
+    HelmholtzSolve,
+    HelmholtzSolveBatched,
+    SolveOptions,
+    entry_map,
+    helmholtz_solve,
+    helmholtz_solve_batched,
+)
 from ._lib import HelmzError, lib_path, load  # noqa: F401

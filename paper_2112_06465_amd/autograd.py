@@ -3,7 +3,9 @@
 ``helmholtz_solve(row_ptr, col_idx, vals, b)`` returns x = A^{-1} b
 (zbicgstab_solve); its backward runs one adjoint solve (zbicgstab_adjoint)
 and returns grad_b = lambda and grad_vals = -lambda_i conj(x_j), in torch's
-real-pair convention for complex gradients.  ``entry_map`` expresses matrix
+real-pair convention for complex gradients.  ``helmholtz_solve_batched`` does
+the same for B systems on one pattern (zbicgstab_solve_batched /
+zbicgstab_adjoint_batched).  ``entry_map`` expresses matrix
 entries as an affine function vals = vals0 + Phi beta of parameters beta
 (Phi sparse, nnz x m, held as CSR together with Phi^H); its backward is
 the rectangular SpMV Phi^H grad_vals (csr_zspmv_rect).  All arithmetic runs
@@ -59,6 +61,40 @@ class HelmholtzSolve(torch.autograd.Function):
 def helmholtz_solve(row_ptr, col_idx, vals, b, opts: SolveOptions | None = None):
     """Differentiable x = A^{-1} b on the GPU."""
     return HelmholtzSolve.apply(vals, b, row_ptr, col_idx, opts or SolveOptions())
+
+
+class HelmholtzSolveBatched(torch.autograd.Function):
+    """x[:, j] = A_j^{-1} b[:, j] for B systems on one pattern (vals (nnz, B), b (n, B))."""
+
+    @staticmethod
+    def forward(ctx, vals, b, row_ptr, col_idx, opts: SolveOptions):
+        x, infos = B.zbicgstab_solve_batched(row_ptr, col_idx, vals.detach().contiguous(), b.detach().contiguous(),
+                                             rtol=opts.rtol, maxiter=opts.maxiter, flags=opts.flags & B.PRECOND_JACOBI)
+        bad = [i for i in infos if i["status"] != B.OK]
+        if bad:
+            raise RuntimeError(f"forward solve did not converge: {bad[0]}")
+        ctx.save_for_backward(vals.detach().contiguous(), x, row_ptr, col_idx)
+        ctx.opts = opts
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        vals, x, row_ptr, col_idx = ctx.saved_tensors
+        opts = ctx.opts
+        need_vals = ctx.needs_input_grad[0]
+        grad_b, grad_vals, infos = B.zbicgstab_adjoint_batched(row_ptr, col_idx, vals, x,
+                                                               gx.to(torch.complex128).contiguous(), rtol=opts.rtol,
+                                                               maxiter=opts.maxiter, flags=opts.flags,
+                                                               want_grad_vals=need_vals)
+        bad = [i for i in infos if i["status"] != B.OK]
+        if bad:
+            raise RuntimeError(f"adjoint solve did not converge: {bad[0]}")
+        return grad_vals, (grad_b if ctx.needs_input_grad[1] else None), None, None, None
+
+
+def helmholtz_solve_batched(row_ptr, col_idx, vals, b, opts: SolveOptions | None = None):
+    """Differentiable X = [A_j^{-1} b_j] for B systems sharing one pattern."""
+    return HelmholtzSolveBatched.apply(vals, b, row_ptr, col_idx, opts or SolveOptions())
 
 
 class EntryMap(torch.autograd.Function):

@@ -92,6 +92,23 @@ def csr_zspmv(row_ptr, col_idx, vals, x, y=None):
     return y
 
 
+def autotune_spmv(row_ptr, col_idx, vals, x=None) -> int:
+    """Time every lane count on this matrix and keep the fastest for it (hz_autotune_spmv); returns it."""
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    if x is None:
+        g = torch.Generator(device="cpu").manual_seed(0)
+        x = torch.randn(n, dtype=torch.complex128, generator=g).to(dev)
+    _need(x, "x", torch.complex128, dev)
+    if x.numel() != n:
+        raise ValueError("x has the wrong length")
+    y = torch.empty(n, dtype=torch.complex128, device=dev)
+    L = C.c_int(0)
+    rc = load().hz_autotune_spmv(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                                 vals.data_ptr(), x.data_ptr(), y.data_ptr(), C.byref(L))
+    _check("hz_autotune_spmv", rc)
+    return int(L.value)
+
+
 def csr_cspmv(row_ptr, col_idx, vals, x, y=None):
     """y = A x, complex64 CSR (csr_cspmv)."""
     dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex64)
@@ -389,6 +406,52 @@ def zbicgstab_solve_batched(row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxite
                                         int(maxiter), int(flags), wp, wbytes, C.cast(infos, C.c_void_p))
     _check("zbicgstab_solve_batched", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
     return x, [i.as_dict() for i in infos]
+
+
+def zbicgstab_adjoint_batched_workspace_bytes(nsys: int, n: int, nnz: int, flags: int = 0) -> int:
+    return int(load().zbicgstab_adjoint_batched_workspace_bytes(int(nsys), int(n), int(nnz), int(flags)))
+
+
+def zbicgstab_adjoint_batched(row_ptr, col_idx, vals, x, grad_x, rtol=1e-10, maxiter=20000, flags=PRECOND_NONE,
+                              want_grad_vals=True, ws=None):
+    """Backward of a shared-pattern batch (zbicgstab_adjoint_batched).
+
+    ``vals`` (nnz, B), ``x`` and ``grad_x`` (n, B).  Returns
+    (grad_b (n, B), grad_vals (nnz, B) or None, [info per system]).
+    """
+    dev = vals.device
+    _need(row_ptr, "row_ptr", torch.int32, dev)
+    _need(col_idx, "col_idx", torch.int32, dev)
+    _need(vals, "vals", torch.complex128, dev)
+    n, nnz = row_ptr.numel() - 1, col_idx.numel()
+    if vals.dim() != 2 or vals.shape[0] != nnz:
+        raise ValueError("vals must be (nnz, B)")
+    nsys = vals.shape[1]
+    _need(grad_x, "grad_x", torch.complex128, dev)
+    if tuple(grad_x.shape) != (n, nsys):
+        raise ValueError("grad_x must be (n, B)")
+    grad_b = torch.empty(n, nsys, dtype=torch.complex128, device=dev)
+    grad_vals = None
+    if want_grad_vals:
+        _need(x, "x", torch.complex128, dev)
+        if tuple(x.shape) != (n, nsys):
+            raise ValueError("x must be (n, B)")
+        grad_vals = torch.empty(nnz, nsys, dtype=torch.complex128, device=dev)
+    need = zbicgstab_adjoint_batched_workspace_bytes(nsys, n, nnz, flags)
+    if need == 0:
+        raise ValueError("unsupported batch size")
+    if ws is None:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    _need(ws, "ws", torch.uint8, dev)
+    wp, wbytes = _aligned_ptr(ws, need)
+    infos = (HzInfo * nsys)()
+    rc = load().zbicgstab_adjoint_batched(handle(dev), _stream(dev), nsys, n, nnz, row_ptr.data_ptr(),
+                                          col_idx.data_ptr(), vals.data_ptr(), x.data_ptr() if want_grad_vals else None,
+                                          grad_x.data_ptr(), grad_b.data_ptr(),
+                                          grad_vals.data_ptr() if want_grad_vals else None, float(rtol), int(maxiter),
+                                          int(flags), wp, wbytes, C.cast(infos, C.c_void_p))
+    _check("zbicgstab_adjoint_batched", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
+    return grad_b, grad_vals, [i.as_dict() for i in infos]
 
 
 def csr_reorder_workspace_bytes(n: int, nnz: int) -> int:

@@ -26,8 +26,18 @@ using hz::kMaxGrid;
 using hz::kParts;
 using hz::SolverScal;
 
+// A lane count picked by hz_autotune_spmv for one matrix (by its index arrays).
+struct TuneEntry {
+    const int* rp;
+    const int* ci;
+    int n;
+    int64_t nnz;
+    int L;
+};
+
 struct hz_handle {
     int device;
+    std::vector<TuneEntry> tune;  // autotuned lanes per row, newest last
     double* part;          // kParts * kMaxGrid partials for standalone reductions
     int* dflag;            // device word for CSR validation
     unsigned long long* dcount;  // device counter for the locality test
@@ -59,15 +69,24 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 // Lanes per row for the vector-CSR kernels: the smallest power of two not
 // below half the mean row length, in [2, 64], so each lane holds about two
 // entries of a row.  HZ_SPMV_LANES overrides (tuning).
-int pick_lanes(int n, int64_t nnz) {
-    if (const char* env = std::getenv("HZ_SPMV_LANES")) {
-        int v = std::atoi(env);
-        if (v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64) return v;
-    }
+int rule_lanes(int n, int64_t nnz) {
     const double mean = n > 0 ? double(nnz) / double(n) : 1.0;
     int L = 2;
     while (L < 64 && 2 * L < mean) L *= 2;
     return L;
+}
+
+// The lane count for a matrix: HZ_SPMV_LANES if set, else the handle's
+// autotuned choice for these index arrays, else the rule above.
+int pick_lanes(const hz_handle* h, const int* rp, const int* ci, int n, int64_t nnz) {
+    if (const char* env = std::getenv("HZ_SPMV_LANES")) {
+        int v = std::atoi(env);
+        if (v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64) return v;
+    }
+    if (h != nullptr)
+        for (auto it = h->tune.rbegin(); it != h->tune.rend(); ++it)
+            if (it->rp == rp && it->ci == ci && it->n == n && it->nnz == nnz) return it->L;
+    return rule_lanes(n, nnz);
 }
 
 // Contiguous chunks of rows per block (see hz_kernels.hpp): G <= kMaxGrid
@@ -341,7 +360,7 @@ int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nn
                hz_solve_info* infos) {
     const int n = row_off[nsys] - row_off[0];
     const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
-    const int L = pick_lanes(n, nnz);
+    const int L = pick_lanes(h, rp, ci, n, nnz);
     const WorkMap m = build_map(nsys, row_off, L);
     SolveWs w;
     ws_layout<double>(n, nnz, jacobi, nsys, m.G, ws, &w);
@@ -519,7 +538,7 @@ int permute_csr(hipStream_t s, int n, int nnz, const int* rp, const int* ci, con
     if (nnz > 0) {
         hipLaunchKernelGGL(hz::k_perm_fill, grid1(int64_t(n) * 8), dim3(kBlock), 0, s, n, rp, ci, v, perm, inv,
                            static_cast<const int*>(rp2), ci2, v2);
-        hipLaunchKernelGGL(hz::k_row_sort, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(rp2), ci2, v2);
+        hipLaunchKernelGGL(hz::k_row_sort<double2>, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(rp2), ci2, v2);
     }
     HZ_HIP(hipGetLastError());
     return HZ_OK;
@@ -781,6 +800,41 @@ int solve_multi(hz_handle* h, hipStream_t s, int B, int n, int nnz, const int* r
     return worst;
 }
 
+// Batched adjoint workspace: the batched solver's workspace, conj(g) [n][B]
+// and, unless A_j = A_j^T is asserted, the transposed pattern with the source
+// entry of each transposed entry and the conjugate-transposed values [nnz][B].
+struct AdjMultiWs {
+    char* solve;
+    double2* gconj;
+    int* t_rp;
+    int* t_ci;
+    int* t_src;
+    int* fill;
+    double2* t_vals;
+};
+
+size_t adjoint_multi_layout(int B, int n, int64_t nnz, int flags, char* base, AdjMultiWs* out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const size_t nn = size_t(n > 0 ? n : 1), nz = size_t(nnz > 0 ? nnz : 1);
+    AdjMultiWs a{};
+    a.solve = static_cast<char*>(take(multi_layout(B, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr)));
+    a.gconj = static_cast<double2*>(take(sizeof(double2) * nn * size_t(B)));
+    if (!(flags & HZ_SYMMETRIC)) {
+        a.t_rp = static_cast<int*>(take(sizeof(int) * (nn + 1)));
+        a.t_ci = static_cast<int*>(take(sizeof(int) * nz));
+        a.t_src = static_cast<int*>(take(sizeof(int) * nz));
+        a.fill = static_cast<int*>(take(sizeof(int) * nn));
+        a.t_vals = static_cast<double2*>(take(sizeof(double2) * nz * size_t(B)));
+    }
+    if (out) *out = a;
+    return off;
+}
+
 // Mixed refinement workspace: outer scalars, the complex64 solver's own
 // workspace (vectors, partials, scalars, map, D^{-1}, demoted matrix), the
 // FP64 residual and the complex64 right-hand side and correction.
@@ -920,12 +974,59 @@ static int spmv_common_checks(hz_handle* h, int n, int nnz, const int* rp, const
     return HZ_OK;
 }
 
+int hz_autotune_spmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci,
+                     const hz_c128* vals, const hz_c128* x, hz_c128* y, int* lanes) {
+    int rc = spmv_common_checks(h, n, nnz, rp, ci, vals, x, y, sizeof(hz_c128));
+    if (rc) return rc;
+    if (lanes == nullptr) return HZ_ERR_INVALID;
+    *lanes = rule_lanes(n, nnz);
+    if (n == 0) return HZ_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess) {
+        if (ev[0]) (void)hipEventDestroy(ev[0]);
+        return HZ_ERR_HIP;
+    }
+    constexpr int kCand[6] = {2, 4, 8, 16, 32, 64};
+    float best_ms[6];
+    for (float& b : best_ms) b = 1e30f;
+    rc = HZ_OK;
+    // two rounds over the candidates, 2 warm-up and 5 timed launches each; the faster round counts
+    for (int round = 0; round < 2 && rc == HZ_OK; ++round)
+        for (int c = 0; c < 6 && rc == HZ_OK; ++c) {
+            const int L = kCand[c];
+            const Geom geo = geom_for(n, kBlock / L);
+            auto a = spmv_args<double>(n, geo, rp, ci, reinterpret_cast<const double2*>(vals),
+                                       reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nullptr,
+                                       nullptr);
+            for (int k = 0; k < 2; ++k) launch_spmv<double, hz::EPI_NONE>(L, a, s);
+            if (hipEventRecord(ev[0], s) != hipSuccess) rc = HZ_ERR_HIP;
+            for (int k = 0; k < 5; ++k) launch_spmv<double, hz::EPI_NONE>(L, a, s);
+            float ms = 0.f;
+            if (rc == HZ_OK && (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                                hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+                rc = HZ_ERR_HIP;
+            if (rc == HZ_OK && ms < best_ms[c]) best_ms[c] = ms;
+        }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (rc) return rc;
+    int bc = 0;
+    for (int c = 1; c < 6; ++c)
+        if (best_ms[c] < best_ms[bc]) bc = c;
+    for (auto it = h->tune.begin(); it != h->tune.end();)
+        it = (it->rp == rp && it->ci == ci && it->n == n && it->nnz == nnz) ? h->tune.erase(it) : it + 1;
+    h->tune.push_back(TuneEntry{rp, ci, n, nnz, kCand[bc]});
+    *lanes = kCand[bc];
+    return HZ_OK;
+}
+
 int csr_zspmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c128* vals,
               const hz_c128* x, hz_c128* y) {
     int rc = spmv_common_checks(h, n, nnz, rp, ci, vals, x, y, sizeof(hz_c128));
     if (rc || n == 0) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int L = pick_lanes(n, nnz);
+    const int L = pick_lanes(h, rp, ci, n, nnz);
     const Geom geo = geom_for(n, kBlock / L);
     auto a = spmv_args<double>(n, geo, rp, ci, reinterpret_cast<const double2*>(vals),
                                reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nullptr, nullptr);
@@ -939,7 +1040,7 @@ int csr_cspmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, con
     int rc = spmv_common_checks(h, n, nnz, rp, ci, vals, x, y, sizeof(hz_c64));
     if (rc || n == 0) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int L = pick_lanes(n, nnz);
+    const int L = pick_lanes(h, rp, ci, n, nnz);
     const Geom geo = geom_for(n, kBlock / L);
     auto a = spmv_args<float>(n, geo, rp, ci, reinterpret_cast<const float2*>(vals), reinterpret_cast<const float2*>(x),
                               reinterpret_cast<float2*>(y), nullptr, nullptr);
@@ -1032,9 +1133,13 @@ static int check_row_off(int nsys, const int* row_off, int* n_total) {
 size_t zbicgstab_varbatch_workspace_bytes(int nsys, const int* row_off, int nnz, int flags) {
     int n = 0;
     if (nnz < 0 || check_row_off(nsys, row_off, &n) != HZ_OK) return 0;
-    const int L = pick_lanes(n, nnz);
-    const WorkMap m = build_map(nsys, row_off, L);
-    return ws_layout<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nsys, m.G, nullptr, nullptr);
+    // the lane count (hence the block count) is chosen per call: size for the largest map
+    size_t most = 0;
+    for (int L = 2; L <= 64; L *= 2) {
+        const WorkMap m = build_map(nsys, row_off, L);
+        most = std::max(most, ws_layout<double>(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nsys, m.G, nullptr, nullptr));
+    }
+    return most;
 }
 
 int zbicgstab_solve_varbatch(hz_handle* h, hz_stream stream, int nsys, const int* row_off, int nnz, const int* rp,
@@ -1077,7 +1182,7 @@ int solve_mixed(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, cons
     const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
     MixedWs mw;
     mixed_layout(n, nnz, jacobi, ws, &mw);
-    const int L = pick_lanes(n, nnz);
+    const int L = pick_lanes(h, rp, ci, n, nnz);
     const Geom geo = geom_for(n, kBlock / L);
     const int row_off[2] = {0, n};
     const WorkMap m = build_map(1, row_off, L);
@@ -1256,7 +1361,7 @@ int csr_zspmv_rect(hz_handle* h, hz_stream stream, int m, int ncols, int nnz, co
     if (misaligned(x, 16) || misaligned(y, 16) || misaligned(vals, 16)) return HZ_ERR_INVALID;
     if (ncols > 0 && overlap(x, 16 * size_t(ncols), y, 16 * size_t(m))) return HZ_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int L = pick_lanes(m, nnz);
+    const int L = pick_lanes(h, rp, ci, m, nnz);
     const Geom geo = geom_for(m, kBlock / L);
     auto a = spmv_args<double>(m, geo, rp, ci, reinterpret_cast<const double2*>(vals),
                                reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nullptr, nullptr);
@@ -1274,7 +1379,7 @@ int csr_zgrad_vals(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp
         return HZ_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
     launch_grad_vals(n, rp, ci, reinterpret_cast<const double2*>(lambda), reinterpret_cast<const double2*>(x),
-                     reinterpret_cast<double2*>(grad_vals), pick_lanes(n, nnz), s);
+                     reinterpret_cast<double2*>(grad_vals), pick_lanes(h, rp, ci, n, nnz), s);
     HZ_HIP(hipGetLastError());
     return HZ_OK;
 }
@@ -1325,7 +1430,7 @@ int zbicgstab_adjoint(hz_handle* h, hz_stream stream, int n, int nnz, const int*
         hipLaunchKernelGGL(hz::k_scan_1block, dim3(1), dim3(1024), 0, s, n + 1, a.t_rp);
         HZ_HIP(hipMemcpyAsync(a.fill, a.t_rp, sizeof(int) * size_t(n), hipMemcpyDeviceToDevice, s));
         hipLaunchKernelGGL(hz::k_tr_scatter, grid1(n), dim3(kBlock), 0, s, n, rp, ci, A, a.fill, a.t_ci, a.t_vals);
-        hipLaunchKernelGGL(hz::k_row_sort, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(a.t_rp), a.t_ci,
+        hipLaunchKernelGGL(hz::k_row_sort<double2>, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(a.t_rp), a.t_ci,
                            a.t_vals);
         HZ_HIP(hipGetLastError());
         rc = solve_single(h, s, n, nnz, a.t_rp, a.t_ci, a.t_vals, g, lam, rtol, maxiter, sflags, a.solve, info);
@@ -1333,10 +1438,87 @@ int zbicgstab_adjoint(hz_handle* h, hz_stream stream, int n, int nnz, const int*
     }
     if (grad_vals != nullptr && nnz > 0)
         launch_grad_vals(n, rp, ci, lam, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(grad_vals),
-                         pick_lanes(n, nnz), s);
+                         pick_lanes(h, rp, ci, n, nnz), s);
     HZ_HIP(hipGetLastError());
     HZ_HIP(hipStreamSynchronize(s));
     return info->status;
+}
+
+size_t zbicgstab_adjoint_batched_workspace_bytes(int nsys, int n, int nnz, int flags) {
+    if (nsys < 1 || nsys > hz::kMultiMax || n < 0 || nnz < 0) return 0;
+    return adjoint_multi_layout(nsys, n, nnz, flags, nullptr, nullptr);
+}
+
+int zbicgstab_adjoint_batched(hz_handle* h, hz_stream stream, int nsys, int n, int nnz, const int* rp, const int* ci,
+                              const hz_c128* vals, const hz_c128* x, const hz_c128* grad_x, hz_c128* grad_b,
+                              hz_c128* grad_vals, double rtol, int maxiter, int flags, void* ws, size_t ws_bytes,
+                              hz_solve_info* infos) {
+    if (h == nullptr || infos == nullptr || nsys < 1 || nsys > hz::kMultiMax) return HZ_ERR_INVALID;
+    std::memset(infos, 0, sizeof(hz_solve_info) * size_t(nsys));
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (!(rtol >= 0.0) || maxiter < 0) return HZ_ERR_INVALID;
+    if (int64_t(n) * nsys >= (int64_t(1) << 31)) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    const size_t vb = 16 * size_t(n) * size_t(nsys);
+    if (grad_x == nullptr || grad_b == nullptr || misaligned(grad_x, 16) || misaligned(grad_b, 16) ||
+        misaligned(vals, 16))
+        return HZ_ERR_INVALID;
+    if (grad_vals != nullptr && (x == nullptr || misaligned(x, 16) || misaligned(grad_vals, 16))) return HZ_ERR_INVALID;
+    if (overlap(grad_x, vb, grad_b, vb)) return HZ_ERR_INVALID;
+    AdjMultiWs a;
+    const size_t need = adjoint_multi_layout(nsys, n, nnz, flags, static_cast<char*>(ws), &a);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (flags & HZ_VALIDATE) {
+        rc = validate_csr(h, s, n, nnz, rp, ci);
+        if (rc) return rc;
+    }
+    const double2* A = reinterpret_cast<const double2*>(vals);
+    const double2* g = reinterpret_cast<const double2*>(grad_x);
+    double2* lam = reinterpret_cast<double2*>(grad_b);
+    const int64_t nB = int64_t(n) * nsys;
+    const int sflags = (flags & HZ_PRECOND_JACOBI) | HZ_X0_ZERO;
+    if (flags & HZ_SYMMETRIC) {
+        // A_j^H lambda_j = g_j  <=>  A_j conj(lambda_j) = conj(g_j)  when A_j = A_j^T
+        hipLaunchKernelGGL(hz::k_conj, grid1(nB), dim3(kBlock), 0, s, int(nB), g, a.gconj);
+        HZ_HIP(hipGetLastError());
+        rc = solve_multi(h, s, nsys, n, nnz, rp, ci, A, a.gconj, lam, rtol, maxiter, sflags, a.solve, infos);
+        if (rc < 0) return rc;
+        hipLaunchKernelGGL(hz::k_conj, grid1(nB), dim3(kBlock), 0, s, int(nB), static_cast<const double2*>(lam), lam);
+    } else {
+        // transposed pattern with source entries (count, scan, scatter, per-row sort), then conj values per system
+        HZ_HIP(hipMemsetAsync(a.t_rp, 0, sizeof(int) * (size_t(n) + 1), s));
+        if (nnz > 0) hipLaunchKernelGGL(hz::k_tr_count, grid1(nnz), dim3(kBlock), 0, s, int64_t(nnz), ci, a.t_rp);
+        hipLaunchKernelGGL(hz::k_scan_1block, dim3(1), dim3(1024), 0, s, n + 1, a.t_rp);
+        HZ_HIP(hipMemcpyAsync(a.fill, a.t_rp, sizeof(int) * size_t(n), hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(hz::k_tr_scatter_idx, grid1(n), dim3(kBlock), 0, s, n, rp, ci, a.fill, a.t_ci, a.t_src);
+        hipLaunchKernelGGL(hz::k_row_sort<int>, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(a.t_rp),
+                           a.t_ci, a.t_src);
+        if (nnz > 0)
+            hipLaunchKernelGGL(hz::k_m_conj_vals, grid1(int64_t(nnz) * nsys), dim3(kBlock), 0, s, int64_t(nnz), nsys,
+                               static_cast<const int*>(a.t_src), A, a.t_vals);
+        HZ_HIP(hipGetLastError());
+        rc = solve_multi(h, s, nsys, n, nnz, a.t_rp, a.t_ci, a.t_vals, g, lam, rtol, maxiter, sflags, a.solve, infos);
+        if (rc < 0) return rc;
+    }
+    if (grad_vals != nullptr && nnz > 0) {
+        const int BL = multi_lanes(nsys);
+        hz::MultiArgs m{};
+        m.n = n;
+        m.B = nsys;
+        m.geo = geom_for(n, kBlock / BL);
+        m.row_ptr = rp;
+        m.col_idx = ci;
+        with_multi(BL, [&]<int BB>() {
+            hipLaunchKernelGGL((hz::k_m_grad_vals<BB>), dim3(m.geo.G), dim3(kBlock), 0, s, m,
+                               static_cast<const double2*>(lam), reinterpret_cast<const double2*>(x),
+                               reinterpret_cast<double2*>(grad_vals));
+        });
+    }
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipStreamSynchronize(s));
+    return rc;
 }
 
 size_t csr_reorder_workspace_bytes(int n, int nnz) {

@@ -64,16 +64,32 @@ __global__ __launch_bounds__(kBlock) void k_tr_scatter(int n, const int* __restr
     }
 }
 
-// sort each row of a CSR matrix by column, carrying the values (insertion
-// sort; rows are short).  Used for the transpose and for P A P^T.
+// scatter entry p = (i, j) to row j of the transpose as column i, recording
+// its source index p (the values of several systems are gathered by it later)
+__global__ __launch_bounds__(kBlock) void k_tr_scatter_idx(int n, const int* __restrict__ rp,
+                                                           const int* __restrict__ ci, int* __restrict__ fill,
+                                                           int* __restrict__ tci, int* __restrict__ tsrc) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int q = atomicAdd(&fill[ci[p]], 1);
+        tci[q] = (int)i;
+        tsrc[q] = p;
+    }
+}
+
+// sort each row of a CSR matrix by column, carrying a payload per entry (the
+// values, or source entry indices); insertion sort, rows are short.  Used for
+// the transpose and for P A P^T.
+template <typename V>
 __global__ __launch_bounds__(kBlock) void k_row_sort(int n, const int* __restrict__ trp, int* __restrict__ tci,
-                                                    double2* __restrict__ tv) {
+                                                    V* __restrict__ tv) {
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
     const int lo = trp[j], hi = trp[j + 1];
     for (int q = lo + 1; q < hi; ++q) {
         const int c = tci[q];
-        const double2 a = tv[q];
+        const V a = tv[q];
         int k = q - 1;
         while (k >= lo && tci[k] > c) {
             tci[k + 1] = tci[k];

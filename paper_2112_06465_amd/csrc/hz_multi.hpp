@@ -483,4 +483,32 @@ __global__ __launch_bounds__(kBlock) void k_m_colscale(int64_t nnz, int B, const
     out[f] = cmul<double>(vals[f], dinv[(size_t)ci[p] * B + j]);
 }
 
+// Conjugate transposes of every system: tvals[q*B + j] = conj(vals[tsrc[q]*B + j]).
+__global__ __launch_bounds__(kBlock) void k_m_conj_vals(int64_t nnz, int B, const int* __restrict__ tsrc,
+                                                        const double2* __restrict__ vals,
+                                                        double2* __restrict__ tvals) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f >= nnz * B) return;
+    const int64_t q = f / B;
+    const int j = (int)(f % B);
+    const double2 a = vals[(size_t)tsrc[q] * B + j];
+    tvals[f] = mk<double>(a.x, -a.y);
+}
+
+// Entry gradients of every system: grad[p*B + j] = -lam_j[row_p] conj(x_j[col_p]).
+template <int BL>
+__global__ HZ_STREAM_BOUNDS void k_m_grad_vals(const MultiArgs a, const double2* __restrict__ lam,
+                                               const double2* __restrict__ xs, double2* __restrict__ grad) {
+    HZ_MULTI_ROWS;
+    if (j >= a.B) return;
+    for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+        const double2 l = lam[(size_t)i * Bz + j];
+        const double2 nl = mk<double>(-l.x, -l.y);
+        for (int p = a.row_ptr[i]; p < a.row_ptr[i + 1]; ++p) {
+            const double2 xv = xs[(size_t)a.col_idx[p] * Bz + j];
+            grad[(size_t)p * Bz + j] = cmul<double>(nl, mk<double>(xv.x, -xv.y));
+        }
+    }
+}
+
 }  // namespace hz

@@ -1,0 +1,71 @@
+"""The launch-shape autotuner: the tuned lane count is one of the product's
+own instantiations, so a product after tuning equals, bitwise, the product
+forced to that lane count; other index arrays keep the built-in rule."""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hz():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2112_06465_amd as hz
+
+    return hz
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def forced(hz, L, *args):
+    os.environ["HZ_SPMV_LANES"] = str(L)
+    try:
+        return hz.csr_zspmv(*args).cpu().numpy()
+    finally:
+        del os.environ["HZ_SPMV_LANES"]
+
+
+def test_tuned_lanes_are_used_bitwise_and_only_for_that_matrix(hz):
+    A, b, _ = W.config_cube(30, seed=1)
+    rp, ci, v = dev(A.row_ptr), dev(A.col_idx), dev(A.vals)
+    x = dev(np.random.default_rng(3).standard_normal(A.n) + 1j * np.random.default_rng(4).standard_normal(A.n))
+    os.environ.pop("HZ_SPMV_LANES", None)
+    rule = hz.csr_zspmv(rp.clone(), ci.clone(), v, x).cpu().numpy()  # fresh index arrays: never tuned
+    L = hz.autotune_spmv(rp, ci, v, x)
+    assert L in (2, 4, 8, 16, 32, 64)
+    y = hz.csr_zspmv(rp, ci, v, x).cpu().numpy()
+    assert np.array_equal(y.view(np.float64), forced(hz, L, rp, ci, v, x).view(np.float64))
+    yo = O.zspmv(A, x.cpu().numpy())
+    assert np.linalg.norm(y - yo) / np.linalg.norm(yo) <= 1e-14
+    # copies of the index arrays are another matrix for the handle: the rule applies
+    mean = A.nnz / A.n
+    Lr = 2
+    while Lr < 64 and 2 * Lr < mean:
+        Lr *= 2
+    r2 = hz.csr_zspmv(rp.clone(), ci.clone(), v, x).cpu().numpy()
+    assert np.array_equal(r2.view(np.float64), rule.view(np.float64))
+    assert np.array_equal(rule.view(np.float64), forced(hz, Lr, rp, ci, v, x).view(np.float64))
+    # a solve on the tuned matrix still meets its tolerance
+    xs, info = hz.zbicgstab_solve(rp, ci, v, dev(b), rtol=1e-9)
+    assert info["status"] == hz.OK
+    xs = xs.cpu().numpy()
+    assert np.linalg.norm(b - O.zspmv(A, xs)) / np.linalg.norm(b) <= 1e-9 * (1 + 1e-3)
+
+
+def test_every_forced_lane_count_matches_the_oracle(hz):
+    A, _, _ = W.config_cube(14, seed=2)
+    rp, ci, v = dev(A.row_ptr), dev(A.col_idx), dev(A.vals)
+    xh = np.random.default_rng(5).standard_normal(A.n) + 1j * np.random.default_rng(6).standard_normal(A.n)
+    yo = O.zspmv(A, xh)
+    for L in (2, 4, 8, 16, 32, 64):
+        y = forced(hz, L, rp, ci, v, dev(xh))
+        assert np.linalg.norm(y - yo) / np.linalg.norm(yo) <= 1e-14, L
