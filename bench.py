@@ -76,13 +76,10 @@ def read_traffic(kernel):
     except OSError:
         return None
     m_hash = re.search(r"kernel source hash:\s*`?([0-9a-f]{16})", txt)
-    m_bytes = re.search(r"HBM bytes per launch \(scaled\):\s*([0-9.eE+]+)", txt)
-    m_kern = re.search(r"counted kernel:\s*`([^`]+)`", txt)
-    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+    if not m_hash or m_hash.group(1) != kernel_source_hash():
         return None
-    if not m_kern or m_kern.group(1) != kernel:
-        return None
-    return float(m_bytes.group(1))
+    m_bytes = re.search(r"HBM bytes per launch \(scaled\), `" + re.escape(kernel) + r"`:\s*([0-9.eE+]+)", txt)
+    return float(m_bytes.group(1)) if m_bytes else None
 
 
 def cpu_baseline(A, b, x_spmv, budget_iters=300):

@@ -70,7 +70,18 @@ typedef struct {
     int renumbered;          /* 1 if solved in the level-set numbering      */
     double relres_recursive; /* last ||r||/||b|| of the recursive residual  */
     double relres_true;      /* ||b - A x|| / ||b||, recomputed in FP64     */
+    int breakdown;           /* status HZ_BREAKDOWN: which scalar was 0     */
+    int reserved;
 } hz_solve_info;
+
+/* hz_solve_info.breakdown: the quantity that became exactly zero */
+enum {
+    HZ_BD_NONE = 0,
+    HZ_BD_RHO = 1,    /* rho = <rhat, r>                                  */
+    HZ_BD_RHAT_V = 2, /* <rhat, v>, the denominator of alpha              */
+    HZ_BD_TT = 3,     /* <t, t>, the denominator of omega                 */
+    HZ_BD_OMEGA = 4   /* omega itself                                     */
+};
 
 /* Handle with scratch for the standalone reductions and the solvers.
  * Allocates device memory once; returns HZ_ERR_HIP if that fails. */

@@ -25,6 +25,8 @@ class HzInfo(C.Structure):
         ("renumbered", C.c_int),
         ("relres_recursive", C.c_double),
         ("relres_true", C.c_double),
+        ("breakdown", C.c_int),
+        ("reserved", C.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -35,6 +37,7 @@ class HzInfo(C.Structure):
             "renumbered": self.renumbered,
             "relres_recursive": self.relres_recursive,
             "relres_true": self.relres_true,
+            "breakdown": self.breakdown,
         }
 
 

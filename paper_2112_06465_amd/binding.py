@@ -17,6 +17,7 @@ from ._lib import HelmzError, HzC128, HzInfo, load
 OK, NOT_CONVERGED, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 PRECOND_NONE, PRECOND_JACOBI, X0_ZERO, VALIDATE, SYMMETRIC = 0x0, 0x1, 0x4, 0x8, 0x10
 REORDER, NO_REORDER = 0x20, 0x40
+BD_NONE, BD_RHO, BD_RHAT_V, BD_TT, BD_OMEGA = 0, 1, 2, 3, 4  # info["breakdown"]: the scalar that became 0
 
 _handles: dict[int, int] = {}
 _hlock = threading.Lock()

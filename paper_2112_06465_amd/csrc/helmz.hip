@@ -89,15 +89,14 @@ int pick_lanes(const hz_handle* h, const int* rp, const int* ci, int n, int64_t 
     return rule_lanes(n, nnz);
 }
 
-// Contiguous chunks of rows per block (see hz_kernels.hpp): G <= kMaxGrid
-// blocks, a multiple of 8 when there are at least 8, chunk = ceil(n / G).
+// Blocks of a launch over n rows taken `step` rows at a time: G <= kMaxGrid,
+// a multiple of 8 when there are at least 8 (one group per XCD, struct Rows).
 Geom geom_for(int n, int step) {
     const int64_t steps = (int64_t(n) + step - 1) / step;
     int64_t G = steps < kMaxGrid ? steps : kMaxGrid;
     if (G < 1) G = 1;
     if (G >= hz::kXcd) G -= G % hz::kXcd;
-    const int64_t chunk = (int64_t(n) + G - 1) / G;
-    return Geom{int(G), int(chunk > 0 ? chunk : 1)};
+    return Geom{int(G)};
 }
 
 inline dim3 grid1(int64_t n) { return dim3(unsigned((n + kBlock - 1) / kBlock)); }
@@ -161,11 +160,14 @@ int enqueue_far_count(hz_handle* h, hipStream_t s, int n, const int* rp, const i
     return HZ_OK;
 }
 
-// Fused iteration (p and s formed per gathered column) unless more than 5 %
-// of the entries lie far from the diagonal; HZ_FUSED=0/1 overrides.
-bool choose_fused(const hz_handle* h, int64_t nnz) {
+// The gather-light iteration (p and s materialised, one gathered vector per
+// product) measured faster than or equal to the fused one (p and s formed
+// per gathered column, three gathered vectors) on every workload here: equal
+// on the naturally numbered cylinder, 1.6x faster on the renumbered cabin,
+// 2.4x on the randomly numbered one.  HZ_FUSED=1 selects the fused kernels.
+bool choose_fused(const hz_handle*, int64_t) {
     if (const char* env = std::getenv("HZ_FUSED")) return std::atoi(env) != 0;
-    return double(*h->hcount) <= 0.05 * double(nnz);
+    return false;
 }
 
 int check_csr_args(int n, int nnz, const int* rp, const int* ci, const void* vals) {
@@ -182,11 +184,12 @@ using hz::BlockMap;
 using hz::SysMap;
 
 // Work map of a solver launch over nsys systems with host row offsets
-// row_off[0..nsys].  One system: the G <= kMaxGrid blocks of geom_for, each
-// a contiguous row chunk.  Several systems: every system gets
-// ceil(n_j / R) blocks (R rows per block, chosen so the whole launch has
-// about kMaxGrid blocks), blocks of one system are consecutive, and the
-// total is padded to a multiple of 8 with empty blocks.
+// row_off[0..nsys].  One system: the G <= kMaxGrid blocks of geom_for in 8
+// groups (one per XCD) that deal their eighth of the rows out in tiles.
+// Several systems: every system gets ceil(n_j / R) blocks (R rows per
+// block, chosen so the whole launch has about kMaxGrid blocks), each with a
+// contiguous chunk of its system, blocks of one system are consecutive, and
+// the total is padded to a multiple of 8 with empty blocks.
 struct WorkMap {
     int nsys = 0, G = 0, stride = 0;
     std::vector<BlockMap> blocks;
@@ -198,11 +201,13 @@ WorkMap build_map(int nsys, const int* row_off, int L) {
     m.nsys = nsys;
     const int64_t N = int64_t(row_off[nsys]) - row_off[0];
     if (nsys == 1) {
+        // one group of blocks per XCD, each group's blocks taking its rows' tiles in turn (struct Rows)
         const Geom geo = geom_for(int(N), kBlock / L);
+        const int groups = (geo.G % hz::kXcd == 0) ? hz::kXcd : 1, K = geo.G / groups;
         for (int b = 0; b < geo.G; ++b) {
-            const int64_t r0 = std::min<int64_t>(N, int64_t(b) * geo.chunk);
-            const int64_t r1 = std::min<int64_t>(N, r0 + geo.chunk);
-            m.blocks.push_back(BlockMap{0, int(row_off[0] + r0), int(row_off[0] + r1), b});
+            const int x = b / K;
+            const int64_t x0 = N * x / groups, x1 = N * (x + 1) / groups;
+            m.blocks.push_back(BlockMap{0, int(row_off[0] + x0), int(row_off[0] + x1), b % K, K, b});
         }
         m.systems.push_back(SysMap{0, geo.G, row_off[0], row_off[1]});
     } else {
@@ -214,11 +219,11 @@ WorkMap build_map(int nsys, const int* row_off, int L) {
             m.systems.push_back(SysMap{int(m.blocks.size()), int(gj), row_off[j], row_off[j + 1]});
             for (int64_t b = 0; b < gj; ++b) {
                 const int64_t r0 = std::min<int64_t>(nj, b * chunk), r1 = std::min<int64_t>(nj, r0 + chunk);
-                m.blocks.push_back(BlockMap{j, int(row_off[j] + r0), int(row_off[j] + r1), int(b)});
+                m.blocks.push_back(BlockMap{j, int(row_off[j] + r0), int(row_off[j] + r1), 0, 1, int(b)});
             }
         }
         while (m.blocks.size() >= size_t(hz::kXcd) && m.blocks.size() % hz::kXcd != 0)
-            m.blocks.push_back(BlockMap{-1, 0, 0, 0});
+            m.blocks.push_back(BlockMap{-1, 0, 0, 0, 1, 0});
     }
     m.G = int(m.blocks.size());
     m.stride = std::max(m.G, kMaxGrid);
@@ -393,8 +398,6 @@ int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nn
     hipLaunchKernelGGL(hz::k_init<double>, dim3(m.G), dim3(kBlock), 0, s, a, rsrc);
     hipLaunchKernelGGL(hz::k_fin_init<double>, dim3(nsys), dim3(kBlock), 0, s, a);
     HZ_HIP(hipGetLastError());
-    rc = enqueue_far_count(h, s, n, rp, ci);
-    if (rc) return rc;
     SolverScal* hs = h->hsc;
     HZ_HIP(hipMemcpyAsync(hs, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
     HZ_HIP(hipMemcpyAsync(h->hflag, w.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -422,6 +425,7 @@ int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nn
         infos[j].outer_steps = 0;
         infos[j].relres_recursive = out[j].relres;
         infos[j].relres_true = out[j].relres_true;
+        infos[j].breakdown = out[j].why;
         worst = std::max(worst, out[j].status);
     }
     return worst;
@@ -795,6 +799,7 @@ int solve_multi(hz_handle* h, hipStream_t s, int B, int n, int nnz, const int* r
         infos[j].renumbered = 0;
         infos[j].relres_recursive = hs[j].relres;
         infos[j].relres_true = hs[j].relres_true;
+        infos[j].breakdown = hs[j].why;
         worst = std::max(worst, hs[j].status);
     }
     return worst;
@@ -1208,8 +1213,6 @@ int solve_mixed(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, cons
     hipLaunchKernelGGL(hz::k_dot_part<1>, dim3(geo.G), B, 0, s, n, geo, bd, nullptr, partI);
     hipLaunchKernelGGL(hz::k_fin_bnorm, one, B, 0, s, partI, geo.G, mw.outer);
     HZ_HIP(hipGetLastError());
-    rc = enqueue_far_count(h, s, n, rp, ci);
-    if (rc) return rc;
     SolverScal* ho = h->hsc2;
     SolverScal* hi = h->hsc;
     HZ_HIP(hipMemcpyAsync(ho, mw.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));

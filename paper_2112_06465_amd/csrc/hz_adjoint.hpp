@@ -116,11 +116,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_vals(int n, Geom geo, const int
                                                       const int* __restrict__ ci, const double2* __restrict__ lam,
                                                       const double2* __restrict__ x, double2* __restrict__ gv) {
     constexpr int RPS = kBlock / L;
-    const int lb = logical_block(blockIdx.x, geo.G);
-    const int64_t r0 = (int64_t)lb * geo.chunk;
-    const int64_t r1 = r0 + geo.chunk < (int64_t)n ? r0 + geo.chunk : (int64_t)n;
+    const Rows rw = rows_of_block(n, geo).rw;
     const int g = threadIdx.x / L, lane = threadIdx.x % L;
-    for (int64_t row = r0 + g; row < r1; row += RPS) {
+    for (int64_t row = rw.x0 + (int64_t)rw.k * RPS + g; row < rw.x1; row += (int64_t)rw.K * RPS) {
         const double2 l = lam[row];
         for (int p = rp[row] + lane; p < rp[row + 1]; p += L) {
             const double2 xv = x[ci[p]];

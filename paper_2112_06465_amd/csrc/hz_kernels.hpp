@@ -193,25 +193,51 @@ template <int K> __device__ __forceinline__ void store_partials(double* __restri
 
 // Chunked row ownership of a launch (see the file comment).
 struct Geom {
-    int G;      // blocks
-    int chunk;  // rows per block
+    int G;  // blocks: a multiple of 8 when there are at least 8
 };
 
 __device__ __forceinline__ int logical_block(int b, int G) {
     return (G % kXcd == 0) ? (b % kXcd) * (G / kXcd) + b / kXcd : b;
 }
 
+// The rows of a block.  The block is the k-th of the K blocks that share the
+// row range [x0, x1) of its group and takes that range's tiles k, k + K,
+// k + 2K, ... (a tile is kBlock/L rows in a row product, kBlock rows in an
+// element-wise pass).  A launch of G >= 8 blocks has 8 groups, one per XCD,
+// each owning an eighth of the rows; the K blocks of an XCD then advance
+// through its range side by side, so the part of x their gathers touch at
+// any time is a few tiles plus the matrix bandwidth, small enough for the
+// XCD's L2 (with one contiguous chunk per block it would be K separate
+// windows).  A system of a batch with its own chunk per block is K = 1.
+struct Rows {
+    int64_t x0, x1;
+    int k, K;
+};
+__device__ __forceinline__ Rows group_rows(int n, int G, int lb) {
+    Rows r;
+    const int groups = (G % kXcd == 0) ? kXcd : 1;
+    r.K = G / groups;
+    const int x = lb / r.K;
+    r.k = lb % r.K;
+    r.x0 = (int64_t)n * x / groups;
+    r.x1 = (int64_t)n * (x + 1) / groups;
+    return r;
+}
+
 struct RowRange {
     int lb;
-    int64_t r0, r1;
+    Rows rw;
 };
 __device__ __forceinline__ RowRange rows_of_block(int n, Geom geo) {
     RowRange r;
     r.lb = logical_block(blockIdx.x, geo.G);
-    r.r0 = (int64_t)r.lb * geo.chunk;
-    r.r1 = r.r0 + geo.chunk < (int64_t)n ? r.r0 + geo.chunk : (int64_t)n;
+    r.rw = group_rows(n, geo.G, r.lb);
     return r;
 }
+
+// Element-wise pass over the rows of a block (tiles of kBlock rows).
+#define HZ_FOR_ELEMS(i, rw) \
+    for (int64_t i = (rw).x0 + (int64_t)(rw).k * kBlock + threadIdx.x; i < (rw).x1; i += (int64_t)(rw).K * kBlock)
 
 // ------------------------------------------------------------------ row product (vector CSR)
 
@@ -247,32 +273,34 @@ __device__ __forceinline__ cx<T> row_partial(int beg, int end, int lane, const i
     return acc;
 }
 
-// Row loop of a block: rows r0 + g, r0 + g + RPS, ... (g = thread / L).  With
+// Row loop of a block over its tiles of RPS = kBlock/L rows (g = thread / L
+// picks the row of the tile).  With
 // PF the next step's row_ptr pair is loaded before the current row's product,
 // so that load's latency overlaps the current step (two more live registers;
 // kernels whose column functor gathers several vectors leave it off to stay
 // within 64 VGPRs).  epi(row, total) runs in lane 0 of each row's group after
 // the group sum.  The trip count is uniform across the block.
 template <typename T, int L, int U, bool PF = true, typename Op, typename Epi>
-__device__ __forceinline__ void for_rows(int64_t r0, int64_t r1, const int* __restrict__ rp,
-                                         const int* __restrict__ ci, const cx<T>* __restrict__ vals, Op op, Epi epi) {
+__device__ __forceinline__ void for_rows(const Rows& rw, const int* __restrict__ rp, const int* __restrict__ ci,
+                                         const cx<T>* __restrict__ vals, Op op, Epi epi) {
     constexpr int RPS = kBlock / L;
     const int g = threadIdx.x / L, lane = threadIdx.x % L;
-    int64_t row = r0 + g;
+    const int64_t first = rw.x0 + (int64_t)rw.k * RPS, step = (int64_t)rw.K * RPS, r1 = rw.x1;
+    int64_t row = first + g;
     int beg = 0, end = 0;
     if (row < r1) {
         beg = rp[row];
         end = rp[row + 1];
     }
-    for (int64_t base = r0; base < r1; base += RPS) {
-        const int64_t nrow = row + RPS;
+    for (int64_t base = first; base < r1; base += step) {
+        const int64_t nrow = row + step;
         int nbeg = 0, nend = 0;
         if (PF && nrow < r1) {
             nbeg = rp[nrow];
             nend = rp[nrow + 1];
         }
         const bool ok = row < r1;
-        if (!PF && ok && base != r0) {
+        if (!PF && ok && base != first) {
             beg = rp[row];
             end = rp[row + 1];
         }
@@ -314,9 +342,11 @@ struct alignas(256) SolverScal {
     int zero_x;  // ||b|| = 0: the solution is x = 0
     int bad_diag;  // Jacobi requested with a zero diagonal entry
     int pending;   // half-step exit taken in iteration `pending`; the next first kernel concludes
+    int why;       // for a breakdown: which scalar vanished (BD_*)
 };
 
 enum : int { ST_OK = 0, ST_NOT_CONVERGED = 1, ST_BREAKDOWN = 2, ST_NONFINITE = 3 };
+enum : int { BD_NONE = 0, BD_RHO = 1, BD_RHAT_V = 2, BD_TT = 3, BD_OMEGA = 4 };
 
 // Reset the scalar blocks of nsys systems before a solve.
 __global__ void k_sc_init(SolverScal* sc, int nsys, double rtol, int maxiter) {
@@ -331,12 +361,12 @@ __global__ void k_sc_init(SolverScal* sc, int nsys, double rtol, int maxiter) {
 
 // ------------------------------------------------------------------ work map of a solver launch
 
-// Logical block lb of a solver launch belongs to system `sys`, owns rows
-// [r0, r1) of the (block-diagonal) matrix and is the `local`-th block of its
-// system; sys < 0 marks padding.  System j owns the contiguous logical block
+// Logical block lb of a solver launch belongs to system `sys`, takes the rows
+// that (x0, x1, k, K) describe (as in struct Rows) of the (block-diagonal)
+// matrix and is the `local`-th block of its system; sys < 0 marks padding.  System j owns the contiguous logical block
 // range [gbeg, gbeg + gcnt).  A single solve is the one-system case.
 struct BlockMap {
-    int sys, r0, r1, local;
+    int sys, x0, x1, k, K, local;  // rows as in struct Rows
 };
 struct SysMap {
     int gbeg, gcnt, row0, row1;
@@ -365,7 +395,7 @@ template <typename T> struct BicgArgs {
 
 struct SysBlock {
     int lb, sys, local;
-    int64_t r0, r1;
+    Rows rw;
     int gbeg, gcnt;
 };
 template <typename T> __device__ __forceinline__ SysBlock sys_block(const BicgArgs<T>& a) {
@@ -374,8 +404,10 @@ template <typename T> __device__ __forceinline__ SysBlock sys_block(const BicgAr
     const BlockMap m = a.bmap[q.lb];
     q.sys = m.sys;
     q.local = m.local;
-    q.r0 = m.r0;
-    q.r1 = m.r1;
+    q.rw.x0 = m.x0;
+    q.rw.x1 = m.x1;
+    q.rw.k = m.k;
+    q.rw.K = m.K;
     if (m.sys >= 0) {
         const SysMap sm = a.smap[m.sys];
         q.gbeg = sm.gbeg;
@@ -389,9 +421,10 @@ template <typename T> __device__ __forceinline__ SysBlock sys_block(const BicgAr
 __device__ __forceinline__ bool sys_leader(const SysBlock& q) { return q.local == 0 && threadIdx.x == 0; }
 
 // Record the end of system q's solve (its leader thread only).
-__device__ __forceinline__ void finish(SolverScal* sc, int* ndone, int status, int iterations) {
+__device__ __forceinline__ void finish(SolverScal* sc, int* ndone, int status, int iterations, int why = BD_NONE) {
     sc->status = status;
     sc->iters = iterations;
+    sc->why = why;
     sc->done = 1;
     atomicAdd(ndone, 1);
 }
@@ -452,7 +485,7 @@ __global__ HZ_STREAM_BOUNDS void k_spmv(const SpmvArgs<T> a) {
     const cx<T>* __restrict__ xv = a.x;
     auto op = [xv](int c) { return xv[c]; };
     double e[1] = {0.0};
-    for_rows<T, L, U>(rr.r0, rr.r1, a.row_ptr, a.col_idx, a.vals, op, [&](int64_t row, cx<T> acc) {
+    for_rows<T, L, U>(rr.rw, a.row_ptr, a.col_idx, a.vals, op, [&](int64_t row, cx<T> acc) {
         if constexpr (EPI == EPI_RESID) {
             const cx<T> bw = a.w[row];
             acc.x = bw.x - acc.x;
@@ -474,7 +507,7 @@ __global__ HZ_STREAM_BOUNDS void k_sys_resid(const BicgArgs<T> a, const cx<T>* _
     if (q.sys < 0) return;
     auto op = [xin](int c) { return xin[c]; };
     double e[1] = {0.0};
-    for_rows<T, L, U>(q.r0, q.r1, a.row_ptr, a.col_idx, vals, op, [&](int64_t row, cx<T> acc) {
+    for_rows<T, L, U>(q.rw, a.row_ptr, a.col_idx, vals, op, [&](int64_t row, cx<T> acc) {
         const cx<T> bw = a.b[row];
         acc.x = bw.x - acc.x;
         acc.y = bw.y - acc.y;
@@ -526,20 +559,20 @@ __device__ __forceinline__ bool iteration_start(const BicgArgs<T>& a, const SysB
     if (it > 1) {
         const double rel = __builtin_sqrt(h[2]) / sc->bnorm;
         om = sc->omega;
-        int stt = -1, sit = 0;
+        int stt = -1, sit = 0, why = BD_NONE;
         if (!__builtin_isfinite(rel)) stt = ST_NONFINITE, sit = it - 1;
         else if (rel <= sc->rtol) stt = ST_OK, sit = it - 1;
-        else if (zzero(om)) stt = ST_BREAKDOWN, sit = it - 1;
+        else if (zzero(om)) stt = ST_BREAKDOWN, sit = it - 1, why = BD_OMEGA;
         else if (it - 1 >= sc->maxiter) stt = ST_NOT_CONVERGED, sit = sc->maxiter;
         else if (!zfinite(rho)) stt = ST_NONFINITE, sit = it;
-        else if (zzero(rho)) stt = ST_BREAKDOWN, sit = it;
+        else if (zzero(rho)) stt = ST_BREAKDOWN, sit = it, why = BD_RHO;
         else {
             beta = zmul(zdiv(rho, sc->rho2[(it - 1) & 1]), zdiv(sc->alpha, om));
             if (!zfinite(beta)) stt = ST_NONFINITE, sit = it;
         }
         if (sys_leader(q)) sc->relres = rel;
         if (stt >= 0) {
-            if (sys_leader(q)) finish(sc, a.ndone, stt, sit);
+            if (sys_leader(q)) finish(sc, a.ndone, stt, sit, why);
             return false;
         }
     }
@@ -581,7 +614,7 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_A(const BicgArgs<T> a) {
         return p_update<T>(false, bt, omt, r[c], pold[c], vold[c]);
     };
     double e[2] = {0.0, 0.0};
-    for_rows<T, L, U, false>(q.r0, q.r1, a.row_ptr, a.col_idx, a.vals, pcol, [&](int64_t row, cx<T> acc) {
+    for_rows<T, L, U, false>(q.rw, a.row_ptr, a.col_idx, a.vals, pcol, [&](int64_t row, cx<T> acc) {
         pnew[row] = pcol((int)row);
         vnew[row] = acc;
         const cx<T> w = a.rh[row];
@@ -603,7 +636,7 @@ __device__ __forceinline__ bool alpha_step(const BicgArgs<T>& a, const SysBlock&
     sys_sum<2>(a.part + kPartA * a.stride, a.stride, q.gbeg, q.gcnt, h);
     const double2 sigma = mk<double>(h[0], h[1]);
     if (!zfinite(sigma) || zzero(sigma)) {
-        if (sys_leader(q)) finish(sc, a.ndone, zzero(sigma) ? ST_BREAKDOWN : ST_NONFINITE, it);
+        if (sys_leader(q)) finish(sc, a.ndone, zzero(sigma) ? ST_BREAKDOWN : ST_NONFINITE, it, zzero(sigma) ? BD_RHAT_V : BD_NONE);
         return false;
     }
     alpha = zdiv(sc->rho2[it & 1], sigma);
@@ -622,7 +655,7 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_B(const BicgArgs<T> a) {
     const cx<T>* __restrict__ v = a.v[it & 1];
     auto scol = [=](int c) { return cfma<T>(mk<T>(-al.x, -al.y), v[c], r[c]); };
     double e[4] = {0.0, 0.0, 0.0, 0.0};
-    for_rows<T, L, U>(q.r0, q.r1, a.row_ptr, a.col_idx, a.vals, scol, [&](int64_t row, cx<T> acc) {
+    for_rows<T, L, U>(q.rw, a.row_ptr, a.col_idx, a.vals, scol, [&](int64_t row, cx<T> acc) {
         const cx<T> s = scol((int)row);
         a.s[row] = s;
         a.t[row] = acc;
@@ -655,7 +688,7 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_C(const BicgArgs<T> a) {
         return;
     }
     if (rel <= sc->rtol) {  // half-step exit: x += alpha p (concluded by the next first kernel)
-        for (int64_t i = q.r0 + threadIdx.x; i < q.r1; i += kBlock) a.x[i] = cfma<T>(al, p[i], a.x[i]);
+        HZ_FOR_ELEMS(i, q.rw) a.x[i] = cfma<T>(al, p[i], a.x[i]);
         if (sys_leader(q)) {
             sc->relres = rel;
             sc->pending = it;
@@ -664,16 +697,16 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_C(const BicgArgs<T> a) {
     }
     const double2 ts = mk<double>(h[1], h[2]);
     const double tt = h[3];
-    int st = -1;
+    int st = -1, why = BD_NONE;
     double2 om = mk<double>(0.0, 0.0);
     if (!zfinite(ts) || !__builtin_isfinite(tt)) st = ST_NONFINITE;
-    else if (tt == 0.0) st = ST_BREAKDOWN;
+    else if (tt == 0.0) st = ST_BREAKDOWN, why = BD_TT;
     else {
         om = zdiv(ts, mk<double>(tt, 0.0));
         if (!zfinite(om)) st = ST_NONFINITE;
     }
     if (st >= 0) {
-        if (sys_leader(q)) finish(sc, a.ndone, st, it);
+        if (sys_leader(q)) finish(sc, a.ndone, st, it, why);
         return;
     }
     if (sys_leader(q)) {
@@ -682,7 +715,7 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_C(const BicgArgs<T> a) {
     }
     const cx<T> omt = narrow<T>(om), nom = mk<T>(-omt.x, -omt.y);
     double e[3] = {0.0, 0.0, 0.0};
-    for (int64_t i = q.r0 + threadIdx.x; i < q.r1; i += kBlock) {
+    HZ_FOR_ELEMS(i, q.rw) {
         const cx<T> sv = a.s[i], tv = a.t[i], rh = a.rh[i];
         cx<T> x = a.x[i];
         x = cfma<T>(al, p[i], x);
@@ -722,7 +755,7 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_P(const BicgArgs<T> a) {
     const cx<T>* __restrict__ pold = a.p[(it - 1) & 1];
     const cx<T>* __restrict__ vold = a.v[(it - 1) & 1];
     cx<T>* __restrict__ pnew = a.p[it & 1];
-    for (int64_t i = q.r0 + threadIdx.x; i < q.r1; i += kBlock)
+    HZ_FOR_ELEMS(i, q.rw)
         pnew[i] = first ? a.r[i] : p_update<T>(false, bt, omt, a.r[i], pold[i], vold[i]);
 }
 
@@ -737,7 +770,7 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_A1(const BicgArgs<T> a) {
     cx<T>* __restrict__ v = a.v[it & 1];
     auto pcol = [p](int c) { return p[c]; };
     double e[2] = {0.0, 0.0};
-    for_rows<T, L, U>(q.r0, q.r1, a.row_ptr, a.col_idx, a.vals, pcol, [&](int64_t row, cx<T> acc) {
+    for_rows<T, L, U>(q.rw, a.row_ptr, a.col_idx, a.vals, pcol, [&](int64_t row, cx<T> acc) {
         v[row] = acc;
         const cx<T> w = a.rh[row];
         double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
@@ -756,7 +789,7 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_S(const BicgArgs<T> a) {
     const cx<T> nal = mk<T>((T)-alpha.x, (T)-alpha.y);
     const cx<T>* __restrict__ v = a.v[it & 1];
     double e[1] = {0.0};
-    for (int64_t i = q.r0 + threadIdx.x; i < q.r1; i += kBlock) {
+    HZ_FOR_ELEMS(i, q.rw) {
         const cx<T> s = cfma<T>(nal, v[i], a.r[i]);
         a.s[i] = s;
         e[0] = __builtin_fma((double)s.x, (double)s.x, e[0]);
@@ -773,7 +806,7 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_B1(const BicgArgs<T> a) {
     const cx<T>* __restrict__ sv = a.s;
     auto scol = [sv](int c) { return sv[c]; };
     double e[3] = {0.0, 0.0, 0.0};
-    for_rows<T, L, U>(q.r0, q.r1, a.row_ptr, a.col_idx, a.vals, scol, [&](int64_t row, cx<T> acc) {
+    for_rows<T, L, U>(q.rw, a.row_ptr, a.col_idx, a.vals, scol, [&](int64_t row, cx<T> acc) {
         const cx<T> s = sv[row];
         a.t[row] = acc;
         double2 c = cdotacc(acc.x, acc.y, s.x, s.y, mk<double>(e[0], e[1]));
@@ -806,7 +839,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const BicgArgs<T> a, const cx<T
     const SysBlock q = sys_block(a);
     if (q.sys < 0) return;
     double e[3] = {0.0, 0.0, 0.0}, eb[1] = {0.0};
-    for (int64_t i = q.r0 + threadIdx.x; i < q.r1; i += kBlock) {
+    HZ_FOR_ELEMS(i, q.rw) {
         const cx<T> bv = a.b[i], rv = src[i];
         if (a.r != src) a.r[i] = rv;
         const_cast<cx<T>*>(a.rh)[i] = rv;
@@ -840,6 +873,7 @@ __global__ __launch_bounds__(kBlock) void k_fin_init(const BicgArgs<T> a) {
     sc->zero_x = 0;
     sc->iters = 0;
     sc->pending = 0;
+    sc->why = BD_NONE;
     sc->status = ST_NOT_CONVERGED;
     sc->alpha = sc->omega = sc->beta = mk<double>(1.0, 0.0);
     if (!__builtin_isfinite(bn) || !__builtin_isfinite(hr[2])) return finish(sc, a.ndone, ST_NONFINITE, 0);
@@ -870,7 +904,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_zero_if(const BicgArgs<T> a) {
     const SysBlock q = sys_block(a);
     if (q.sys < 0 || !a.sc[q.sys].zero_x) return;
-    for (int64_t i = q.r0 + threadIdx.x; i < q.r1; i += kBlock) a.x[i] = mk<T>(T(0), T(0));
+    HZ_FOR_ELEMS(i, q.rw) a.x[i] = mk<T>(T(0), T(0));
 }
 
 // ------------------------------------------------------------------ Jacobi folding: A D^{-1}
@@ -928,7 +962,7 @@ __global__ __launch_bounds__(kBlock) void k_dot_part(int n, Geom geo, const doub
     double e[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) e[k] = 0.0;
-    for (int64_t i = rr.r0 + threadIdx.x; i < rr.r1; i += kBlock) {
+    HZ_FOR_ELEMS(i, rr.rw) {
         const double2 xv = x[i];
         if constexpr (MODE == 0) {
             const double2 yv = y[i];

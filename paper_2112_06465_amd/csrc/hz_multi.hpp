@@ -148,13 +148,17 @@ __device__ __forceinline__ double2 mrow(const MultiArgs& a, int64_t i, int j, co
     const size_t Bz = (size_t)a.B;                          \
     (void)Bz
 
+// The block's rows for slot g: its tiles of S rows (see struct Rows).
+#define HZ_MROWS(i) \
+    for (int64_t i = rr.rw.x0 + (int64_t)rr.rw.k * S + g; i < rr.rw.x1; i += (int64_t)rr.rw.K * S)
+
 // Solve set-up: r = src, rhat = src; partials <rhat,r>, ||r||^2 (C), ||b||^2 (I).
 template <int BL>
 __global__ HZ_STREAM_BOUNDS void k_m_init(const MultiArgs a, const double2* src) {
     HZ_MULTI_ROWS;
     double e[3] = {0.0, 0.0, 0.0}, eb[1] = {0.0};
     if (j < a.B)
-        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+        HZ_MROWS(i) {
             const size_t q = (size_t)i * Bz + j;
             const double2 bv = a.b[q], rv = src[q];
             if (a.r != src) a.r[q] = rv;
@@ -188,6 +192,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_fin_init(const MultiArgs a) {
     sc->zero_x = 0;
     sc->iters = 0;
     sc->pending = 0;
+    sc->why = BD_NONE;
     sc->status = ST_NOT_CONVERGED;
     sc->alpha = sc->omega = sc->beta = mk<double>(1.0, 0.0);
     if (!__builtin_isfinite(bn) || !__builtin_isfinite(hr[2])) return finish(sc, a.ndone, ST_NONFINITE, 0);
@@ -224,20 +229,20 @@ __global__ HZ_STREAM_BOUNDS void k_m_P(const MultiArgs a) {
     if (it > 1) {
         const double rel = __builtin_sqrt(h[2]) / sc->bnorm;
         om = sc->omega;
-        int stt = -1, sit = 0;
+        int stt = -1, sit = 0, why = BD_NONE;
         if (!__builtin_isfinite(rel)) stt = ST_NONFINITE, sit = it - 1;
         else if (rel <= sc->rtol) stt = ST_OK, sit = it - 1;
-        else if (zzero(om)) stt = ST_BREAKDOWN, sit = it - 1;
+        else if (zzero(om)) stt = ST_BREAKDOWN, sit = it - 1, why = BD_OMEGA;
         else if (it - 1 >= sc->maxiter) stt = ST_NOT_CONVERGED, sit = sc->maxiter;
         else if (!zfinite(rho)) stt = ST_NONFINITE, sit = it;
-        else if (zzero(rho)) stt = ST_BREAKDOWN, sit = it;
+        else if (zzero(rho)) stt = ST_BREAKDOWN, sit = it, why = BD_RHO;
         else {
             beta = zmul(zdiv(rho, sc->rho2[(it - 1) & 1]), zdiv(sc->alpha, om));
             if (!zfinite(beta)) stt = ST_NONFINITE, sit = it;
         }
         if (lead) sc->relres = rel;
         if (stt >= 0) {
-            if (lead) finish(sc, a.ndone, stt, sit);
+            if (lead) finish(sc, a.ndone, stt, sit, why);
             return;
         }
     }
@@ -246,7 +251,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_P(const MultiArgs a) {
         sc->beta = beta;
         sc->cur = it;
     }
-    for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+    HZ_MROWS(i) {
         const size_t q = (size_t)i * Bz + j;
         const double2 rv = a.r[q];
         if (it == 1) {
@@ -267,7 +272,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_A1(const MultiArgs a) {
     HZ_MULTI_ROWS;
     double e[2] = {0.0, 0.0};
     if (j < a.B && !a.sc[j].done && !a.sc[j].pending)
-        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+        HZ_MROWS(i) {
             const double2 acc = mrow<U>(a, i, j, a.p);
             const size_t q = (size_t)i * Bz + j;
             a.v[q] = acc;
@@ -295,7 +300,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_S(const MultiArgs a) {
             const int it = sc->cur;
             const double2 sigma = mk<double>(h[0], h[1]);
             if (!zfinite(sigma) || zzero(sigma)) {
-                if (mleader<BL>(rr.lb)) finish(sc, a.ndone, zzero(sigma) ? ST_BREAKDOWN : ST_NONFINITE, it);
+                if (mleader<BL>(rr.lb)) finish(sc, a.ndone, zzero(sigma) ? ST_BREAKDOWN : ST_NONFINITE, it, zzero(sigma) ? BD_RHAT_V : BD_NONE);
                 go = false;
             } else {
                 alpha = zdiv(sc->rho2[it & 1], sigma);
@@ -305,7 +310,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_S(const MultiArgs a) {
     }
     if (go) {
         const double2 nal = mk<double>(-alpha.x, -alpha.y);
-        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+        HZ_MROWS(i) {
             const size_t q = (size_t)i * Bz + j;
             const double2 sv = cfma<double>(nal, a.v[q], a.r[q]);
             a.s[q] = sv;
@@ -323,7 +328,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_B1(const MultiArgs a) {
     HZ_MULTI_ROWS;
     double e[3] = {0.0, 0.0, 0.0};
     if (j < a.B && !a.sc[j].done)
-        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+        HZ_MROWS(i) {
             const double2 acc = mrow<U>(a, i, j, a.s);
             const size_t q = (size_t)i * Bz + j;
             a.t[q] = acc;
@@ -367,15 +372,15 @@ __global__ HZ_STREAM_BOUNDS void k_m_C(const MultiArgs a) {
             } else {
                 const double2 ts = mk<double>(h[1], h[2]);
                 const double tt = h[3];
-                int st = -1;
+                int st = -1, why = BD_NONE;
                 if (!zfinite(ts) || !__builtin_isfinite(tt)) st = ST_NONFINITE;
-                else if (tt == 0.0) st = ST_BREAKDOWN;
+                else if (tt == 0.0) st = ST_BREAKDOWN, why = BD_TT;
                 else {
                     om = zdiv(ts, mk<double>(tt, 0.0));
                     if (!zfinite(om)) st = ST_NONFINITE;
                 }
                 if (st >= 0) {
-                    if (lead) finish(sc, a.ndone, st, it);
+                    if (lead) finish(sc, a.ndone, st, it, why);
                 } else {
                     mode = 2;
                     if (lead) {
@@ -387,13 +392,13 @@ __global__ HZ_STREAM_BOUNDS void k_m_C(const MultiArgs a) {
         }
     }
     if (mode == 1) {
-        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+        HZ_MROWS(i) {
             const size_t q = (size_t)i * Bz + j;
             a.x[q] = cfma<double>(al, a.p[q], a.x[q]);
         }
     } else if (mode == 2) {
         const double2 nom = mk<double>(-om.x, -om.y);
-        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+        HZ_MROWS(i) {
             const size_t q = (size_t)i * Bz + j;
             const double2 sv = a.s[q], tv = a.t[q], rh = a.rh[q];
             double2 x = a.x[q];
@@ -421,7 +426,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_resid(const MultiArgs a, const double2* __r
     a2.vals = vals;
     double e[1] = {0.0};
     if (j < a.B)
-        for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+        HZ_MROWS(i) {
             const double2 acc = mrow<U>(a2, i, j, xin);
             const size_t q = (size_t)i * Bz + j;
             const double2 bv = a.b[q];
@@ -449,7 +454,7 @@ template <int BL>
 __global__ HZ_STREAM_BOUNDS void k_m_zero_if(const MultiArgs a) {
     HZ_MULTI_ROWS;
     if (j >= a.B || !a.sc[j].zero_x) return;
-    for (int64_t i = rr.r0 + g; i < rr.r1; i += S) a.x[(size_t)i * Bz + j] = mk<double>(0.0, 0.0);
+    HZ_MROWS(i) a.x[(size_t)i * Bz + j] = mk<double>(0.0, 0.0);
 }
 
 // dinv[i*B + j] = 1 / A_j(i, i); a missing or zero diagonal flags sc[j].bad_diag.
@@ -501,7 +506,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_grad_vals(const MultiArgs a, const double2*
                                                const double2* __restrict__ xs, double2* __restrict__ grad) {
     HZ_MULTI_ROWS;
     if (j >= a.B) return;
-    for (int64_t i = rr.r0 + g; i < rr.r1; i += S) {
+    HZ_MROWS(i) {
         const double2 l = lam[(size_t)i * Bz + j];
         const double2 nl = mk<double>(-l.x, -l.y);
         for (int p = a.row_ptr[i]; p < a.row_ptr[i + 1]; ++p) {

@@ -94,7 +94,7 @@ def test_batched_adjoint_without_entry_gradients_and_statuses(hz):
     lam, gv, infos = hz.zbicgstab_adjoint_batched(dev(P.row_ptr), dev(P.col_idx), dev(vals.T), None, dev(G),
                                                   rtol=1e-12, flags=hz.SYMMETRIC, want_grad_vals=False)
     assert gv is None
-    assert infos[0]["status"] == hz.BREAKDOWN
+    assert infos[0]["status"] == hz.BREAKDOWN and infos[0]["breakdown"] == hz.BD_RHAT_V
     assert infos[1]["status"] == hz.OK
     l1 = np.linalg.solve(vals[1].reshape(2, 2).conj().T, G[:, 1])
     assert np.allclose(lam.cpu().numpy()[:, 1], l1, rtol=1e-11)

@@ -107,6 +107,7 @@ def test_batch_reports_each_status(hz):
     xs, infos = solve_batch(hz, systems, 1e-9, hz.PRECOND_NONE)
     assert infos[0]["status"] == hz.OK and true_relres(A, xs[0], b) <= 1e-9 * (1 + 1e-3)
     assert infos[1]["status"] == hz.BREAKDOWN and infos[1]["iterations"] == 1
+    assert infos[1]["breakdown"] == hz.BD_RHAT_V and infos[0]["breakdown"] == hz.BD_NONE
     assert infos[2]["status"] == hz.OK and true_relres(A2, xs[2], b2) <= 1e-9 * (1 + 1e-3)
     assert infos[3]["status"] == hz.OK and infos[3]["iterations"] == 0 and np.all(xs[3] == 0)
     _, infos = solve_batch(hz, systems[:1] + systems[2:3], 1e-12, hz.PRECOND_NONE, maxiter=5)

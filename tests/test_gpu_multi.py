@@ -119,6 +119,7 @@ def test_each_system_reports_its_own_status(hz):
     rhs = np.array([[1, 0], [1, 1], [0, 0]], complex)
     xs, infos = solve_multi(hz, P, vals, rhs, 1e-12, hz.PRECOND_NONE)
     assert infos[0]["status"] == hz.BREAKDOWN and infos[0]["iterations"] == 1
+    assert infos[0]["breakdown"] == hz.BD_RHAT_V and infos[1]["breakdown"] == hz.BD_NONE
     assert infos[1]["status"] == hz.OK
     assert np.allclose(xs[1], np.linalg.solve(vals[1].reshape(2, 2), rhs[1]), rtol=1e-12)
     assert infos[2]["status"] == hz.OK and infos[2]["iterations"] == 0 and np.all(xs[2] == 0)

@@ -277,7 +277,7 @@ def test_solve_breakdown_and_invalid(hz):
     Z = CSR(np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0 + 0j, 1.0 + 0j]))
     rp, ci, v = dev_csr(Z)
     _, info = hz.zbicgstab_solve(rp, ci, v, dev(np.array([1.0 + 0j, 0j])), rtol=1e-8)
-    assert info["status"] == hz.BREAKDOWN and info["iterations"] == 1
+    assert info["status"] == hz.BREAKDOWN and info["iterations"] == 1 and info["breakdown"] == hz.BD_RHAT_V
     with pytest.raises(hz.HelmzError) as e:
         hz.zbicgstab_solve(rp, ci, v, dev(np.ones(2, complex)), rtol=1e-8, flags=hz.PRECOND_JACOBI)
     assert e.value.code == -1
@@ -329,7 +329,7 @@ def test_solve_both_iteration_variants(hz, jacobi, monkeypatch):
         Z = CSR(np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0 + 0j, 1.0 + 0j]))
         rp, ci, v = dev_csr(Z)
         _, info = hz.zbicgstab_solve(rp, ci, v, dev(np.array([1.0 + 0j, 0j])), rtol=1e-8)
-        assert info["status"] == hz.BREAKDOWN and info["iterations"] == 1
+        assert info["status"] == hz.BREAKDOWN and info["iterations"] == 1 and info["breakdown"] == hz.BD_RHAT_V
         A, b, _ = W.config_cube(6)
         rp, ci, v = dev_csr(A)
         _, info = hz.zbicgstab_solve(rp, ci, v, dev(b), rtol=1e-14, maxiter=3)
