@@ -443,19 +443,29 @@ struct LevelWs {
     unsigned* key;
     unsigned* key2;
     int* idx;
+    int* bylevel;             // nodes sorted by (level, index)
+    int* off;                 // n + 2: first position of each level in bylevel
+    unsigned long long* ck;   // Cuthill-McKee keys of one level, and their sorted copy
+    unsigned long long* ck2;
+    int* cv;
     void* tmp;
     size_t tmp_bytes;
 };
 
+// rocPRIM scratch for the sorts and the scan of n items (the 32-bit level
+// sort with end_bit bits, the 64-bit per-level sort, the row-pointer scan).
 size_t prim_tmp_bytes(int n, unsigned end_bit) {
-    size_t a = 0, b = 0;
+    size_t a = 0, b = 0, c = 0;
     const unsigned* ku = nullptr;
     unsigned* ko = nullptr;
+    const unsigned long long* k64 = nullptr;
+    unsigned long long* k64o = nullptr;
     const int* vi = nullptr;
     int* vo = nullptr;
     if (rocprim::radix_sort_pairs(nullptr, a, ku, ko, vi, vo, unsigned(n), 0u, end_bit) != hipSuccess) return 0;
+    if (rocprim::radix_sort_pairs(nullptr, c, k64, k64o, vi, vo, unsigned(n), 0u, 64u) != hipSuccess) return 0;
     if (rocprim::inclusive_scan(nullptr, b, vi, vo, size_t(n) + 1, rocprim::plus<int>()) != hipSuccess) return 0;
-    return std::max<size_t>(std::max(a, b), 1);
+    return std::max<size_t>(std::max(std::max(a, b), c), 1);
 }
 
 size_t level_layout(int n, char* base, LevelWs* out) {
@@ -473,6 +483,11 @@ size_t level_layout(int n, char* base, LevelWs* out) {
     w.key = static_cast<unsigned*>(take(sizeof(unsigned) * nn));
     w.key2 = static_cast<unsigned*>(take(sizeof(unsigned) * nn));
     w.idx = static_cast<int*>(take(sizeof(int) * nn));
+    w.bylevel = static_cast<int*>(take(sizeof(int) * nn));
+    w.off = static_cast<int*>(take(sizeof(int) * (nn + 2)));
+    w.ck = static_cast<unsigned long long*>(take(sizeof(unsigned long long) * nn));
+    w.ck2 = static_cast<unsigned long long*>(take(sizeof(unsigned long long) * nn));
+    w.cv = static_cast<int*>(take(sizeof(int) * nn));
     w.tmp_bytes = prim_tmp_bytes(int(nn), 32u);
     w.tmp = take(w.tmp_bytes);
     if (out) *out = w;
@@ -501,10 +516,14 @@ int bfs(hz_handle* h, hipStream_t s, int n, const int* rp, const int* ci, const 
     return HZ_OK;
 }
 
-// Level-set ordering: a first search from node 0 finds a far node (the
-// smallest index on its deepest level), a second search from there gives the
-// levels; perm lists the nodes by (level, caller's index), unreached nodes
-// last, and inv is its inverse.  level_out (nullable) receives the levels.
+// Level-set (Cuthill-McKee) ordering: a first search from node 0 finds a far
+// node (the smallest index on its deepest level), a second search from there
+// gives the levels.  A stable sort of (level, caller's index) groups the
+// levels; then, level after level, each level is sorted stably by (smallest
+// new position of a neighbour on the previous level, degree capped at 255).
+// Unreached nodes come last in index order.  perm lists the caller's index
+// of every new row, inv is its inverse (also the running positions while the
+// levels are placed); level_out (nullable) receives the levels.
 int level_order(hz_handle* h, hipStream_t s, int n, const int* rp, const int* ci, const LevelWs& w, int* perm,
                 int* inv, int* level_out) {
     HZ_HIP(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(w.scal), 0, 1, s));
@@ -525,7 +544,40 @@ int level_order(hz_handle* h, hipStream_t s, int n, const int* rp, const int* ci
     if (tb == 0 || tb > w.tmp_bytes) return HZ_ERR_WORKSPACE;
     tb = w.tmp_bytes;
     HZ_HIP(rocprim::radix_sort_pairs(w.tmp, tb, static_cast<const unsigned*>(w.key), w.key2,
-                                     static_cast<const int*>(w.idx), perm, unsigned(n), 0u, end_bit, s));
+                                     static_cast<const int*>(w.idx), w.bylevel, unsigned(n), 0u, end_bit, s));
+    // level offsets to the host (levels 0..last, then the unreached bucket or n)
+    hipLaunchKernelGGL(hz::k_level_starts, grid1(n), dim3(kBlock), 0, s, n, static_cast<const unsigned*>(w.key2),
+                       w.off);
+    HZ_HIP(hipGetLastError());
+    std::vector<int> off(size_t(last) + 2);
+    HZ_HIP(hipMemcpyAsync(off.data(), w.off, sizeof(int) * off.size(), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipMemcpyAsync(perm, w.bylevel, sizeof(int) * size_t(n), hipMemcpyDeviceToDevice, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    // level 0 is the start node alone; every later level by its Cuthill-McKee keys
+    hipLaunchKernelGGL(hz::k_cm_place, dim3(1), dim3(kBlock), 0, s, 1, static_cast<const int*>(perm), 0, inv);
+    unsigned kbits = 8;
+    while (kbits < 64 && (uint64_t(n) >> (kbits - 8)) != 0) ++kbits;
+    size_t tb64 = 0;
+    {
+        const unsigned long long* k64 = nullptr;
+        unsigned long long* k64o = nullptr;
+        const int* vi = nullptr;
+        int* vo = nullptr;
+        HZ_HIP(rocprim::radix_sort_pairs(nullptr, tb64, k64, k64o, vi, vo, unsigned(n), 0u, kbits));
+        if (tb64 > w.tmp_bytes) return HZ_ERR_WORKSPACE;
+    }
+    for (int L = 1; L <= last; ++L) {
+        const int first = off[L], m = off[L + 1] - off[L];
+        if (m <= 0) continue;
+        hipLaunchKernelGGL(hz::k_cm_keys, grid1(m), dim3(kBlock), 0, s, m,
+                           static_cast<const int*>(w.bylevel) + first, rp, ci, static_cast<const int*>(w.level), L,
+                           static_cast<const int*>(inv), n, w.ck, w.cv);
+        tb = w.tmp_bytes;
+        HZ_HIP(rocprim::radix_sort_pairs(w.tmp, tb, static_cast<const unsigned long long*>(w.ck), w.ck2,
+                                         static_cast<const int*>(w.cv), perm + first, unsigned(m), 0u, kbits, s));
+        hipLaunchKernelGGL(hz::k_cm_place, grid1(m), dim3(kBlock), 0, s, m, static_cast<const int*>(perm) + first,
+                           first, inv);
+    }
     hipLaunchKernelGGL(hz::k_invert, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(perm), inv);
     HZ_HIP(hipGetLastError());
     return HZ_OK;

@@ -1,22 +1,25 @@
-// Level-set (breadth-first) reordering of a CSR matrix on the device.
+// Level-set (Cuthill-McKee) reordering of a CSR matrix on the device.
 //
 // The solver's kernels gather x by column index.  When the caller's numbering
 // scatters the neighbours of a row across the whole vector (a randomly
 // numbered mesh), each gathered 16-byte element pulls a cache line from far
 // away and the product becomes gather-bound.  Renumbering the unknowns by
-// breadth-first level from a pseudo-peripheral node (a Cuthill-McKee-type
-// ordering without the degree sort) puts the neighbours of every row within
-// two adjacent level sets, so the x window of a block stays in its XCD's L2.
-// BiCGStab with Jacobi scaling is invariant under a symmetric permutation
-// P A P^T (all inner products are sums over the same index set), so the
-// solve in the new numbering is the same method up to rounding order.
+// breadth-first level from a pseudo-peripheral node puts the neighbours of
+// every row within two adjacent level sets; ordering each level the
+// Cuthill-McKee way (by the new position of the earliest neighbour on the
+// previous level, then by degree) also keeps the neighbours of consecutive
+// rows close together inside those levels, so a row's gathers share cache
+// lines.  BiCGStab with Jacobi scaling is invariant under a symmetric
+// permutation P A P^T (all inner products are sums over the same index set),
+// so the solve in the new numbering is the same method up to rounding order.
 //
 // Everything here is integer and index work and is bitwise reproducible:
 //   * BFS levels are distances, independent of the order threads run in: a
 //     level-L pass writes only the value L + 1, so racing writers agree;
-//   * the order within a level is by the caller's index (a stable radix sort
-//     of (level, index) on the host side), so the permutation is a pure
-//     function of the pattern.
+//   * levels are formed by a stable radix sort of (level, index); each level
+//     is then sorted stably by (earliest new position of a neighbour on the
+//     previous level, degree), level after level, so ties fall back to the
+//     caller's index and the permutation is a pure function of the pattern.
 #pragma once
 
 #include "hz_kernels.hpp"
@@ -77,6 +80,47 @@ __global__ __launch_bounds__(kBlock) void k_order_keys(int n, const int* __restr
     const int l = level[i];
     key[i] = unsigned(l < 0 ? Lmax + 1 : l);
     idx[i] = (int)i;
+}
+
+// off[key] = first position of each key in the sorted keys skey[0..n); the
+// last position also writes off[skey[n-1] + 1] = n.
+__global__ __launch_bounds__(kBlock) void k_level_starts(int n, const unsigned* __restrict__ skey,
+                                                         int* __restrict__ off) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const unsigned c = skey[k];
+    if (k == 0 || skey[k - 1] != c) off[c] = (int)k;
+    if (k == n - 1) off[c + 1] = n;
+}
+
+// Cuthill-McKee keys of the m nodes of level L (given in index order): the
+// smallest new position pos[u] of a neighbour u on level L - 1 (n when there
+// is none), shifted left by 8, plus the degree capped at 255.
+__global__ __launch_bounds__(kBlock) void k_cm_keys(int m, const int* __restrict__ nodes, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, const int* __restrict__ level, int L,
+                                                    const int* __restrict__ pos, int n,
+                                                    unsigned long long* __restrict__ key, int* __restrict__ val) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    const int v = nodes[i];
+    int pmin = n;
+    for (int p = rp[v]; p < rp[v + 1]; ++p) {
+        const int u = ci[p];
+        if (level[u] == L - 1) {
+            const int q = pos[u];
+            pmin = q < pmin ? q : pmin;
+        }
+    }
+    const int deg = rp[v + 1] - rp[v];
+    key[i] = ((unsigned long long)pmin << 8) | (unsigned long long)(deg < 255 ? deg : 255);
+    val[i] = v;
+}
+
+// pos[order[i]] = first + i for the m nodes just placed
+__global__ __launch_bounds__(kBlock) void k_cm_place(int m, const int* __restrict__ order, int first,
+                                                     int* __restrict__ pos) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < m) pos[order[i]] = first + (int)i;
 }
 
 // inv[perm[k]] = k

@@ -150,23 +150,23 @@ def test_adjoint_in_level_order(hz):
         assert np.linalg.norm(l.cpu().numpy() - lam) / np.linalg.norm(lam) < 1e-8
 
 
-def test_full_size_cabin_level_order_matches_scipy_bfs(hz):
-    """Cabin (n=1.24M, randomly numbered): levels and order equal those from scipy's BFS."""
+def test_full_size_cabin_level_order_matches_oracle_with_scipy_bfs(hz):
+    """Cabin (n=1.24M, randomly numbered): levels and order equal the oracle's, with scipy's BFS distances."""
     import scipy.sparse as sp
     import scipy.sparse.csgraph as cg
 
     A, _, _ = W.config_cabin()
     G = sp.csr_matrix((np.ones(A.nnz), A.col_idx, A.row_ptr), shape=(A.n, A.n))
-    d0 = cg.shortest_path(G, unweighted=True, indices=0)
-    start = int(np.flatnonzero(d0 == d0.max())[0])
-    lev = cg.shortest_path(G, unweighted=True, indices=start)
-    lev = np.where(np.isinf(lev), -1, lev).astype(np.int64)
+
+    def scipy_bfs(rp, ci, start):
+        d = cg.shortest_path(G, unweighted=True, indices=start)
+        return np.where(np.isinf(d), -1, d).astype(np.int64)
+
+    perm_o, inv_o, lev_o = R.level_order(A.row_ptr, A.col_idx, bfs=scipy_bfs)
     perm, inv, level = hz.csr_level_order(dev(A.row_ptr), dev(A.col_idx))
-    assert np.array_equal(level.cpu().numpy(), lev)
-    key = np.where(lev < 0, lev.max() + 1, lev)
-    assert np.array_equal(perm.cpu().numpy(), np.lexsort((np.arange(A.n), key)))
-    p, iv = perm.cpu().numpy(), inv.cpu().numpy()
-    assert np.array_equal(iv[p], np.arange(A.n))
+    assert np.array_equal(level.cpu().numpy(), lev_o)
+    assert np.array_equal(perm.cpu().numpy(), perm_o)
+    assert np.array_equal(inv.cpu().numpy(), inv_o)
     rows = A.row_of_entry()
-    band = np.abs(iv[rows] - iv[A.col_idx]).max()
-    print(f"cabin: {lev.max() + 1} levels, widest {np.bincount(lev).max()}, bandwidth after renumbering {band}")
+    band = np.abs(inv_o[rows] - inv_o[A.col_idx]).max()
+    print(f"cabin: {lev_o.max() + 1} levels, widest {np.bincount(lev_o).max()}, bandwidth after renumbering {band}")

@@ -1,13 +1,15 @@
 """Pins of the oracle's level-set ordering and symmetric permutation.
 
 The ordering has a plain definition (graph distances from a start found by
-one pseudo-peripheral step, then a sort by (level, index)); these tests fix
+one pseudo-peripheral step, then Cuthill-McKee within the levels); these tests fix
 it by closed forms on graphs whose distances are known (paths, grids, cubes),
-by the defining properties of breadth-first levels on a scrambled mesh, and
-by an independent route to P A P^T (dense permutation, COO re-sort).
+by the defining properties of breadth-first levels on a scrambled mesh, by
+equality with the textbook queue form of Cuthill-McKee, and by an
+independent route to P A P^T (dense permutation, COO re-sort).
 """
 
 import numpy as np
+import pytest
 
 import oracle.reorder as R
 import workloads as W
@@ -46,14 +48,55 @@ def test_path_graph_closed_form():
     assert np.array_equal(inv[perm], np.arange(n))
 
 
+def textbook_cuthill_mckee(row_ptr, col_idx, start):
+    """Queue form: take nodes in order, append each one's unvisited neighbours by (degree, index)."""
+    n = len(row_ptr) - 1
+    deg = np.diff(row_ptr)
+    seen = np.zeros(n, bool)
+    seen[start] = True
+    order, head = [start], 0
+    while head < len(order):
+        v = order[head]
+        head += 1
+        new = sorted({int(c) for c in col_idx[row_ptr[v]:row_ptr[v + 1]] if not seen[c]}, key=lambda c: (deg[c], c))
+        for c in new:
+            seen[c] = True
+        order.extend(new)
+    return np.array(order)
+
+
 def test_grid_levels_are_manhattan_distances_from_far_corner():
     nx, ny = 9, 6
     A = grid_csr(nx, ny)
     perm, inv, level = R.level_order(A.row_ptr, A.col_idx)
     x, y = np.arange(nx * ny) % nx, np.arange(nx * ny) // nx
     assert np.array_equal(level, (nx - 1 - x) + (ny - 1 - y))
-    # order: by level, then by index
-    assert np.array_equal(perm, np.lexsort((np.arange(nx * ny), level)))
+    assert perm[0] == nx * ny - 1 and np.all(np.diff(level[perm]) >= 0)
+
+
+@pytest.mark.parametrize("case", ["grid", "cube", "scrambled_cube", "random_graph"])
+def test_level_formulation_equals_textbook_cuthill_mckee(case):
+    rng = np.random.default_rng(11)
+    if case == "grid":
+        A = grid_csr(7, 5)
+    elif case == "cube":
+        A = W.helmholtz_cube(5)
+    elif case == "scrambled_cube":
+        A0 = W.helmholtz_cube(6)
+        A = permute_symmetric(A0, rng.permutation(A0.n))
+    else:  # connected random graph: a path plus random symmetric chords, varied degrees
+        n = 300
+        r = np.concatenate([np.arange(n - 1), rng.integers(0, n, 400)])
+        c = np.concatenate([np.arange(1, n), rng.integers(0, n, 400)])
+        keep = r != c
+        r, c = r[keep], c[keep]
+        rows = np.concatenate([r, c, np.arange(n)])
+        cols = np.concatenate([c, r, np.arange(n)])
+        key = np.unique(rows * n + cols)
+        A = csr_from_coo(n, key // n, key % n, np.ones(key.size, complex))
+    perm, inv, level = R.level_order(A.row_ptr, A.col_idx)
+    assert np.array_equal(perm, textbook_cuthill_mckee(A.row_ptr, A.col_idx, int(perm[0])))
+    assert np.array_equal(inv[perm], np.arange(A.n))
 
 
 def test_cube_levels_are_3d_manhattan_distances():
