@@ -205,6 +205,27 @@ int zbicgstab_solve_batched(hz_handle *handle, hz_stream stream, int nsys, int n
                             const int *col_idx, const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol,
                             int maxiter, int flags, void *ws, size_t ws_bytes, hz_solve_info *infos);
 
+/* Workspace (bytes) for zbicgstab_solve_sweep: nsys wavenumbers on n rows. */
+size_t zbicgstab_sweep_workspace_bytes(int nsys, int n, int nnz, int flags);
+
+/*
+ * Frequency sweep: solve A(k_j) x_j = b_j for nsys wavenumbers k_j with
+ * A(k) = K - k^2 M + i k B, the finite-element Helmholtz operator (stiffness,
+ * mass and boundary matrices of Section 2's equation) on one pattern.  K, M
+ * and B are real DEVICE arrays of nnz doubles on row_ptr/col_idx (8-byte
+ * aligned); ks is a HOST array of nsys finite wavenumbers.  The same
+ * per-system BiCGStab as zbicgstab_solve_batched (same limits, flags,
+ * layout of b and x [n][nsys], infos and return value), but the entries of
+ * every system are formed on the fly from the three shared arrays: 24 bytes
+ * per entry for the whole sweep instead of 16 bytes per entry per system.
+ * Under HZ_PRECOND_JACOBI each system is scaled by its own diagonal
+ * K_ii - k_j^2 M_ii + i k_j B_ii, applied to the gathered vectors.
+ */
+int zbicgstab_solve_sweep(hz_handle *handle, hz_stream stream, int nsys, int n, int nnz, const int *row_ptr,
+                          const int *col_idx, const double *K, const double *M, const double *B, const double *ks,
+                          const hz_c128 *b, hz_c128 *x, double rtol, int maxiter, int flags, void *ws,
+                          size_t ws_bytes, hz_solve_info *infos);
+
 /* Device workspace (bytes) that zbicgstab_solve_mixed needs. */
 size_t zbicgstab_mixed_workspace_bytes(int n, int nnz, int flags);
 

@@ -63,6 +63,8 @@ SIGNATURES = {
     "zbicgstab_solve_varbatch": (I, [P, P, I, P, I, P, P, P, P, P, D, I, I, P, SZ, P]),
     "zbicgstab_batched_workspace_bytes": (SZ, [I, I, I, I]),
     "zbicgstab_solve_batched": (I, [P, P, I, I, I, P, P, P, P, P, D, I, I, P, SZ, P]),
+    "zbicgstab_sweep_workspace_bytes": (SZ, [I, I, I, I]),
+    "zbicgstab_solve_sweep": (I, [P, P, I, I, I, P, P, P, P, P, P, P, P, D, I, I, P, SZ, P]),
     "csr_zspmv_rect": (I, [P, P, I, I, I, P, P, P, P, P]),
     "csr_zgrad_vals": (I, [P, P, I, I, P, P, P, P, P]),
     "zbicgstab_adjoint_workspace_bytes": (SZ, [I, I, I]),

@@ -409,6 +409,55 @@ def zbicgstab_solve_batched(row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxite
     return x, [i.as_dict() for i in infos]
 
 
+def zbicgstab_sweep_workspace_bytes(nsys: int, n: int, nnz: int, flags: int = 0) -> int:
+    return int(load().zbicgstab_sweep_workspace_bytes(int(nsys), int(n), int(nnz), int(flags)))
+
+
+def zbicgstab_solve_sweep(row_ptr, col_idx, K, M, Bmat, ks, b, x=None, rtol=1e-8, maxiter=20000,
+                          flags=PRECOND_NONE | X0_ZERO, ws=None):
+    """Frequency sweep A(k_j) = K - k_j^2 M + i k_j B on one pattern (zbicgstab_solve_sweep).
+
+    ``K``, ``M``, ``Bmat`` are float64 GPU tensors of nnz entries, ``ks`` a
+    sequence of nsys wavenumbers (host), ``b`` and ``x`` (n, nsys).  Returns
+    (x, [info per system]).
+    """
+    import numpy as np
+
+    dev = K.device
+    _need(row_ptr, "row_ptr", torch.int32, dev)
+    _need(col_idx, "col_idx", torch.int32, dev)
+    n, nnz = row_ptr.numel() - 1, col_idx.numel()
+    for t, name in ((K, "K"), (M, "M"), (Bmat, "Bmat")):
+        _need(t, name, torch.float64, dev)
+        if t.numel() != nnz:
+            raise ValueError(f"{name} must hold nnz entries")
+    kh = np.ascontiguousarray(np.asarray(ks, dtype=np.float64))
+    nsys = kh.size
+    _need(b, "b", torch.complex128, dev)
+    if tuple(b.shape) != (n, nsys):
+        raise ValueError("b must be (n, nsys)")
+    if x is None:
+        x = torch.zeros(n, nsys, dtype=torch.complex128, device=dev)
+        flags |= X0_ZERO
+    _need(x, "x", torch.complex128, dev)
+    if tuple(x.shape) != (n, nsys):
+        raise ValueError("x must be (n, nsys)")
+    need = zbicgstab_sweep_workspace_bytes(nsys, n, nnz, flags)
+    if need == 0:
+        raise ValueError("unsupported number of wavenumbers")
+    if ws is None:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    _need(ws, "ws", torch.uint8, dev)
+    wp, wbytes = _aligned_ptr(ws, need)
+    infos = (HzInfo * nsys)()
+    rc = load().zbicgstab_solve_sweep(handle(dev), _stream(dev), nsys, n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                                      K.data_ptr(), M.data_ptr(), Bmat.data_ptr(), kh.ctypes.data, b.data_ptr(),
+                                      x.data_ptr(), float(rtol), int(maxiter), int(flags), wp, wbytes,
+                                      C.cast(infos, C.c_void_p))
+    _check("zbicgstab_solve_sweep", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
+    return x, [i.as_dict() for i in infos]
+
+
 def zbicgstab_adjoint_batched_workspace_bytes(nsys: int, n: int, nnz: int, flags: int = 0) -> int:
     return int(load().zbicgstab_adjoint_batched_workspace_bytes(int(nsys), int(n), int(nnz), int(flags)))
 

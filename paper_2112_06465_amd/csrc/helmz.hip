@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -703,9 +704,23 @@ template <typename F> void with_multi(int BL, F&& f) {
 constexpr int kMultiU = 4;  // entries in flight per lane in the batched row product (v = A p)
 constexpr int kMultiUt = 3;  // the same for t = A s, whose epilogue holds more registers
 
+// Values of a shared-pattern batch: explicit [nnz][B] values, or a
+// frequency sweep K - k_j^2 M + i k_j Bm from three real [nnz] arrays and the
+// host wavenumbers ks[B].
+struct MultiVals {
+    const double2* vals = nullptr;
+    const double* K = nullptr;
+    const double* M = nullptr;
+    const double* Bm = nullptr;
+    const double* ks = nullptr;
+    bool kmb() const { return vals == nullptr; }
+};
+
 // Workspace of a shared-pattern batch: per-system scalars, partials
 // [kParts][G][BL], the done counter, six [n][B] vectors (r, rhat, p, v, s,
-// t) and, under Jacobi, D^{-1} [n][B] and the column-scaled values [nnz][B].
+// t) and, under Jacobi, D^{-1} [n][B] plus either the column-scaled values
+// [nnz][B] (explicit values) or the scaled gather vectors q = D^{-1} p and
+// u = D^{-1} s [n][B] (a sweep); a sweep also keeps its wavenumbers [B].
 struct MultiWs {
     SolverScal* sc;
     double* part;
@@ -713,9 +728,12 @@ struct MultiWs {
     double2* vec[6];
     double2* dinv;
     double2* ahat;
+    double2* q;
+    double2* u;
+    double* kw;
 };
 
-size_t multi_layout(int B, int n, int64_t nnz, bool jacobi, char* base, MultiWs* out) {
+size_t multi_layout(int B, int n, int64_t nnz, bool jacobi, bool kmb, char* base, MultiWs* out) {
     const int BL = multi_lanes(B);
     const Geom geo = geom_for(n, kBlock / BL);
     size_t off = 0;
@@ -731,7 +749,10 @@ size_t multi_layout(int B, int n, int64_t nnz, bool jacobi, char* base, MultiWs*
     w.ndone = static_cast<int*>(take(sizeof(int)));
     for (auto& v : w.vec) v = static_cast<double2*>(take(sizeof(double2) * nb));
     w.dinv = jacobi ? static_cast<double2*>(take(sizeof(double2) * nb)) : nullptr;
-    w.ahat = jacobi ? static_cast<double2*>(take(sizeof(double2) * zb)) : nullptr;
+    w.ahat = (jacobi && !kmb) ? static_cast<double2*>(take(sizeof(double2) * zb)) : nullptr;
+    w.q = (jacobi && kmb) ? static_cast<double2*>(take(sizeof(double2) * nb)) : nullptr;
+    w.u = (jacobi && kmb) ? static_cast<double2*>(take(sizeof(double2) * nb)) : nullptr;
+    w.kw = kmb ? static_cast<double*>(take(sizeof(double) * size_t(B))) : nullptr;
     if (out) *out = w;
     return off;
 }
@@ -739,6 +760,7 @@ size_t multi_layout(int B, int n, int64_t nnz, bool jacobi, char* base, MultiWs*
 // The five-kernel iteration for every system of the batch, in chunks of 8,
 // 16, ..., 64 iterations with a poll of the done counter between chunks; one
 // more P-kernel after maxiter concludes the last iteration.
+template <int VS>
 int iterate_multi(hz_handle* h, hipStream_t s, const hz::MultiArgs& a, int BL, int maxiter) {
     const dim3 G(a.geo.G), Bk(kBlock);
     int launched = 0, poll = 8, err = 0;
@@ -747,9 +769,9 @@ int iterate_multi(hz_handle* h, hipStream_t s, const hz::MultiArgs& a, int BL, i
             const int k_n = (maxiter - launched) < poll ? (maxiter - launched) : poll;
             for (int k = 0; k < k_n; ++k) {
                 hipLaunchKernelGGL((hz::k_m_P<BB>), G, Bk, 0, s, a);
-                hipLaunchKernelGGL((hz::k_m_A1<BB, kMultiU>), G, Bk, 0, s, a);
+                hipLaunchKernelGGL((hz::k_m_A1<BB, kMultiU, VS>), G, Bk, 0, s, a);
                 hipLaunchKernelGGL((hz::k_m_S<BB>), G, Bk, 0, s, a);
-                hipLaunchKernelGGL((hz::k_m_B1<BB, kMultiUt>), G, Bk, 0, s, a);
+                hipLaunchKernelGGL((hz::k_m_B1<BB, kMultiUt, VS>), G, Bk, 0, s, a);
                 hipLaunchKernelGGL((hz::k_m_C<BB>), G, Bk, 0, s, a);
             }
             launched += k_n;
@@ -767,33 +789,39 @@ int iterate_multi(hz_handle* h, hipStream_t s, const hz::MultiArgs& a, int BL, i
     return err ? HZ_ERR_HIP : HZ_OK;
 }
 
-// B systems on one pattern (values [nnz][B], vectors [n][B]) after argument
-// checks.  infos[j] receives system j's result; returns the largest status.
-int solve_multi(hz_handle* h, hipStream_t s, int B, int n, int nnz, const int* rp, const int* ci, const double2* A,
-                const double2* bd, double2* xd, double rtol, int maxiter, int flags, char* ws, hz_solve_info* infos) {
-    const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
+// y = b - A xin for every system of the batch (the caller's values).
+template <int VS>
+void launch_m_resid(int BL, const hz::MultiArgs& a, const double2* vals, const double2* xin, double2* y,
+                    hipStream_t s) {
+    with_multi(BL, [&]<int BB>() {
+        hipLaunchKernelGGL((hz::k_m_resid<BB, kMultiU, VS>), dim3(a.geo.G), dim3(kBlock), 0, s, a, vals, xin, y);
+    });
+}
+
+// B systems on one pattern (vectors [n][B]) after argument checks.  infos[j]
+// receives system j's result; returns the largest status.
+int solve_multi(hz_handle* h, hipStream_t s, int B, int n, int nnz, const int* rp, const int* ci,
+                const MultiVals& mv, const double2* bd, double2* xd, double rtol, int maxiter, int flags, char* ws,
+                hz_solve_info* infos) {
+    const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0, kmb = mv.kmb();
     const int BL = multi_lanes(B);
     const Geom geo = geom_for(n, kBlock / BL);
     MultiWs w;
-    multi_layout(B, n, nnz, jacobi, ws, &w);
+    multi_layout(B, n, nnz, jacobi, kmb, ws, &w);
     const int64_t nB = int64_t(n) * B;
     HZ_HIP(hipMemsetAsync(w.ndone, 0, sizeof(int), s));
     hipLaunchKernelGGL(hz::k_sc_init, dim3((B + 255) / 256), dim3(256), 0, s, w.sc, B, rtol, maxiter);
-    const double2* Aop = A;
-    if (jacobi) {
-        hipLaunchKernelGGL(hz::k_m_jacobi, grid1(nB), dim3(kBlock), 0, s, n, B, rp, ci, A, w.dinv, w.sc);
-        if (nnz > 0)
-            hipLaunchKernelGGL(hz::k_m_colscale, grid1(int64_t(nnz) * B), dim3(kBlock), 0, s, int64_t(nnz), B, ci,
-                               A, static_cast<const double2*>(w.dinv), w.ahat);
-        Aop = w.ahat;
-    }
-    hz::MultiArgs a;
+    hz::MultiArgs a{};
     a.n = n;
     a.B = B;
     a.geo = geo;
     a.row_ptr = rp;
     a.col_idx = ci;
-    a.vals = Aop;
+    a.vals = mv.vals;
+    a.K = mv.K;
+    a.M = mv.M;
+    a.Bm = mv.Bm;
+    a.kw = w.kw;
     a.b = bd;
     a.r = w.vec[0];
     a.rh = w.vec[1];
@@ -801,22 +829,48 @@ int solve_multi(hz_handle* h, hipStream_t s, int B, int n, int nnz, const int* r
     a.v = w.vec[3];
     a.s = w.vec[4];
     a.t = w.vec[5];
+    a.q = a.p;
+    a.u = a.s;
     a.x = xd;
     a.part = w.part;
     a.sc = w.sc;
     a.ndone = w.ndone;
+    if (kmb) HZ_HIP(hipMemcpyAsync(w.kw, mv.ks, sizeof(double) * size_t(B), hipMemcpyHostToDevice, s));
+    if (jacobi) {
+        if (kmb) {
+            hipLaunchKernelGGL(hz::k_m_jacobi_kmb, grid1(nB), dim3(kBlock), 0, s, n, B, rp, ci, mv.K, mv.M, mv.Bm,
+                               static_cast<const double*>(w.kw), w.dinv, w.sc);
+            a.dinv = w.dinv;
+            a.q = w.q;
+            a.u = w.u;
+        } else {
+            hipLaunchKernelGGL(hz::k_m_jacobi, grid1(nB), dim3(kBlock), 0, s, n, B, rp, ci, mv.vals, w.dinv, w.sc);
+            if (nnz > 0)
+                hipLaunchKernelGGL(hz::k_m_colscale, grid1(int64_t(nnz) * B), dim3(kBlock), 0, s, int64_t(nnz), B,
+                                   ci, mv.vals, static_cast<const double2*>(w.dinv), w.ahat);
+            a.vals = w.ahat;
+        }
+    }
     const dim3 G(geo.G), Bk(kBlock);
     const double2* rsrc = bd;
-    if (flags & HZ_X0_ZERO) HZ_HIP(hipMemsetAsync(xd, 0, sizeof(double2) * size_t(nB), s));
+    if (flags & HZ_X0_ZERO) {
+        HZ_HIP(hipMemsetAsync(xd, 0, sizeof(double2) * size_t(nB), s));
+    } else if (kmb) {
+        // r = b - A x0 on the caller's x0, then y0 = D x0
+        launch_m_resid<hz::VS_KMB>(BL, a, nullptr, static_cast<const double2*>(xd), a.r, s);
+        if (jacobi)
+            hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(nB), Bk, 0, s, int(nB),
+                               static_cast<const double2*>(w.dinv), xd, 1);
+        rsrc = a.r;
+    } else {
+        // y0 = D x0, then r = b - (A D^{-1}) y0
+        if (jacobi)
+            hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(nB), Bk, 0, s, int(nB),
+                               static_cast<const double2*>(w.dinv), xd, 1);
+        launch_m_resid<hz::VS_EXPLICIT>(BL, a, a.vals, static_cast<const double2*>(xd), a.r, s);
+        rsrc = a.r;
+    }
     with_multi(BL, [&]<int BB>() {
-        if (!(flags & HZ_X0_ZERO)) {
-            if (jacobi)
-                hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(nB), Bk, 0, s, int(nB),
-                                   static_cast<const double2*>(w.dinv), xd, 1);
-            hipLaunchKernelGGL((hz::k_m_resid<BB, kMultiU>), G, Bk, 0, s, a, Aop, static_cast<const double2*>(xd),
-                               a.r);
-            rsrc = a.r;
-        }
         hipLaunchKernelGGL((hz::k_m_init<BB>), G, Bk, 0, s, a, rsrc);
         hipLaunchKernelGGL((hz::k_m_fin_init<BB>), dim3(1), Bk, 0, s, a);
     });
@@ -828,18 +882,22 @@ int solve_multi(hz_handle* h, hipStream_t s, int B, int n, int nnz, const int* r
     for (int j = 0; j < B; ++j)
         if (hs[j].bad_diag) return HZ_ERR_INVALID;
     if (*h->hflag < B) {
-        int rc = iterate_multi(h, s, a, BL, maxiter);
+        int rc = kmb ? iterate_multi<hz::VS_KMB>(h, s, a, BL, maxiter)
+                     : iterate_multi<hz::VS_EXPLICIT>(h, s, a, BL, maxiter);
         if (rc) return rc;
     }
     with_multi(BL, [&]<int BB>() {
         hipLaunchKernelGGL((hz::k_m_zero_if<BB>), G, Bk, 0, s, a);
-        if (jacobi)
-            hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(nB), Bk, 0, s, int(nB),
-                               static_cast<const double2*>(w.dinv), xd, 0);
-        // true residual with the caller's values
-        hipLaunchKernelGGL((hz::k_m_resid<BB, kMultiU>), G, Bk, 0, s, a, A, static_cast<const double2*>(xd), a.t);
-        hipLaunchKernelGGL((hz::k_m_fin_true<BB>), dim3(1), Bk, 0, s, a);
     });
+    if (jacobi)
+        hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(nB), Bk, 0, s, int(nB),
+                           static_cast<const double2*>(w.dinv), xd, 0);
+    // true residual with the caller's values
+    if (kmb)
+        launch_m_resid<hz::VS_KMB>(BL, a, nullptr, static_cast<const double2*>(xd), a.t, s);
+    else
+        launch_m_resid<hz::VS_EXPLICIT>(BL, a, mv.vals, static_cast<const double2*>(xd), a.t, s);
+    with_multi(BL, [&]<int BB>() { hipLaunchKernelGGL((hz::k_m_fin_true<BB>), dim3(1), Bk, 0, s, a); });
     HZ_HIP(hipGetLastError());
     HZ_HIP(hipMemcpyAsync(hs.data(), w.sc, sizeof(SolverScal) * size_t(B), hipMemcpyDeviceToHost, s));
     HZ_HIP(hipStreamSynchronize(s));
@@ -879,7 +937,8 @@ size_t adjoint_multi_layout(int B, int n, int64_t nnz, int flags, char* base, Ad
     };
     const size_t nn = size_t(n > 0 ? n : 1), nz = size_t(nnz > 0 ? nnz : 1);
     AdjMultiWs a{};
-    a.solve = static_cast<char*>(take(multi_layout(B, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr)));
+    a.solve =
+        static_cast<char*>(take(multi_layout(B, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, false, nullptr, nullptr)));
     a.gconj = static_cast<double2*>(take(sizeof(double2) * nn * size_t(B)));
     if (!(flags & HZ_SYMMETRIC)) {
         a.t_rp = static_cast<int*>(take(sizeof(int) * (nn + 1)));
@@ -1320,7 +1379,7 @@ int solve_mixed(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, cons
 
 size_t zbicgstab_batched_workspace_bytes(int nsys, int n, int nnz, int flags) {
     if (nsys < 1 || nsys > hz::kMultiMax || n < 0 || nnz < 0) return 0;
-    return multi_layout(nsys, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr);
+    return multi_layout(nsys, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, false, nullptr, nullptr);
 }
 
 int zbicgstab_solve_batched(hz_handle* h, hz_stream stream, int nsys, int n, int nnz, const int* rp, const int* ci,
@@ -1344,9 +1403,49 @@ int zbicgstab_solve_batched(hz_handle* h, hz_stream stream, int nsys, int n, int
         rc = validate_csr(h, s, n, nnz, rp, ci);
         if (rc) return rc;
     }
-    return solve_multi(h, s, nsys, n, nnz, rp, ci, reinterpret_cast<const double2*>(vals),
-                       reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxiter, flags,
+    MultiVals mv;
+    mv.vals = reinterpret_cast<const double2*>(vals);
+    return solve_multi(h, s, nsys, n, nnz, rp, ci, mv, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxiter, flags,
                        static_cast<char*>(ws), infos);
+}
+
+size_t zbicgstab_sweep_workspace_bytes(int nsys, int n, int nnz, int flags) {
+    if (nsys < 1 || nsys > hz::kMultiMax || n < 0 || nnz < 0) return 0;
+    return multi_layout(nsys, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, true, nullptr, nullptr);
+}
+
+int zbicgstab_solve_sweep(hz_handle* h, hz_stream stream, int nsys, int n, int nnz, const int* rp, const int* ci,
+                          const double* K, const double* M, const double* Bmat, const double* ks, const hz_c128* b,
+                          hz_c128* x, double rtol, int maxiter, int flags, void* ws, size_t ws_bytes,
+                          hz_solve_info* infos) {
+    if (h == nullptr || infos == nullptr || nsys < 1 || nsys > hz::kMultiMax) return HZ_ERR_INVALID;
+    std::memset(infos, 0, sizeof(hz_solve_info) * size_t(nsys));
+    int rc = check_csr_args(n, nnz, rp, ci, K);
+    if (rc) return rc;
+    if (!(rtol >= 0.0) || maxiter < 0 || ks == nullptr) return HZ_ERR_INVALID;
+    for (int j = 0; j < nsys; ++j)
+        if (!std::isfinite(ks[j])) return HZ_ERR_INVALID;
+    if (int64_t(n) * nsys >= (int64_t(1) << 31)) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (nnz > 0 && (M == nullptr || Bmat == nullptr || misaligned(K, 8) || misaligned(M, 8) || misaligned(Bmat, 8)))
+        return HZ_ERR_INVALID;
+    if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16)) return HZ_ERR_INVALID;
+    const size_t vb = 16 * size_t(n) * size_t(nsys);
+    if (overlap(b, vb, x, vb)) return HZ_ERR_INVALID;
+    const size_t need = zbicgstab_sweep_workspace_bytes(nsys, n, nnz, flags);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (flags & HZ_VALIDATE) {
+        rc = validate_csr(h, s, n, nnz, rp, ci);
+        if (rc) return rc;
+    }
+    MultiVals mv;
+    mv.K = K;
+    mv.M = M;
+    mv.Bm = Bmat;
+    mv.ks = ks;
+    return solve_multi(h, s, nsys, n, nnz, rp, ci, mv, reinterpret_cast<const double2*>(b),
+                       reinterpret_cast<double2*>(x), rtol, maxiter, flags, static_cast<char*>(ws), infos);
 }
 
 size_t zbicgstab_mixed_workspace_bytes(int n, int nnz, int flags) {
@@ -1538,7 +1637,9 @@ int zbicgstab_adjoint_batched(hz_handle* h, hz_stream stream, int nsys, int n, i
         // A_j^H lambda_j = g_j  <=>  A_j conj(lambda_j) = conj(g_j)  when A_j = A_j^T
         hipLaunchKernelGGL(hz::k_conj, grid1(nB), dim3(kBlock), 0, s, int(nB), g, a.gconj);
         HZ_HIP(hipGetLastError());
-        rc = solve_multi(h, s, nsys, n, nnz, rp, ci, A, a.gconj, lam, rtol, maxiter, sflags, a.solve, infos);
+        MultiVals mv;
+        mv.vals = A;
+        rc = solve_multi(h, s, nsys, n, nnz, rp, ci, mv, a.gconj, lam, rtol, maxiter, sflags, a.solve, infos);
         if (rc < 0) return rc;
         hipLaunchKernelGGL(hz::k_conj, grid1(nB), dim3(kBlock), 0, s, int(nB), static_cast<const double2*>(lam), lam);
     } else {
@@ -1554,7 +1655,9 @@ int zbicgstab_adjoint_batched(hz_handle* h, hz_stream stream, int nsys, int n, i
             hipLaunchKernelGGL(hz::k_m_conj_vals, grid1(int64_t(nnz) * nsys), dim3(kBlock), 0, s, int64_t(nnz), nsys,
                                static_cast<const int*>(a.t_src), A, a.t_vals);
         HZ_HIP(hipGetLastError());
-        rc = solve_multi(h, s, nsys, n, nnz, a.t_rp, a.t_ci, a.t_vals, g, lam, rtol, maxiter, sflags, a.solve, infos);
+        MultiVals mv;
+        mv.vals = a.t_vals;
+        rc = solve_multi(h, s, nsys, n, nnz, a.t_rp, a.t_ci, mv, g, lam, rtol, maxiter, sflags, a.solve, infos);
         if (rc < 0) return rc;
     }
     if (grad_vals != nullptr && nnz > 0) {

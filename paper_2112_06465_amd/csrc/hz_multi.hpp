@@ -34,20 +34,33 @@ namespace hz {
 
 constexpr int kMultiMax = 256;  // most systems per shared-pattern launch
 
+// Where the row product takes system j's entry p from.
+enum : int {
+    VS_EXPLICIT = 0,  // vals[p*B + j] (column-scaled by D_j^{-1} under Jacobi)
+    VS_KMB = 1        // K[p] - k_j^2 M[p] + i k_j Bm[p] (a frequency sweep; never scaled)
+};
+
 struct MultiArgs {
     int n;     // rows of the shared pattern
     int B;     // systems
     Geom geo;  // row chunks of the geo.G blocks
     const int* __restrict__ row_ptr;
     const int* __restrict__ col_idx;
-    const double2* __restrict__ vals;  // [nnz][B], column-scaled under Jacobi
-    const double2* b;                  // [n][B]
+    const double2* __restrict__ vals;  // VS_EXPLICIT: [nnz][B]
+    const double* __restrict__ K;      // VS_KMB: three real [nnz] arrays and the wavenumbers [B]
+    const double* __restrict__ M;
+    const double* __restrict__ Bm;
+    const double* __restrict__ kw;
+    const double2* dinv;  // non-null: the products act on q = D^{-1} p and u = D^{-1} s ([n][B])
+    const double2* b;     // [n][B]
     double2* r;
     double2* rh;
     double2* p;
     double2* v;
     double2* s;
     double2* t;
+    double2* q;  // the vector A1 gathers: p itself, or D^{-1} p written by P
+    double2* u;  // the vector B1 gathers: s itself, or D^{-1} s written by S
     double2* x;
     double* part;    // [kParts][G][BL]
     SolverScal* sc;  // [B]
@@ -118,9 +131,29 @@ template <int BL> __device__ __forceinline__ double* mregion(const MultiArgs& a,
 // The leader of system j: lane j of row slot 0 in logical block 0.
 template <int BL> __device__ __forceinline__ bool mleader(int lb) { return lb == 0 && threadIdx.x < BL; }
 
+// Entry p of system j.  k = (k_j, k_j^2) for VS_KMB.
+template <int VS>
+__device__ __forceinline__ double2 mval(const MultiArgs& a, int p, int j, double2 k) {
+    if constexpr (VS == VS_EXPLICIT) {
+        return a.vals[(size_t)p * a.B + j];
+    } else {
+        return mk<double>(__builtin_fma(-k.y, a.M[p], a.K[p]), k.x * a.Bm[p]);
+    }
+}
+
+template <int VS> __device__ __forceinline__ double2 mwave(const MultiArgs& a, int j) {
+    if constexpr (VS == VS_KMB) {
+        const double kj = a.kw[j];
+        return mk<double>(kj, kj * kj);
+    } else {
+        return mk<double>(0.0, 0.0);
+    }
+}
+
 // Row i of A times X for lane j: entries in order, U loads of each kind in flight.
-template <int U>
-__device__ __forceinline__ double2 mrow(const MultiArgs& a, int64_t i, int j, const double2* __restrict__ X) {
+template <int U, int VS>
+__device__ __forceinline__ double2 mrow(const MultiArgs& a, int64_t i, int j, const double2* __restrict__ X,
+                                        double2 k) {
     const size_t B = (size_t)a.B;
     const int beg = a.row_ptr[i], end = a.row_ptr[i + 1];
     double2 acc = mk<double>(0.0, 0.0);
@@ -131,13 +164,13 @@ __device__ __forceinline__ double2 mrow(const MultiArgs& a, int64_t i, int j, co
 #pragma unroll
         for (int u = 0; u < U; ++u) c[u] = a.col_idx[p + u];
 #pragma unroll
-        for (int u = 0; u < U; ++u) av[u] = a.vals[(size_t)(p + u) * B + j];
+        for (int u = 0; u < U; ++u) av[u] = mval<VS>(a, p + u, j, k);
 #pragma unroll
         for (int u = 0; u < U; ++u) xv[u] = X[(size_t)c[u] * B + j];
 #pragma unroll
         for (int u = 0; u < U; ++u) acc = cfma<double>(av[u], xv[u], acc);
     }
-    for (; p < end; ++p) acc = cfma<double>(a.vals[(size_t)p * B + j], X[(size_t)a.col_idx[p] * B + j], acc);
+    for (; p < end; ++p) acc = cfma<double>(mval<VS>(a, p, j, k), X[(size_t)a.col_idx[p] * B + j], acc);
     return acc;
 }
 
@@ -262,18 +295,20 @@ __global__ HZ_STREAM_BOUNDS void k_m_P(const MultiArgs a) {
                                          pv.y - __builtin_fma(om.x, vv.y, om.y * vv.x));
             a.p[q] = cfma<double>(beta, d, rv);
         }
+        if (a.dinv) a.q[q] = cmul<double>(a.dinv[q], a.p[q]);
     }
 }
 
 // A1-kernel: v = A p; partial <rhat, v>.
-template <int BL, int U>
+template <int BL, int U, int VS>
 __global__ HZ_STREAM_BOUNDS void k_m_A1(const MultiArgs a) {
     if (all_done(a)) return;
     HZ_MULTI_ROWS;
     double e[2] = {0.0, 0.0};
-    if (j < a.B && !a.sc[j].done && !a.sc[j].pending)
+    if (j < a.B && !a.sc[j].done && !a.sc[j].pending) {
+        const double2 k = mwave<VS>(a, j);
         HZ_MROWS(i) {
-            const double2 acc = mrow<U>(a, i, j, a.p);
+            const double2 acc = mrow<U, VS>(a, i, j, a.q, k);
             const size_t q = (size_t)i * Bz + j;
             a.v[q] = acc;
             const double2 w = a.rh[q];
@@ -281,6 +316,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_A1(const MultiArgs a) {
             e[0] = c.x;
             e[1] = c.y;
         }
+    }
     mstore<BL, 2>(mregion<BL>(a, kPartA), a.geo.G, rr.lb, e);
 }
 
@@ -314,6 +350,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_S(const MultiArgs a) {
             const size_t q = (size_t)i * Bz + j;
             const double2 sv = cfma<double>(nal, a.v[q], a.r[q]);
             a.s[q] = sv;
+            if (a.dinv) a.u[q] = cmul<double>(a.dinv[q], sv);
             e[0] = __builtin_fma(sv.x, sv.x, e[0]);
             e[0] = __builtin_fma(sv.y, sv.y, e[0]);
         }
@@ -322,14 +359,15 @@ __global__ HZ_STREAM_BOUNDS void k_m_S(const MultiArgs a) {
 }
 
 // B1-kernel: t = A s; partials <t, s>, ||t||^2.
-template <int BL, int U>
+template <int BL, int U, int VS>
 __global__ HZ_STREAM_BOUNDS void k_m_B1(const MultiArgs a) {
     if (all_done(a)) return;
     HZ_MULTI_ROWS;
     double e[3] = {0.0, 0.0, 0.0};
-    if (j < a.B && !a.sc[j].done)
+    if (j < a.B && !a.sc[j].done) {
+        const double2 k = mwave<VS>(a, j);
         HZ_MROWS(i) {
-            const double2 acc = mrow<U>(a, i, j, a.s);
+            const double2 acc = mrow<U, VS>(a, i, j, a.u, k);
             const size_t q = (size_t)i * Bz + j;
             a.t[q] = acc;
             const double2 sv = a.s[q];
@@ -339,6 +377,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_B1(const MultiArgs a) {
             e[2] = __builtin_fma(acc.x, acc.x, e[2]);
             e[2] = __builtin_fma(acc.y, acc.y, e[2]);
         }
+    }
     mstore<BL, 3>(mregion<BL>(a, kPartB + 1), a.geo.G, rr.lb, e);
 }
 
@@ -417,17 +456,19 @@ __global__ HZ_STREAM_BOUNDS void k_m_C(const MultiArgs a) {
     mstore<BL, 3>(mregion<BL>(a, kPartC), a.geo.G, rr.lb, e);
 }
 
-// y = b - A xin for every system (values `vals`); partial ||y||^2 (I).
-template <int BL, int U>
+// y = b - A xin for every system (explicit values `vals`, or K, M, Bm);
+// partial ||y||^2 (I).
+template <int BL, int U, int VS>
 __global__ HZ_STREAM_BOUNDS void k_m_resid(const MultiArgs a, const double2* __restrict__ vals,
                                            const double2* __restrict__ xin, double2* __restrict__ y) {
     HZ_MULTI_ROWS;
     MultiArgs a2 = a;
     a2.vals = vals;
     double e[1] = {0.0};
+    const double2 k = j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0);
     if (j < a.B)
         HZ_MROWS(i) {
-            const double2 acc = mrow<U>(a2, i, j, xin);
+            const double2 acc = mrow<U, VS>(a2, i, j, xin, k);
             const size_t q = (size_t)i * Bz + j;
             const double2 bv = a.b[q];
             const double2 d = mk<double>(bv.x - acc.x, bv.y - acc.y);
@@ -468,6 +509,30 @@ __global__ __launch_bounds__(kBlock) void k_m_jacobi(int n, int B, const int* __
     double2 d = mk<double>(0.0, 0.0);
     for (int p = rp[i]; p < rp[i + 1]; ++p)
         if (ci[p] == i) d = vals[(size_t)p * B + j];
+    if (d.x == 0.0 && d.y == 0.0) {
+        sc[j].bad_diag = 1;  // every writer stores 1
+        dinv[f] = mk<double>(0.0, 0.0);
+        return;
+    }
+    const double q = d.x * d.x + d.y * d.y;
+    dinv[f] = mk<double>(d.x / q, -d.y / q);
+}
+
+// dinv[i*B + j] = 1 / (K_ii - k_j^2 M_ii + i k_j Bm_ii); a missing or zero
+// diagonal flags sc[j].bad_diag.
+__global__ __launch_bounds__(kBlock) void k_m_jacobi_kmb(int n, int B, const int* __restrict__ rp,
+                                                         const int* __restrict__ ci, const double* __restrict__ K,
+                                                         const double* __restrict__ M, const double* __restrict__ Bm,
+                                                         const double* __restrict__ kw, double2* __restrict__ dinv,
+                                                         SolverScal* sc) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f >= (int64_t)n * B) return;
+    const int64_t i = f / B;
+    const int j = (int)(f % B);
+    const double kj = kw[j];
+    double2 d = mk<double>(0.0, 0.0);
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (ci[p] == i) d = mk<double>(__builtin_fma(-kj * kj, M[p], K[p]), kj * Bm[p]);
     if (d.x == 0.0 && d.y == 0.0) {
         sc[j].bad_diag = 1;  // every writer stores 1
         dinv[f] = mk<double>(0.0, 0.0);

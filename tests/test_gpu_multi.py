@@ -160,3 +160,54 @@ def test_full_size_cylinder_frequency_sweep(hz):
         assert true_relres(A.with_vals(vals[j]), xs[j], rhs[j]) <= 1e-8 * (1 + 1e-3)
         its.append(infos[j]["iterations"])
     print(f"frequency sweep B=64 n={A.n}: iterations min {min(its)} max {max(its)}")
+
+
+def solve_sweep(hz, A, info, ks, rhs, tol, flags, maxiter=20000, x0=None):
+    K, M, Bm = (dev(info[k]) for k in ("K", "M", "B"))
+    x = None if x0 is None else dev(np.ascontiguousarray(x0.T))
+    xs, infos = hz.zbicgstab_solve_sweep(dev(A.row_ptr), dev(A.col_idx), K, M, Bm, ks, dev(np.ascontiguousarray(rhs.T)),
+                                         x=x, rtol=tol, maxiter=maxiter, flags=flags)
+    xs = xs.cpu().numpy()
+    return [xs[:, j].copy() for j in range(len(ks))], infos
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_sweep_from_three_matrices_matches_explicit_values(hz, jacobi):
+    """K - k^2 M + i k B formed in the kernels: same solutions as the batch with explicit values."""
+    A, vals, rhs, ks, info = W.config_freq_sweep(B=6, h=0.1, kmin=4.0, kmax=9.0, seed=6)
+    flags = hz.PRECOND_JACOBI if jacobi else hz.PRECOND_NONE
+    xs, infos = solve_sweep(hz, A, info, ks, rhs, 1e-10, flags)
+    xe, ie = solve_multi(hz, A, vals, rhs, 1e-10, flags)
+    for j in range(6):
+        Aj = A.with_vals(vals[j])
+        assert infos[j]["status"] == hz.OK, infos[j]
+        assert true_relres(Aj, xs[j], rhs[j]) <= 1e-10 * (1 + 1e-3)
+        assert np.linalg.norm(xs[j] - xe[j]) / np.linalg.norm(xe[j]) < 1e-7
+        assert abs(infos[j]["relres_true"] - true_relres(Aj, xs[j], rhs[j])) <= 1e-3 * infos[j]["relres_true"] + 1e-16
+
+
+def test_sweep_initial_guess_and_invalid_wavenumber(hz):
+    A, vals, rhs, ks, info = W.config_freq_sweep(B=3, h=0.15, kmin=3.0, kmax=6.0, seed=7)
+    xa, _ = solve_sweep(hz, A, info, ks, rhs, 1e-4, hz.PRECOND_JACOBI)
+    xs, infos = solve_sweep(hz, A, info, ks, rhs, 1e-10, hz.PRECOND_JACOBI, x0=np.stack(xa))
+    _, cold = solve_sweep(hz, A, info, ks, rhs, 1e-10, hz.PRECOND_JACOBI)
+    for j in range(3):
+        assert infos[j]["status"] == hz.OK and infos[j]["iterations"] < cold[j]["iterations"]
+        assert true_relres(A.with_vals(vals[j]), xs[j], rhs[j]) <= 1e-10 * (1 + 1e-3)
+    bad = np.array(ks, dtype=float)
+    bad[1] = np.nan
+    with pytest.raises(hz.HelmzError) as e:
+        solve_sweep(hz, A, info, bad, rhs, 1e-8, hz.PRECOND_JACOBI)
+    assert e.value.code == -1
+
+
+def test_full_size_cylinder_sweep_from_three_matrices(hz):
+    """64 wavenumbers k ~ U[10, 40] on the cylinder (n=209,777) from K, M, B: Jacobi-BiCGStab to 1e-8 each."""
+    A, vals, rhs, ks, info = W.config_freq_sweep(B=64)
+    xs, infos = solve_sweep(hz, A, info, ks, rhs, 1e-8, hz.PRECOND_JACOBI, maxiter=50000)
+    its = []
+    for j in range(64):
+        assert infos[j]["status"] == hz.OK, (j, ks[j], infos[j])
+        assert true_relres(A.with_vals(vals[j]), xs[j], rhs[j]) <= 1e-8 * (1 + 1e-3)
+        its.append(infos[j]["iterations"])
+    print(f"K/M/B sweep B=64 n={A.n}: iterations min {min(its)} max {max(its)}")

@@ -132,7 +132,8 @@ def config_freq_sweep(
 
     Draw order: node jitter, the B wavenumbers, then B right-hand sides
     (each drawn as in a single solve).  Returns (pattern CSR with the first
-    system's values, vals (B, nnz), rhs (B, n), ks, info).
+    system's values, vals (B, nnz), rhs (B, n), ks, info); info["K"],
+    info["M"], info["B"] are the real matrices on the pattern.
     """
     rng = make_rng(seed)
     mesh = cylinder_mesh(h=h, rng=rng, robin=robin)
@@ -145,7 +146,7 @@ def config_freq_sweep(
     interior = np.flatnonzero(~mesh["boundary_node"])
     A = asm["A"].with_vals(vals[0])
     rhs = np.stack([point_source_rhs(A.n, interior, rng)[0] for _ in range(B)])
-    return A, vals, rhs, ks, {"seed": seed, "workload": f"freq_sweep_B{B}_h{h:g}"}
+    return A, vals, rhs, ks, {"seed": seed, "workload": f"freq_sweep_B{B}_h{h:g}", "K": K, "M": M, "B": Bm}
 
 
 def config_cube_batch(B: int = 32, seed: int = 0, nmin: int = 16, nmax: int = 64):
