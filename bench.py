@@ -122,6 +122,8 @@ def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10, caller_orde
         ("fp64", lambda: hz.zbicgstab_solve(rp, ci, vals, b, x=x, rtol=tol, maxiter=50000, flags=flags, ws=ws)),
         ("mixed", lambda: hz.zbicgstab_solve_mixed(rp, ci, vals, b, x=x, rtol=tol, inner_rtol=1e-4, maxiter=50000,
                                                    flags=flags, ws=wsm)),
+        ("mixed_reliable", lambda: hz.zbicgstab_solve_mixed(rp, ci, vals, b, x=x, rtol=tol, maxiter=50000,
+                                                            flags=flags | hz.RELIABLE, ws=wsm)),
     ]
     if caller_order_too:
         # the same FP64 solve kept in the caller's numbering (no level-set renumbering)
@@ -144,6 +146,7 @@ def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10, caller_orde
         else:
             res[label]["rel_err_vs_fp64"] = float(np.linalg.norm(xh - x64) / np.linalg.norm(x64))
     res["mixed_speedup"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)
+    res["mixed_reliable_speedup"] = round(res["fp64"]["ms"] / res["mixed_reliable"]["ms"], 3)
     return res
 
 

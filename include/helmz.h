@@ -62,6 +62,7 @@ enum {
 #define HZ_SYMMETRIC 0x10     /* caller asserts A = A^T (adjoint shortcut) */
 #define HZ_REORDER 0x20       /* always renumber by level sets first       */
 #define HZ_NO_REORDER 0x40    /* never renumber (smaller workspace)        */
+#define HZ_RELIABLE 0x80      /* mixed: reliable updates, not restarts     */
 
 typedef struct {
     int status;              /* HZ_OK / HZ_NOT_CONVERGED / HZ_BREAKDOWN / HZ_NONFINITE */
@@ -242,6 +243,16 @@ size_t zbicgstab_mixed_workspace_bytes(int n, int nnz, int flags);
  * of inner iterations, info->outer_steps the number of corrections, and
  * info->relres_true the final FP64 residual.  Workspace, stream, x,
  * renumbering and status conventions as for zbicgstab_solve.
+ *
+ * With HZ_RELIABLE the corrections are not separate solves: one complex64
+ * BiCGStab runs on A D^{-1} y = b / ||b|| and, whenever its recursive
+ * residual has fallen by the factor inner_rtol (0 < inner_rtol < 1, e.g.
+ * 0.1) since the last update or the iteration has ended, a reliable update
+ * (Sleijpen and van der Vorst) moves ||b|| D^{-1} y into the FP64 x, forms
+ * r = b - A x in FP64 and replaces the complex64 residual by r / ||b||,
+ * keeping the Krylov directions.  The decision is on the FP64 residual;
+ * info->outer_steps counts the updates (at most max_outer) and
+ * info->iterations the complex64 iterations (at most maxiter in total).
  */
 int zbicgstab_solve_mixed(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr,
                           const int *col_idx, const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol,

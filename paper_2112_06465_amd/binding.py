@@ -16,7 +16,7 @@ from ._lib import HelmzError, HzC128, HzInfo, load
 
 OK, NOT_CONVERGED, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 PRECOND_NONE, PRECOND_JACOBI, X0_ZERO, VALIDATE, SYMMETRIC = 0x0, 0x1, 0x4, 0x8, 0x10
-REORDER, NO_REORDER = 0x20, 0x40
+REORDER, NO_REORDER, RELIABLE = 0x20, 0x40, 0x80
 BD_NONE, BD_RHO, BD_RHAT_V, BD_TT, BD_OMEGA = 0, 1, 2, 3, 4  # info["breakdown"]: the scalar that became 0
 
 _handles: dict[int, int] = {}
@@ -228,13 +228,23 @@ def zbicgstab_solve_mixed(
     b,
     x=None,
     rtol=1e-10,
-    inner_rtol=1e-4,
+    inner_rtol=None,
     maxiter=20000,
-    max_outer=50,
+    max_outer=None,
     flags=PRECOND_NONE | X0_ZERO,
     ws=None,
 ):
-    """Complex64-inner BiCGStab with complex128 refinement (zbicgstab_solve_mixed).  Returns (x, info)."""
+    """Complex64-inner BiCGStab with complex128 refinement (zbicgstab_solve_mixed).  Returns (x, info).
+
+    Defaults: restarted refinement with inner_rtol 1e-4 and at most 50
+    corrections; with RELIABLE in ``flags``, reliable updates every decade
+    (inner_rtol 0.1) and at most 200 of them.
+    """
+    reliable = bool(flags & RELIABLE)
+    if inner_rtol is None:
+        inner_rtol = 0.1 if reliable else 1e-4
+    if max_outer is None:
+        max_outer = 200 if reliable else 50
     dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
     _need(b, "b", torch.complex128, dev)
     if b.numel() != n:

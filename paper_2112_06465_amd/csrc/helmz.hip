@@ -19,6 +19,7 @@
 #include "hz_adjoint.hpp"
 #include "hz_reorder.hpp"
 #include "hz_multi.hpp"
+#include "hz_reliable.hpp"
 
 using hz::cx;
 using hz::Geom;
@@ -1026,6 +1027,253 @@ void launch_grad_vals(int n, const int* rp, const int* ci, const double2* lam, c
 }
 
 
+size_t mixed_ws_bytes(int n, int64_t nnz, int flags) {
+    const size_t inner = mixed_layout(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr);
+    return (flags & HZ_NO_REORDER) ? inner : reorder_layout(n, nnz, nullptr, nullptr) + inner;
+}
+
+// Mixed-precision refinement of one system after argument checks; ws holds
+// mixed_layout's workspace.
+int solve_mixed(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci, const double2* A,
+                const double2* bd, double2* xd, double rtol, double inner_rtol, int maxiter, int max_outer, int flags,
+                char* ws, hz_solve_info* info) {
+    const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
+    MixedWs mw;
+    mixed_layout(n, nnz, jacobi, ws, &mw);
+    const int L = pick_lanes(h, rp, ci, n, nnz);
+    const Geom geo = geom_for(n, kBlock / L);
+    const int row_off[2] = {0, n};
+    const WorkMap m = build_map(1, row_off, L);
+    int rc = upload_map(s, m, mw.in);
+    if (rc) return rc;
+    const dim3 one(1), B(kBlock);
+    double* partI = mw.in.part + hz::kPartI * m.stride;
+
+    hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.outer, 1, rtol, max_outer);
+    hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.in.sc, 1, inner_rtol, maxiter);
+    // complex64 copy of the (column-scaled) matrix; r64 holds the FP64 D^{-1} meanwhile
+    const double2* dinv64 = nullptr;
+    if (jacobi) {
+        hipLaunchKernelGGL(hz::k_jacobi_diag<double>, grid1(n), B, 0, s, n, rp, ci, A, mw.r64, mw.outer);
+        hipLaunchKernelGGL(hz::k_demote_vec, grid1(n), B, 0, s, n, static_cast<const double2*>(mw.r64),
+                           static_cast<float2*>(mw.in.dinv));
+        dinv64 = mw.r64;
+    }
+    if (nnz > 0)
+        hipLaunchKernelGGL(hz::k_demote_vals, grid1(nnz), B, 0, s, int64_t(nnz), ci, A, dinv64,
+                           static_cast<float2*>(mw.in.ahat));
+    if (flags & HZ_X0_ZERO) HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
+    hipLaunchKernelGGL(hz::k_dot_part<1>, dim3(geo.G), B, 0, s, n, geo, bd, nullptr, partI);
+    hipLaunchKernelGGL(hz::k_fin_bnorm, one, B, 0, s, partI, geo.G, mw.outer);
+    HZ_HIP(hipGetLastError());
+    SolverScal* ho = h->hsc2;
+    SolverScal* hi = h->hsc;
+    HZ_HIP(hipMemcpyAsync(ho, mw.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    if (ho->bad_diag) return HZ_ERR_INVALID;
+    const bool fused = choose_fused(h, nnz);
+    const hz::BicgArgs<float> ai =
+        bicg_args<float>(m, rp, ci, static_cast<const float2*>(mw.in.ahat), mw.b32, mw.d32, mw.in);
+
+    const float2* dinv32 = jacobi ? static_cast<const float2*>(mw.in.dinv) : nullptr;
+    int inner_total = 0, outer = 0;
+    for (;; ++outer) {
+        // r = b - A x in FP64, and the outer decision
+        launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, mw.r64, bd, partI), s);
+        hipLaunchKernelGGL(hz::k_fin_outer, one, B, 0, s, partI, geo.G, mw.outer, outer, max_outer);
+        HZ_HIP(hipGetLastError());
+        HZ_HIP(hipMemcpyAsync(ho, mw.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipStreamSynchronize(s));
+        if (ho->done) break;
+        // inner complex64 solve of A d = r / ||r|| from d = 0
+        hipLaunchKernelGGL(hz::k_demote_scaled, grid1(n), B, 0, s, n, static_cast<const double2*>(mw.r64), mw.outer,
+                           mw.b32);
+        HZ_HIP(hipMemsetAsync(mw.d32, 0, 8 * size_t(n), s));
+        HZ_HIP(hipMemsetAsync(mw.in.ndone, 0, sizeof(int), s));
+        hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.in.sc, 1, inner_rtol, maxiter);
+        hipLaunchKernelGGL(hz::k_init<float>, dim3(m.G), B, 0, s, ai, static_cast<const float2*>(mw.b32));
+        hipLaunchKernelGGL(hz::k_fin_init<float>, one, B, 0, s, ai);
+        HZ_HIP(hipGetLastError());
+        rc = iterate<float>(h, s, m, ai, L, maxiter, fused);
+        if (rc) return rc;
+        HZ_HIP(hipMemcpyAsync(hi, mw.in.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipStreamSynchronize(s));
+        inner_total += hi->iters;
+        if (hi->status == HZ_NONFINITE) {
+            info->status = HZ_NONFINITE;
+            info->iterations = inner_total;
+            info->outer_steps = outer + 1;
+            return HZ_NONFINITE;
+        }
+        hipLaunchKernelGGL(hz::k_promote_add, grid1(n), B, 0, s, n, static_cast<const float2*>(mw.d32), dinv32,
+                           static_cast<const SolverScal*>(mw.outer), xd);
+    }
+    if (ho->zero_x) HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipStreamSynchronize(s));
+    info->status = ho->status;
+    info->iterations = inner_total;
+    info->outer_steps = outer;
+    info->relres_recursive = ho->relres;
+    info->relres_true = ho->relres_true;
+    return ho->status;
+}
+
+// Enqueue k iterations of the single-system BiCGStab (no poll).
+template <typename T>
+void launch_iterations(hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>& a, int L, int k, bool fused) {
+    const dim3 G(m.G), B(kBlock);
+    with_lanes(L, [&]<int LL, int UU>() {
+        for (int i = 0; i < k; ++i) {
+            if (fused) {
+                hipLaunchKernelGGL((hz::k_bicg_A<T, LL, UU>), G, B, 0, s, a);
+                hipLaunchKernelGGL((hz::k_bicg_B<T, LL, UU>), G, B, 0, s, a);
+            } else {
+                hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, s, a);
+                hipLaunchKernelGGL((hz::k_bicg_A1<T, LL, UU>), G, B, 0, s, a);
+                hipLaunchKernelGGL((hz::k_bicg_S<T>), G, B, 0, s, a);
+                hipLaunchKernelGGL((hz::k_bicg_B1<T, LL, UU>), G, B, 0, s, a);
+            }
+            hipLaunchKernelGGL((hz::k_bicg_C<T>), G, B, 0, s, a);
+        }
+    });
+}
+
+// Mixed precision with reliable updates (HZ_RELIABLE): one complex64
+// BiCGStab on A D^{-1} y = b / ||b||; whenever its recursive residual has
+// fallen by `delta` since the last update, or the inner iteration has ended,
+// x += ||b|| D^{-1} y in FP64, r64 = b - A x in FP64, and the complex64
+// residual is replaced by r64 / ||b||.  Convergence is decided on r64.  An
+// inner iteration that ends without the true residual meeting rtol (an
+// inner breakdown, or recursive convergence that the true residual does not
+// confirm) restarts from the current r64.  info->outer_steps counts the
+// reliable updates, info->iterations the complex64 iterations.
+int solve_mixed_reliable(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci, const double2* A,
+                         const double2* bd, double2* xd, double rtol, double delta, int maxiter, int max_updates,
+                         int flags, char* ws, hz_solve_info* info) {
+    const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
+    MixedWs mw;
+    mixed_layout(n, nnz, jacobi, ws, &mw);
+    const int L = pick_lanes(h, rp, ci, n, nnz);
+    const Geom geo = geom_for(n, kBlock / L);
+    const int row_off[2] = {0, n};
+    const WorkMap m = build_map(1, row_off, L);
+    int rc = upload_map(s, m, mw.in);
+    if (rc) return rc;
+    const dim3 one(1), B(kBlock);
+    double* partI = mw.in.part + hz::kPartI * m.stride;
+    hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.outer, 1, rtol, max_updates);
+    const double2* dinv64 = nullptr;
+    if (jacobi) {
+        hipLaunchKernelGGL(hz::k_jacobi_diag<double>, grid1(n), B, 0, s, n, rp, ci, A, mw.r64, mw.outer);
+        hipLaunchKernelGGL(hz::k_demote_vec, grid1(n), B, 0, s, n, static_cast<const double2*>(mw.r64),
+                           static_cast<float2*>(mw.in.dinv));
+        dinv64 = mw.r64;
+    }
+    if (nnz > 0)
+        hipLaunchKernelGGL(hz::k_demote_vals, grid1(nnz), B, 0, s, int64_t(nnz), ci, A, dinv64,
+                           static_cast<float2*>(mw.in.ahat));
+    if (flags & HZ_X0_ZERO) HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
+    hipLaunchKernelGGL(hz::k_dot_part<1>, dim3(geo.G), B, 0, s, n, geo, bd, nullptr, partI);
+    hipLaunchKernelGGL(hz::k_fin_bnorm, one, B, 0, s, partI, geo.G, mw.outer);
+    // the true residual of the initial iterate and the first decision
+    launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, mw.r64, bd, partI), s);
+    hipLaunchKernelGGL(hz::k_fin_outer, one, B, 0, s, partI, geo.G, mw.outer, 0, max_updates);
+    HZ_HIP(hipGetLastError());
+    SolverScal* ho = h->hsc2;
+    SolverScal* hi = h->hsc;
+    HZ_HIP(hipMemcpyAsync(ho, mw.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    if (ho->bad_diag) return HZ_ERR_INVALID;
+    const bool fused = choose_fused(h, nnz);
+    const hz::BicgArgs<float> ai =
+        bicg_args<float>(m, rp, ci, static_cast<const float2*>(mw.in.ahat), mw.b32, mw.d32, mw.in);
+    const float2* dinv32 = jacobi ? static_cast<const float2*>(mw.in.dinv) : nullptr;
+
+    // (re)start the complex64 iteration from the current r64: y = 0, r = rhat = r64 / ||b||
+    auto start_inner = [&]() -> int {
+        hipLaunchKernelGGL(hz::k_ru_demote, grid1(n), B, 0, s, n, static_cast<const double2*>(mw.r64),
+                           static_cast<const SolverScal*>(mw.outer), ai.r);
+        HZ_HIP(hipMemsetAsync(mw.d32, 0, 8 * size_t(n), s));
+        HZ_HIP(hipMemsetAsync(mw.in.ndone, 0, sizeof(int), s));
+        hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.in.sc, 1, rtol, maxiter);
+        hipLaunchKernelGGL(hz::k_init<float>, dim3(m.G), B, 0, s, ai, static_cast<const float2*>(ai.r));
+        hipLaunchKernelGGL(hz::k_fin_init<float>, one, B, 0, s, ai);
+        HZ_HIP(hipGetLastError());
+        return HZ_OK;
+    };
+    int updates = 0, inner_done_total = 0, launched = 0, poll = 8;
+    if (!ho->done) {
+        // the inner right-hand side b / ||b|| (its norm, about 1, scales the inner test)
+        hipLaunchKernelGGL(hz::k_ru_demote, grid1(n), B, 0, s, n, bd, static_cast<const SolverScal*>(mw.outer),
+                           mw.b32);
+        rc = start_inner();
+        if (rc) return rc;
+    }
+    double ref = ho->relres;
+    while (!ho->done) {
+        const int k = std::min(poll, std::max(1, maxiter - launched));
+        launch_iterations<float>(s, m, ai, L, k, fused);
+        launched += k;
+        HZ_HIP(hipGetLastError());
+        HZ_HIP(hipMemcpyAsync(hi, mw.in.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipStreamSynchronize(s));
+        if (hi->pending && !hi->done) {  // conclude a half-step exit
+            with_lanes(L, [&]<int LL, int UU>() {
+                hipLaunchKernelGGL((hz::k_bicg_P<float>), dim3(m.G), B, 0, s, ai);
+            });
+            HZ_HIP(hipMemcpyAsync(hi, mw.in.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+            HZ_HIP(hipStreamSynchronize(s));
+        }
+        if (poll < 64) poll *= 2;
+        const bool inner_end = hi->done != 0;
+        if (!(inner_end || hi->relres <= delta * ref || launched >= maxiter)) continue;
+        // reliable update: promote y, the FP64 true residual, the decision
+        hipLaunchKernelGGL(hz::k_ru_promote, grid1(n), B, 0, s, n, mw.d32, dinv32,
+                           static_cast<const SolverScal*>(mw.outer), xd);
+        ++updates;
+        launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, mw.r64, bd, partI), s);
+        hipLaunchKernelGGL(hz::k_fin_outer, one, B, 0, s, partI, geo.G, mw.outer, updates, max_updates);
+        HZ_HIP(hipGetLastError());
+        HZ_HIP(hipMemcpyAsync(ho, mw.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipStreamSynchronize(s));
+        if (hi->status == HZ_NONFINITE && inner_end) {
+            info->status = HZ_NONFINITE;
+            info->iterations = inner_done_total + hi->iters;
+            info->outer_steps = updates;
+            return HZ_NONFINITE;
+        }
+        if (ho->done) {
+            inner_done_total += inner_end ? hi->iters : hi->iter - 1;
+            break;
+        }
+        if (launched >= maxiter) {
+            inner_done_total += inner_end ? hi->iters : hi->iter - 1;
+            ho->status = HZ_NOT_CONVERGED;
+            break;
+        }
+        ref = ho->relres;
+        if (inner_end) {  // the inner iteration ended without the true residual meeting rtol: restart it
+            inner_done_total += hi->iters;
+            rc = start_inner();
+            if (rc) return rc;
+        } else {
+            hipLaunchKernelGGL(hz::k_ru_replace, dim3(m.G), B, 0, s, ai, static_cast<const double2*>(mw.r64),
+                               static_cast<const SolverScal*>(mw.outer));
+            HZ_HIP(hipGetLastError());
+        }
+    }
+    if (ho->zero_x) HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipStreamSynchronize(s));
+    info->status = ho->status;
+    info->iterations = inner_done_total;
+    info->outer_steps = updates;
+    info->relres_recursive = ho->relres;
+    info->relres_true = ho->relres_true;
+    return ho->status;
+}
+
 }  // namespace
 
 // ====================================================================== C-ABI
@@ -1285,98 +1533,6 @@ int zbicgstab_solve_varbatch(hz_handle* h, hz_stream stream, int nsys, const int
                       static_cast<char*>(ws), infos);
 }
 
-size_t mixed_ws_bytes(int n, int64_t nnz, int flags) {
-    const size_t inner = mixed_layout(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr);
-    return (flags & HZ_NO_REORDER) ? inner : reorder_layout(n, nnz, nullptr, nullptr) + inner;
-}
-
-// Mixed-precision refinement of one system after argument checks; ws holds
-// mixed_layout's workspace.
-int solve_mixed(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci, const double2* A,
-                const double2* bd, double2* xd, double rtol, double inner_rtol, int maxiter, int max_outer, int flags,
-                char* ws, hz_solve_info* info) {
-    const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
-    MixedWs mw;
-    mixed_layout(n, nnz, jacobi, ws, &mw);
-    const int L = pick_lanes(h, rp, ci, n, nnz);
-    const Geom geo = geom_for(n, kBlock / L);
-    const int row_off[2] = {0, n};
-    const WorkMap m = build_map(1, row_off, L);
-    int rc = upload_map(s, m, mw.in);
-    if (rc) return rc;
-    const dim3 one(1), B(kBlock);
-    double* partI = mw.in.part + hz::kPartI * m.stride;
-
-    hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.outer, 1, rtol, max_outer);
-    hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.in.sc, 1, inner_rtol, maxiter);
-    // complex64 copy of the (column-scaled) matrix; r64 holds the FP64 D^{-1} meanwhile
-    const double2* dinv64 = nullptr;
-    if (jacobi) {
-        hipLaunchKernelGGL(hz::k_jacobi_diag<double>, grid1(n), B, 0, s, n, rp, ci, A, mw.r64, mw.outer);
-        hipLaunchKernelGGL(hz::k_demote_vec, grid1(n), B, 0, s, n, static_cast<const double2*>(mw.r64),
-                           static_cast<float2*>(mw.in.dinv));
-        dinv64 = mw.r64;
-    }
-    if (nnz > 0)
-        hipLaunchKernelGGL(hz::k_demote_vals, grid1(nnz), B, 0, s, int64_t(nnz), ci, A, dinv64,
-                           static_cast<float2*>(mw.in.ahat));
-    if (flags & HZ_X0_ZERO) HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
-    hipLaunchKernelGGL(hz::k_dot_part<1>, dim3(geo.G), B, 0, s, n, geo, bd, nullptr, partI);
-    hipLaunchKernelGGL(hz::k_fin_bnorm, one, B, 0, s, partI, geo.G, mw.outer);
-    HZ_HIP(hipGetLastError());
-    SolverScal* ho = h->hsc2;
-    SolverScal* hi = h->hsc;
-    HZ_HIP(hipMemcpyAsync(ho, mw.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
-    HZ_HIP(hipStreamSynchronize(s));
-    if (ho->bad_diag) return HZ_ERR_INVALID;
-    const bool fused = choose_fused(h, nnz);
-    const hz::BicgArgs<float> ai =
-        bicg_args<float>(m, rp, ci, static_cast<const float2*>(mw.in.ahat), mw.b32, mw.d32, mw.in);
-
-    const float2* dinv32 = jacobi ? static_cast<const float2*>(mw.in.dinv) : nullptr;
-    int inner_total = 0, outer = 0;
-    for (;; ++outer) {
-        // r = b - A x in FP64, and the outer decision
-        launch_spmv<double, hz::EPI_RESID>(L, spmv_args<double>(n, geo, rp, ci, A, xd, mw.r64, bd, partI), s);
-        hipLaunchKernelGGL(hz::k_fin_outer, one, B, 0, s, partI, geo.G, mw.outer, outer, max_outer);
-        HZ_HIP(hipGetLastError());
-        HZ_HIP(hipMemcpyAsync(ho, mw.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
-        HZ_HIP(hipStreamSynchronize(s));
-        if (ho->done) break;
-        // inner complex64 solve of A d = r / ||r|| from d = 0
-        hipLaunchKernelGGL(hz::k_demote_scaled, grid1(n), B, 0, s, n, static_cast<const double2*>(mw.r64), mw.outer,
-                           mw.b32);
-        HZ_HIP(hipMemsetAsync(mw.d32, 0, 8 * size_t(n), s));
-        HZ_HIP(hipMemsetAsync(mw.in.ndone, 0, sizeof(int), s));
-        hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.in.sc, 1, inner_rtol, maxiter);
-        hipLaunchKernelGGL(hz::k_init<float>, dim3(m.G), B, 0, s, ai, static_cast<const float2*>(mw.b32));
-        hipLaunchKernelGGL(hz::k_fin_init<float>, one, B, 0, s, ai);
-        HZ_HIP(hipGetLastError());
-        rc = iterate<float>(h, s, m, ai, L, maxiter, fused);
-        if (rc) return rc;
-        HZ_HIP(hipMemcpyAsync(hi, mw.in.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
-        HZ_HIP(hipStreamSynchronize(s));
-        inner_total += hi->iters;
-        if (hi->status == HZ_NONFINITE) {
-            info->status = HZ_NONFINITE;
-            info->iterations = inner_total;
-            info->outer_steps = outer + 1;
-            return HZ_NONFINITE;
-        }
-        hipLaunchKernelGGL(hz::k_promote_add, grid1(n), B, 0, s, n, static_cast<const float2*>(mw.d32), dinv32,
-                           static_cast<const SolverScal*>(mw.outer), xd);
-    }
-    if (ho->zero_x) HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
-    HZ_HIP(hipGetLastError());
-    HZ_HIP(hipStreamSynchronize(s));
-    info->status = ho->status;
-    info->iterations = inner_total;
-    info->outer_steps = outer;
-    info->relres_recursive = ho->relres;
-    info->relres_true = ho->relres_true;
-    return ho->status;
-}
-
 size_t zbicgstab_batched_workspace_bytes(int nsys, int n, int nnz, int flags) {
     if (nsys < 1 || nsys > hz::kMultiMax || n < 0 || nnz < 0) return 0;
     return multi_layout(nsys, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, false, nullptr, nullptr);
@@ -1461,6 +1617,7 @@ int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const 
     int rc = check_csr_args(n, nnz, rp, ci, vals);
     if (rc) return rc;
     if (!(rtol >= 0.0) || !(inner_rtol > 0.0) || maxiter < 0 || max_outer < 0) return HZ_ERR_INVALID;
+    if ((flags & HZ_RELIABLE) && !(inner_rtol < 1.0)) return HZ_ERR_INVALID;
     if (n == 0) return HZ_OK;
     if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
         return HZ_ERR_INVALID;
@@ -1480,7 +1637,14 @@ int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const 
     bool re = false;
     rc = want_reorder(h, s, n, nnz, rp, ci, flags, &re);
     if (rc) return rc;
-    if (!re) return solve_mixed(h, s, n, nnz, rp, ci, A, bd, xd, rtol, inner_rtol, maxiter, max_outer, flags, w, info);
+    auto run = [&](const int* rp_, const int* ci_, const double2* A_, const double2* b_, double2* x_, char* w_) {
+        return (flags & HZ_RELIABLE)
+                   ? solve_mixed_reliable(h, s, n, nnz, rp_, ci_, A_, b_, x_, rtol, inner_rtol, maxiter, max_outer,
+                                          flags, w_, info)
+                   : solve_mixed(h, s, n, nnz, rp_, ci_, A_, b_, x_, rtol, inner_rtol, maxiter, max_outer, flags, w_,
+                                 info);
+    };
+    if (!re) return run(rp, ci, A, bd, xd, w);
     // P A P^T (P x) = P b in the level-set numbering, then x scattered back
     ReorderWs r;
     const size_t off = reorder_layout(n, nnz, w, &r);
@@ -1493,8 +1657,7 @@ int zbicgstab_solve_mixed(hz_handle* h, hz_stream stream, int n, int nnz, const 
         hipLaunchKernelGGL(hz::k_gather_perm<double>, grid1(n), dim3(kBlock), 0, s, n, r.perm,
                            static_cast<const double2*>(xd), r.x);
     HZ_HIP(hipGetLastError());
-    rc = solve_mixed(h, s, n, nnz, r.rp, r.ci, r.vals, r.b, r.x, rtol, inner_rtol, maxiter, max_outer, flags,
-                     w + off, info);
+    rc = run(r.rp, r.ci, r.vals, r.b, r.x, w + off);
     if (rc < 0) return rc;
     info->renumbered = 1;
     hipLaunchKernelGGL(hz::k_scatter_perm<double>, grid1(n), dim3(kBlock), 0, s, n, r.perm,

@@ -90,3 +90,58 @@ def test_mixed_cylinder_full_size(hz):
     rr = true_relres(A, x.cpu().numpy(), b)
     print(f"mixed cylinder: outer={info['outer_steps']} inner={info['iterations']} relres={rr:.2e}")
     assert rr <= 1e-10 * (1 + 1e-3)
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_reliable_updates_reach_fp64_tolerance(hz, jacobi):
+    """One complex64 BiCGStab with reliable FP64 residual updates: FP64 accuracy, fewer iterations than restarts."""
+    A, b, _ = W.config_cube(20)
+    flags = hz.PRECOND_JACOBI if jacobi else hz.PRECOND_NONE
+    rp, ci, v = dev_csr(A)
+    xr, ir = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-10, flags=flags | hz.RELIABLE)
+    xi, ii = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-10, flags=flags)
+    x64, i64 = hz.zbicgstab_solve(rp, ci, v, dev(b), rtol=1e-12, flags=flags)
+    assert ir["status"] == hz.OK and ir["outer_steps"] >= 2
+    xr = xr.cpu().numpy()
+    assert true_relres(A, xr, b) <= 1e-10 * (1 + 1e-3)
+    assert abs(ir["relres_true"] - true_relres(A, xr, b)) <= 1e-3 * ir["relres_true"]
+    x64 = x64.cpu().numpy()
+    assert np.linalg.norm(xr - x64) / np.linalg.norm(x64) <= 1e-6
+    print(f"cube: reliable {ir['iterations']} its / {ir['outer_steps']} updates, "
+          f"restarted {ii['iterations']} its / {ii['outer_steps']} corrections")
+
+
+def test_reliable_updates_special_cases(hz):
+    A, b, _ = W.config_cube(8)
+    rp, ci, v = dev_csr(A)
+    x, info = hz.zbicgstab_solve_mixed(rp, ci, v, dev(np.zeros(A.n, complex)), flags=hz.RELIABLE)
+    assert info["status"] == hz.OK and torch.count_nonzero(x) == 0
+    x, info = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-14, maxiter=5, flags=hz.RELIABLE)
+    assert info["status"] == hz.NOT_CONVERGED
+    with pytest.raises(hz.HelmzError):
+        hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), inner_rtol=1.0, flags=hz.RELIABLE)
+    # an initial guess is used: its residual is where the updates start from
+    xa, _ = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-5, flags=hz.RELIABLE)
+    xb, ib = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), x=xa.clone(), rtol=1e-10, flags=hz.RELIABLE)
+    _, ic = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-10, flags=hz.RELIABLE)
+    assert ib["status"] == hz.OK and ib["iterations"] < ic["iterations"]
+    assert true_relres(A, xb.cpu().numpy(), b) <= 1e-10 * (1 + 1e-3)
+
+
+def test_reliable_updates_renumbered_cabin(hz):
+    A, b, _ = W.config_cabin(h=0.05, k=12.0, seed=5)
+    rp, ci, v = dev_csr(A)
+    x, info = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-10,
+                                       flags=hz.PRECOND_JACOBI | hz.RELIABLE | hz.REORDER)
+    assert info["status"] == hz.OK and info["renumbered"] == 1
+    assert true_relres(A, x.cpu().numpy(), b) <= 1e-10 * (1 + 1e-3)
+
+
+def test_reliable_updates_cylinder_full_size(hz):
+    A, b, _ = W.config_cylinder()
+    rp, ci, v = dev_csr(A)
+    x, info = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-10, flags=hz.PRECOND_JACOBI | hz.RELIABLE)
+    assert info["status"] == hz.OK, info
+    rr = true_relres(A, x.cpu().numpy(), b)
+    print(f"reliable cylinder: updates={info['outer_steps']} iterations={info['iterations']} relres={rr:.2e}")
+    assert rr <= 1e-10 * (1 + 1e-3)
