@@ -46,10 +46,12 @@ N_REPLICAS = 6
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def spmv_kernel_name(L):
-    """Name of the standalone zSpMV instantiation for L lanes per row (batch U)."""
-    U = 1 if L >= 16 else 2
-    return f"hz::k_spmv<double, {L}, {U}, 0>"
+def spmv_kernel_name(form, L):
+    """Name of the standalone zSpMV kernel for a form ("rows" / "tiles") and lane count."""
+    if form == "tiles":
+        return "hz::k_spmv_tile<double>"
+    U = 4 if L <= 4 else (2 if L == 8 else 1)
+    return f"hz::k_spmv_pipe<double, {L}, {U}>"
 
 
 def spmv_bytes(n, nnz):
@@ -61,10 +63,11 @@ def solve_bytes(n, nnz, iterations):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the device source of the SpMV kernel (hz_kernels.hpp)."""
+    """Hash of the device source of the standalone SpMV kernels (hz_spmv.hpp and hz_kernels.hpp)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2112_06465_amd", "csrc", "hz_kernels.hpp"), "rb") as fh:
-        h.update(fh.read())
+    for f in ("hz_spmv.hpp", "hz_kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2112_06465_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -179,7 +182,10 @@ def spmv_cabin(hz, torch, dev, A, rp, ci, vals, reps=10):
     torch.cuda.synchronize()
     res["analysis_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
     res["levels"] = int(level.max().item()) + 1
-    res["level_sets"] = timed(rp2, ci2, v2, x[perm.long()].contiguous())
+    xp = x[perm.long()].contiguous()
+    res["level_sets"] = timed(rp2, ci2, v2, xp)
+    tune = hz.autotune_spmv(rp2, ci2, v2, xp, details=True)
+    res["level_sets_tuned"] = dict(timed(rp2, ci2, v2, xp), form=tune["form"], lanes=tune["form_lanes"])
     return res
 
 
@@ -386,9 +392,10 @@ def main():
     xv = torch.from_numpy(x_np).to(dev)
     yv = torch.empty_like(xv)
     zv = xv.clone()
-    # rows per wavefront for this matrix, tuned outside the timed region; the replicas below are copies
-    # (other index arrays for the handle), so the tuned count is pinned around their products
-    lanes = hz.autotune_spmv(rp, ci, vals, xv)
+    # launch shapes for this matrix, tuned outside the timed region; the replicas below are copies
+    # (other index arrays for the handle), so the tuned form is pinned around their products
+    tune = hz.autotune_spmv(rp, ci, vals, xv, details=True)
+    lanes, sp_form, sp_lanes = tune["lanes"], tune["form"], tune["form_lanes"]
     xs = torch.zeros_like(b)
     flags = hz.PRECOND_JACOBI | hz.X0_ZERO
     ws = hz.workspace(n, nnz, flags, dev)
@@ -400,12 +407,12 @@ def main():
 
     def step(record):
         spmv_ms = []
-        os.environ["HZ_SPMV_LANES"] = str(lanes)
+        os.environ["HZ_SPMV_FORM"], os.environ["HZ_SPMV_LANES"] = sp_form, str(sp_lanes)
         ev[0].record()
         for r in range(args.spmv_reps):
             hz.csr_zspmv(*reps[r % N_REPLICAS])
         ev[1].record()
-        del os.environ["HZ_SPMV_LANES"]
+        del os.environ["HZ_SPMV_FORM"], os.environ["HZ_SPMV_LANES"]
         hz.zdotc(xv, yv, out=dotout)
         hz.zaxpy(0.7 - 0.3j, xv, zv)
         _, sinfo = hz.zbicgstab_solve(rp, ci, vals, b, x=xs, rtol=args.tol, maxiter=20000, flags=flags, ws=ws)
@@ -437,7 +444,7 @@ def main():
     value = sum(step_bytes) / total_s / 1e9
     spmv_avg_s = float(np.mean(spmv_all)) / 1e3
     spmv_gbs = spmv_bytes(n, nnz) / spmv_avg_s / 1e9
-    traffic = read_traffic(spmv_kernel_name(lanes))
+    traffic = read_traffic(spmv_kernel_name(sp_form, sp_lanes))
 
     # correctness of the last solve, checked on the host with the oracle
     import oracle as O
@@ -467,8 +474,9 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": spmv_kernel_name(lanes),
-            "lanes_per_row": lanes,
+            "kernel": spmv_kernel_name(sp_form, sp_lanes),
+            "form": sp_form,
+            "lanes_per_row": sp_lanes,
             "achieved": round(spmv_gbs, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

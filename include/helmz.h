@@ -95,25 +95,38 @@ const char *hz_strerror(int code);
 /*
  * y = A x, complex128 CSR sparse matrix-vector product (Sections 3.2, 6).
  * x and y hold n entries and must not overlap.  n = 0 is a no-op.
+ * Runs in one of two forms (HZ_SPMV_FORM_*; see hz_autotune_spmv): vector
+ * rows, L lanes per row, with the next rows' loads issued while the current
+ * rows' x gathers are in flight; or block tiles of 64 rows whose entries the
+ * whole block loads contiguously and multiplies into LDS before each row is
+ * summed there.  The result is bitwise reproducible for a given form and L.
  */
 int csr_zspmv(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
               const hz_c128 *vals, const hz_c128 *x, hz_c128 *y);
 
+enum { HZ_SPMV_FORM_ROWS = 0, HZ_SPMV_FORM_TILES = 1 };
+
 /*
- * Autotuner of the product's launch shape (rows per wavefront).  Every
- * product and solve kernel gives a row L lanes (L = 2 ... 64, so 64/L rows
- * per wavefront); the built-in rule takes the smallest power of two not
- * below half the mean row length.  This call times csr_zspmv with each L on
- * the caller's matrix and vectors (two rounds of 5 launches after 2 warm-up
- * launches, HIP events on `stream`), writes the fastest L to *lanes (host)
- * and records it in the handle for this (row_ptr, col_idx, n, nnz): later
+ * Autotuner of the launch shapes for one matrix.  Two choices are made:
+ *  - the lanes per row L (2 ... 64, so 64/L rows per wavefront) of the
+ *    solver kernels' fused row products, timed on that row product;
+ *  - the form of the standalone product (csr_zspmv, csr_cspmv,
+ *    csr_zspmv_rect): vector rows with each L, or block tiles.
+ * Each candidate is timed on the caller's matrix and vectors (two rounds of
+ * 5 launches after 2 warm-up launches, HIP events on `stream`); the fastest
+ * are recorded in the handle for this (row_ptr, col_idx, n, nnz), and later
  * products and solves on the same handle with the same index arrays use
- * it (results change only by summation order).  y is overwritten with A x.
- * Synchronises the stream.  The environment variable HZ_SPMV_LANES, when
- * set, overrides both the rule and the tuned choice.
+ * them (results change only by summation order).  Without tuning, both use
+ * vector rows with the smallest power of two L not below half the mean row
+ * length.  Writes the solver lane count to *lanes, and, where the pointers
+ * are not NULL, the standalone form to *form (HZ_SPMV_FORM_*) and its lane
+ * count to *form_lanes (host memory).  y is overwritten with A x.
+ * Synchronises the stream.  The environment variables HZ_SPMV_LANES (a lane
+ * count) and HZ_SPMV_FORM ("rows" or "tiles"), when set, override the rule
+ * and the tuned choices.
  */
 int hz_autotune_spmv(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
-                     const hz_c128 *vals, const hz_c128 *x, hz_c128 *y, int *lanes);
+                     const hz_c128 *vals, const hz_c128 *x, hz_c128 *y, int *lanes, int *form, int *form_lanes);
 
 /* Same product with complex64 values, vectors and arithmetic. */
 int csr_cspmv(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,

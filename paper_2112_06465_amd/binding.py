@@ -93,8 +93,13 @@ def csr_zspmv(row_ptr, col_idx, vals, x, y=None):
     return y
 
 
-def autotune_spmv(row_ptr, col_idx, vals, x=None) -> int:
-    """Time every lane count on this matrix and keep the fastest for it (hz_autotune_spmv); returns it."""
+def autotune_spmv(row_ptr, col_idx, vals, x=None, details=False):
+    """Time the launch shapes on this matrix and keep the fastest for it (hz_autotune_spmv).
+
+    Returns the solver kernels' lane count; with details=True a dict with
+    that count ("lanes"), the standalone product's form ("form": "rows" or
+    "tiles") and its lane count ("form_lanes").
+    """
     dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
     if x is None:
         g = torch.Generator(device="cpu").manual_seed(0)
@@ -103,10 +108,12 @@ def autotune_spmv(row_ptr, col_idx, vals, x=None) -> int:
     if x.numel() != n:
         raise ValueError("x has the wrong length")
     y = torch.empty(n, dtype=torch.complex128, device=dev)
-    L = C.c_int(0)
+    L, F, FL = C.c_int(0), C.c_int(0), C.c_int(0)
     rc = load().hz_autotune_spmv(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
-                                 vals.data_ptr(), x.data_ptr(), y.data_ptr(), C.byref(L))
+                                 vals.data_ptr(), x.data_ptr(), y.data_ptr(), C.byref(L), C.byref(F), C.byref(FL))
     _check("hz_autotune_spmv", rc)
+    if details:
+        return {"lanes": int(L.value), "form": ("rows", "tiles")[F.value], "form_lanes": int(FL.value)}
     return int(L.value)
 
 

@@ -20,6 +20,7 @@
 #include "hz_reorder.hpp"
 #include "hz_multi.hpp"
 #include "hz_reliable.hpp"
+#include "hz_spmv.hpp"
 
 using hz::cx;
 using hz::Geom;
@@ -28,13 +29,22 @@ using hz::kMaxGrid;
 using hz::kParts;
 using hz::SolverScal;
 
-// A lane count picked by hz_autotune_spmv for one matrix (by its index arrays).
+// Form of a standalone row product (hz_spmv.hpp).
+enum SpForm : int { SP_PIPE = HZ_SPMV_FORM_ROWS, SP_TILE = HZ_SPMV_FORM_TILES };
+struct SpPlan {
+    int form;  // SP_PIPE or SP_TILE
+    int L;     // lanes per row of SP_PIPE
+};
+
+// What hz_autotune_spmv picked for one matrix (by its index arrays): the lane
+// count of the solver kernels' row products and the standalone product's plan.
 struct TuneEntry {
     const int* rp;
     const int* ci;
     int n;
     int64_t nnz;
     int L;
+    SpPlan sp;
 };
 
 struct hz_handle {
@@ -91,6 +101,33 @@ int pick_lanes(const hz_handle* h, const int* rp, const int* ci, int n, int64_t 
     return rule_lanes(n, nnz);
 }
 
+// The standalone product's plan: HZ_SPMV_FORM ("rows" / "tiles") and
+// HZ_SPMV_LANES if set, else the autotuned plan, else pipelined rows with the
+// lane rule.
+SpPlan pick_sp(const hz_handle* h, const int* rp, const int* ci, int n, int64_t nnz) {
+    SpPlan p{SP_PIPE, rule_lanes(n, nnz)};
+    bool tuned = false;
+    if (h != nullptr)
+        for (auto it = h->tune.rbegin(); it != h->tune.rend(); ++it)
+            if (it->rp == rp && it->ci == ci && it->n == n && it->nnz == nnz) {
+                p = it->sp;
+                tuned = true;
+                break;
+            }
+    if (const char* env = std::getenv("HZ_SPMV_LANES")) {
+        const int v = std::atoi(env);
+        if (v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64) {
+            p.L = v;
+            if (!tuned) p.form = SP_PIPE;
+        }
+    }
+    if (const char* env = std::getenv("HZ_SPMV_FORM")) {
+        if (std::strcmp(env, "rows") == 0) p.form = SP_PIPE;
+        if (std::strcmp(env, "tiles") == 0) p.form = SP_TILE;
+    }
+    return p;
+}
+
 // Blocks of a launch over n rows taken `step` rows at a time: G <= kMaxGrid,
 // a multiple of 8 when there are at least 8 (one group per XCD, struct Rows).
 Geom geom_for(int n, int step) {
@@ -125,6 +162,42 @@ void launch_spmv(int L, const hz::SpmvArgs<T>& a, hipStream_t s) {
     });
 }
 
+// Entries per lane in the first batch of a pipelined row (16 slots up to L = 8).
+constexpr int pipe_batch(int L) { return L <= 4 ? 4 : (L == 8 ? 2 : 1); }
+
+// Blocks of a standalone product over n rows, `rows` per block step.
+Geom geom_sp(int n, int rows) {
+    const int64_t steps = (int64_t(n) + rows - 1) / rows;
+    int64_t G = steps < hz::kSpMaxGrid ? steps : hz::kSpMaxGrid;
+    if (G < 1) G = 1;
+    if (G >= hz::kXcd) G -= G % hz::kXcd;
+    return Geom{int(G)};
+}
+
+// y = A x on m rows in the plan's form (nnz >= 1 and at least one x element).
+template <typename T>
+void launch_sp(const SpPlan& p, int m, int nnz, const int* rp, const int* ci, const cx<T>* v, const cx<T>* x,
+               cx<T>* y, hipStream_t s) {
+    hz::SpArgs<T> a{m, nnz, Geom{1}, rp, ci, v, x, y};
+    if (p.form == SP_TILE) {
+        a.geo = geom_sp(m, hz::kTileRows);
+        hipLaunchKernelGGL((hz::k_spmv_tile<T>), dim3(a.geo.G), dim3(hz::kSpBlock), 0, s, a);
+        return;
+    }
+    auto go = [&]<int L>() {
+        a.geo = geom_sp(m, hz::kSpBlock / L);
+        hipLaunchKernelGGL((hz::k_spmv_pipe<T, L, pipe_batch(L)>), dim3(a.geo.G), dim3(hz::kSpBlock), 0, s, a);
+    };
+    switch (p.L) {
+        case 2: go.template operator()<2>(); break;
+        case 4: go.template operator()<4>(); break;
+        case 8: go.template operator()<8>(); break;
+        case 16: go.template operator()<16>(); break;
+        case 32: go.template operator()<32>(); break;
+        default: go.template operator()<64>(); break;
+    }
+}
+
 template <typename T>
 hz::SpmvArgs<T> spmv_args(int n, Geom geo, const int* rp, const int* ci, const cx<T>* v, const cx<T>* x, cx<T>* y,
                           const cx<T>* w, double* part) {
@@ -139,6 +212,19 @@ hz::SpmvArgs<T> spmv_args(int n, Geom geo, const int* rp, const int* ci, const c
     a.w = w;
     a.part = part;
     return a;
+}
+
+// The standalone product y = A x (m rows, at least one x element): the plan's
+// form, or the vector rows of the solver kernels for a matrix without entries.
+template <typename T>
+void standalone_spmv(const hz_handle* h, int m, int nnz, const int* rp, const int* ci, const cx<T>* v, const cx<T>* x,
+                     cx<T>* y, hipStream_t s) {
+    if (nnz > 0) {
+        launch_sp<T>(pick_sp(h, rp, ci, m, nnz), m, nnz, rp, ci, v, x, y, s);
+        return;
+    }
+    const int L = pick_lanes(h, rp, ci, m, nnz);
+    launch_spmv<T, hz::EPI_NONE>(L, spmv_args<T>(m, geom_for(m, kBlock / L), rp, ci, v, x, y, nullptr, nullptr), s);
 }
 
 // Device CSR structure check; synchronises the stream.
@@ -1339,11 +1425,13 @@ static int spmv_common_checks(hz_handle* h, int n, int nnz, const int* rp, const
 }
 
 int hz_autotune_spmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci,
-                     const hz_c128* vals, const hz_c128* x, hz_c128* y, int* lanes) {
+                     const hz_c128* vals, const hz_c128* x, hz_c128* y, int* lanes, int* form, int* form_lanes) {
     int rc = spmv_common_checks(h, n, nnz, rp, ci, vals, x, y, sizeof(hz_c128));
     if (rc) return rc;
     if (lanes == nullptr) return HZ_ERR_INVALID;
     *lanes = rule_lanes(n, nnz);
+    if (form != nullptr) *form = SP_PIPE;
+    if (form_lanes != nullptr) *form_lanes = *lanes;
     if (n == 0) return HZ_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1351,37 +1439,60 @@ int hz_autotune_spmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* 
         if (ev[0]) (void)hipEventDestroy(ev[0]);
         return HZ_ERR_HIP;
     }
+    const double2* A = reinterpret_cast<const double2*>(vals);
+    const double2* xd = reinterpret_cast<const double2*>(x);
+    double2* yd = reinterpret_cast<double2*>(y);
+    // 2 warm-up and 5 timed launches of one candidate; the faster of two rounds counts
+    auto time_it = [&](auto&& launch, float& best) {
+        for (int k = 0; k < 2; ++k) launch();
+        if (hipEventRecord(ev[0], s) != hipSuccess) rc = HZ_ERR_HIP;
+        for (int k = 0; k < 5; ++k) launch();
+        float ms = 0.f;
+        if (rc == HZ_OK && (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
+                            hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+            rc = HZ_ERR_HIP;
+        if (rc == HZ_OK && ms < best) best = ms;
+    };
+    // the solver kernels' lane count, timed on their row product
     constexpr int kCand[6] = {2, 4, 8, 16, 32, 64};
     float best_ms[6];
     for (float& b : best_ms) b = 1e30f;
     rc = HZ_OK;
-    // two rounds over the candidates, 2 warm-up and 5 timed launches each; the faster round counts
     for (int round = 0; round < 2 && rc == HZ_OK; ++round)
         for (int c = 0; c < 6 && rc == HZ_OK; ++c) {
             const int L = kCand[c];
-            const Geom geo = geom_for(n, kBlock / L);
-            auto a = spmv_args<double>(n, geo, rp, ci, reinterpret_cast<const double2*>(vals),
-                                       reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nullptr,
-                                       nullptr);
-            for (int k = 0; k < 2; ++k) launch_spmv<double, hz::EPI_NONE>(L, a, s);
-            if (hipEventRecord(ev[0], s) != hipSuccess) rc = HZ_ERR_HIP;
-            for (int k = 0; k < 5; ++k) launch_spmv<double, hz::EPI_NONE>(L, a, s);
-            float ms = 0.f;
-            if (rc == HZ_OK && (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess ||
-                                hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
-                rc = HZ_ERR_HIP;
-            if (rc == HZ_OK && ms < best_ms[c]) best_ms[c] = ms;
+            const auto a = spmv_args<double>(n, geom_for(n, kBlock / L), rp, ci, A, xd, yd, nullptr, nullptr);
+            time_it([&] { launch_spmv<double, hz::EPI_NONE>(L, a, s); }, best_ms[c]);
         }
+    // the standalone product's plan: pipelined rows at each lane count, and block tiles
+    constexpr int kPlans = 7;
+    const SpPlan plans[kPlans] = {{SP_PIPE, 2},  {SP_PIPE, 4},  {SP_PIPE, 8}, {SP_PIPE, 16},
+                                  {SP_PIPE, 32}, {SP_PIPE, 64}, {SP_TILE, hz::kTileLanes}};
+    float plan_ms[kPlans];
+    for (float& b : plan_ms) b = 1e30f;
+    if (nnz > 0)
+        for (int round = 0; round < 2 && rc == HZ_OK; ++round)
+            for (int c = 0; c < kPlans && rc == HZ_OK; ++c)
+                time_it([&] { launch_sp<double>(plans[c], n, nnz, rp, ci, A, xd, yd, s); }, plan_ms[c]);
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     if (rc) return rc;
     int bc = 0;
     for (int c = 1; c < 6; ++c)
         if (best_ms[c] < best_ms[bc]) bc = c;
+    SpPlan sp{SP_PIPE, rule_lanes(n, nnz)};
+    if (nnz > 0) {
+        int bp = 0;
+        for (int c = 1; c < kPlans; ++c)
+            if (plan_ms[c] < plan_ms[bp]) bp = c;
+        sp = plans[bp];
+    }
     for (auto it = h->tune.begin(); it != h->tune.end();)
         it = (it->rp == rp && it->ci == ci && it->n == n && it->nnz == nnz) ? h->tune.erase(it) : it + 1;
-    h->tune.push_back(TuneEntry{rp, ci, n, nnz, kCand[bc]});
+    h->tune.push_back(TuneEntry{rp, ci, n, nnz, kCand[bc], sp});
     *lanes = kCand[bc];
+    if (form != nullptr) *form = sp.form;
+    if (form_lanes != nullptr) *form_lanes = sp.L;
     return HZ_OK;
 }
 
@@ -1390,11 +1501,8 @@ int csr_zspmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, con
     int rc = spmv_common_checks(h, n, nnz, rp, ci, vals, x, y, sizeof(hz_c128));
     if (rc || n == 0) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int L = pick_lanes(h, rp, ci, n, nnz);
-    const Geom geo = geom_for(n, kBlock / L);
-    auto a = spmv_args<double>(n, geo, rp, ci, reinterpret_cast<const double2*>(vals),
-                               reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nullptr, nullptr);
-    launch_spmv<double, hz::EPI_NONE>(L, a, s);
+    standalone_spmv<double>(h, n, nnz, rp, ci, reinterpret_cast<const double2*>(vals),
+                            reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), s);
     HZ_HIP(hipGetLastError());
     return HZ_OK;
 }
@@ -1404,11 +1512,8 @@ int csr_cspmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, con
     int rc = spmv_common_checks(h, n, nnz, rp, ci, vals, x, y, sizeof(hz_c64));
     if (rc || n == 0) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int L = pick_lanes(h, rp, ci, n, nnz);
-    const Geom geo = geom_for(n, kBlock / L);
-    auto a = spmv_args<float>(n, geo, rp, ci, reinterpret_cast<const float2*>(vals), reinterpret_cast<const float2*>(x),
-                              reinterpret_cast<float2*>(y), nullptr, nullptr);
-    launch_spmv<float, hz::EPI_NONE>(L, a, s);
+    standalone_spmv<float>(h, n, nnz, rp, ci, reinterpret_cast<const float2*>(vals),
+                           reinterpret_cast<const float2*>(x), reinterpret_cast<float2*>(y), s);
     HZ_HIP(hipGetLastError());
     return HZ_OK;
 }
@@ -1675,14 +1780,20 @@ int csr_zspmv_rect(hz_handle* h, hz_stream stream, int m, int ncols, int nnz, co
     int rc = check_csr_args(m, nnz, rp, ci, vals);
     if (rc || m == 0) return rc;
     if (y == nullptr || (ncols > 0 && x == nullptr)) return HZ_ERR_INVALID;
+    if (ncols == 0 && nnz > 0) return HZ_ERR_INVALID;  // entries need columns
     if (misaligned(x, 16) || misaligned(y, 16) || misaligned(vals, 16)) return HZ_ERR_INVALID;
     if (ncols > 0 && overlap(x, 16 * size_t(ncols), y, 16 * size_t(m))) return HZ_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int L = pick_lanes(h, rp, ci, m, nnz);
-    const Geom geo = geom_for(m, kBlock / L);
-    auto a = spmv_args<double>(m, geo, rp, ci, reinterpret_cast<const double2*>(vals),
-                               reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nullptr, nullptr);
-    launch_spmv<double, hz::EPI_NONE>(L, a, s);
+    if (ncols > 0) {
+        standalone_spmv<double>(h, m, nnz, rp, ci, reinterpret_cast<const double2*>(vals),
+                                reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), s);
+    } else {  // no columns, so no entries: y = 0 by the vector rows
+        const int L = pick_lanes(h, rp, ci, m, nnz);
+        auto a = spmv_args<double>(m, geom_for(m, kBlock / L), rp, ci, reinterpret_cast<const double2*>(vals),
+                                   reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y), nullptr,
+                                   nullptr);
+        launch_spmv<double, hz::EPI_NONE>(L, a, s);
+    }
     HZ_HIP(hipGetLastError());
     return HZ_OK;
 }

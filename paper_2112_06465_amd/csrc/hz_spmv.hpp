@@ -1,0 +1,163 @@
+// Standalone row products y = A x (csr_zspmv, csr_cspmv, csr_zspmv_rect).
+//
+// The solver kernels fuse their row products with Krylov updates and block
+// reductions (1024-thread blocks, at most 512 of them, so that every block can
+// sum all partials).  A product on its own has no reduction, so it runs on
+// 256-thread blocks, up to 16 per CU, in one of two forms that the autotuner
+// picks per matrix:
+//
+// * pipelined vector rows (k_spmv_pipe): L lanes per row, U entries per lane
+//   in the first batch.  The loop is unrolled twice with two register sets:
+//   while the x gathers of the current tile are in flight, the (column,
+//   value) loads of the next tile and the row_ptr loads of the tile after it
+//   are already issued.  Every load is unconditional (indices clamped into
+//   range, the results masked afterwards), so the hardware wait counters can
+//   be waited on exactly, without a full drain at each step.
+// * block tiles (k_spmv_tile): a tile of kTileRows rows whose entries are
+//   loaded by the whole block contiguously (thread t takes entries e0 + t,
+//   e0 + t + 256, ...), multiplied by the gathered x and written to LDS; then
+//   kTileLanes threads per row sum the row's products out of LDS.  A tile
+//   with more than kTileCap entries is done as vector rows instead.
+//
+// Row ownership is that of the other kernels (XCD groups, tiles dealt out
+// within a group), with the form's own tile height.  Summation order is fixed
+// by the form and its lane count, so results are bitwise reproducible.
+#pragma once
+
+#include "hz_kernels.hpp"
+
+namespace hz {
+
+constexpr int kSpBlock = 256;                     // threads per block
+constexpr int kSpMaxGrid = 4096;                  // blocks: 16 per CU
+constexpr int kTileRows = 64;                     // rows per tile of the block form
+constexpr int kTileLanes = kSpBlock / kTileRows;  // threads per row in its reduction
+constexpr int kTilePer = 4;                       // entries per thread per tile
+constexpr int kTileCap = kSpBlock * kTilePer;     // entries per tile held in LDS
+
+template <typename T> struct SpArgs {
+    int n;    // rows
+    int nnz;  // >= 1
+    Geom geo;
+    const int* __restrict__ row_ptr;
+    const int* __restrict__ col_idx;
+    const cx<T>* __restrict__ vals;
+    const cx<T>* __restrict__ x;  // at least one element
+    cx<T>* __restrict__ y;
+};
+
+template <typename T, int L, int U>
+__global__ __launch_bounds__(kSpBlock) void k_spmv_pipe(const SpArgs<T> a) {
+    constexpr int RPS = kSpBlock / L;
+    const RowRange rr = rows_of_block(a.n, a.geo);
+    const int g = threadIdx.x / L, lane = threadIdx.x % L;
+    const int64_t first = rr.rw.x0 + (int64_t)rr.rw.k * RPS, step = (int64_t)rr.rw.K * RPS, r1 = rr.rw.x1;
+    const int* __restrict__ rp = a.row_ptr;
+    const int* __restrict__ ci = a.col_idx;
+    const cx<T>* __restrict__ vals = a.vals;
+    const cx<T>* __restrict__ x = a.x;
+    const unsigned nnz = (unsigned)a.nnz;
+    // entry range of row r (empty past the group's last row); loads stay in [0, n]
+    auto bounds = [&](int64_t r, int& b, int& e) {
+        const int64_t rc = r < r1 ? r : r1;
+        const int b0 = rp[rc], e0 = rp[rc + 1 <= r1 ? rc + 1 : r1];
+        b = r < r1 ? b0 : 0;
+        e = r < r1 ? e0 : 0;
+    };
+    // first batch of a row: entry beg + lane + u L for u < U; col -1 marks an empty slot
+    auto batch = [&](int b, int e, int (&c)[U], cx<T> (&v)[U]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const unsigned p = (unsigned)b + (unsigned)(lane + u * L);
+            const unsigned pc = p < nnz ? p : nnz - 1;
+            const int cv = ci[pc];
+            v[u] = vals[pc];
+            c[u] = p < (unsigned)e ? cv : -1;
+        }
+    };
+    // row `row` with entries [b, e) and first batch c/v; issues the next tile's batch
+    // (entries [nb, ne) into c2/v2) and the row bounds two tiles ahead (into nnb/nne)
+    auto one = [&](int64_t row, int b, int e, const int (&c)[U], const cx<T> (&v)[U], int nb, int ne, int (&c2)[U],
+                   cx<T> (&v2)[U], int& nnb, int& nne) {
+        cx<T> o[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) o[u] = x[c[u] >= 0 ? c[u] : 0];
+        batch(nb, ne, c2, v2);
+        bounds(row + 2 * step, nnb, nne);
+        cx<T> acc = mk<T>(T(0), T(0));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const cx<T> f = cfma<T>(v[u], o[u], acc);
+            const bool ok = c[u] >= 0;
+            acc.x = ok ? f.x : acc.x;
+            acc.y = ok ? f.y : acc.y;
+        }
+        if (e - b > L * U) {  // the rest of a long row, unpipelined
+            const cx<T> rest = row_partial<T, L, U>(b + L * U, e, lane, ci, vals, [x](int cc) { return x[cc]; });
+            acc.x += rest.x;
+            acc.y += rest.y;
+        }
+        acc.x = group_sum<L>(acc.x);
+        acc.y = group_sum<L>(acc.y);
+        if (row < r1 && lane == 0) a.y[row] = acc;
+    };
+    int64_t row = first + g;
+    int b0, e0, b1, e1;
+    bounds(row, b0, e0);
+    bounds(row + step, b1, e1);
+    int c0[U], c1[U];
+    cx<T> v0[U], v1[U];
+    batch(b0, e0, c0, v0);
+    for (int64_t base = first; base < r1; base += 2 * step) {
+        one(row, b0, e0, c0, v0, b1, e1, c1, v1, b0, e0);
+        if (base + step >= r1) break;
+        one(row + step, b1, e1, c1, v1, b0, e0, c0, v0, b1, e1);
+        row += 2 * step;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSpBlock) void k_spmv_tile(const SpArgs<T> a) {
+    constexpr int L = kTileLanes;
+    __shared__ cx<T> prod[kTileCap];
+    const RowRange rr = rows_of_block(a.n, a.geo);
+    const int t = threadIdx.x, g = t / L, lane = t % L;
+    const int64_t first = rr.rw.x0 + (int64_t)rr.rw.k * kTileRows, step = (int64_t)rr.rw.K * kTileRows;
+    const int64_t r1 = rr.rw.x1;
+    const int* __restrict__ rp = a.row_ptr;
+    const int* __restrict__ ci = a.col_idx;
+    const cx<T>* __restrict__ vals = a.vals;
+    const cx<T>* __restrict__ x = a.x;
+    for (int64_t r0 = first; r0 < r1; r0 += step) {  // uniform across the block
+        const int64_t re = r0 + kTileRows < r1 ? r0 + kTileRows : r1;
+        const int64_t e0 = rp[r0], e1 = rp[re];
+        const int64_t row = r0 + g;
+        int b = 0, e = 0;
+        if (row < re) {
+            b = rp[row];
+            e = rp[row + 1];
+        }
+        cx<T> acc = mk<T>(T(0), T(0));
+        if (e1 - e0 <= kTileCap) {
+#pragma unroll
+            for (int k = 0; k < kTilePer; ++k) {
+                const int64_t p = e0 + t + k * kSpBlock;
+                if (p < e1) prod[p - e0] = cmul<T>(vals[p], x[ci[p]]);
+            }
+            __syncthreads();
+            for (int64_t q = b - e0 + lane; q < e - e0; q += L) {
+                const cx<T> v = prod[q];
+                acc.x += v.x;
+                acc.y += v.y;
+            }
+            __syncthreads();
+        } else if (row < re) {
+            acc = row_partial<T, L, 1>(b, e, lane, ci, vals, [x](int cc) { return x[cc]; });
+        }
+        acc.x = group_sum<L>(acc.x);
+        acc.y = group_sum<L>(acc.y);
+        if (row < re && lane == 0) a.y[row] = acc;
+    }
+}
+
+}  // namespace hz

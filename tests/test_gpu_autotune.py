@@ -1,6 +1,7 @@
-"""The launch-shape autotuner: the tuned lane count is one of the product's
-own instantiations, so a product after tuning equals, bitwise, the product
-forced to that lane count; other index arrays keep the built-in rule."""
+"""The launch-shape autotuner: the tuned standalone form and lane count are
+one of the product's own instantiations, so a product after tuning equals,
+bitwise, the product forced to that form and lane count; other index arrays
+keep the built-in rule (vector rows, lane rule)."""
 
 import os
 
@@ -26,12 +27,15 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-def forced(hz, L, *args):
+def forced(hz, L, *args, form=None):
     os.environ["HZ_SPMV_LANES"] = str(L)
+    if form is not None:
+        os.environ["HZ_SPMV_FORM"] = form
     try:
         return hz.csr_zspmv(*args).cpu().numpy()
     finally:
         del os.environ["HZ_SPMV_LANES"]
+        os.environ.pop("HZ_SPMV_FORM", None)
 
 
 def test_tuned_lanes_are_used_bitwise_and_only_for_that_matrix(hz):
@@ -40,10 +44,12 @@ def test_tuned_lanes_are_used_bitwise_and_only_for_that_matrix(hz):
     x = dev(np.random.default_rng(3).standard_normal(A.n) + 1j * np.random.default_rng(4).standard_normal(A.n))
     os.environ.pop("HZ_SPMV_LANES", None)
     rule = hz.csr_zspmv(rp.clone(), ci.clone(), v, x).cpu().numpy()  # fresh index arrays: never tuned
-    L = hz.autotune_spmv(rp, ci, v, x)
-    assert L in (2, 4, 8, 16, 32, 64)
+    tune = hz.autotune_spmv(rp, ci, v, x, details=True)
+    assert tune["lanes"] in (2, 4, 8, 16, 32, 64) and tune["form_lanes"] in (2, 4, 8, 16, 32, 64)
+    assert tune["form"] in ("rows", "tiles")
     y = hz.csr_zspmv(rp, ci, v, x).cpu().numpy()
-    assert np.array_equal(y.view(np.float64), forced(hz, L, rp, ci, v, x).view(np.float64))
+    yf = forced(hz, tune["form_lanes"], rp, ci, v, x, form=tune["form"])
+    assert np.array_equal(y.view(np.float64), yf.view(np.float64))
     yo = O.zspmv(A, x.cpu().numpy())
     assert np.linalg.norm(y - yo) / np.linalg.norm(yo) <= 1e-14
     # copies of the index arrays are another matrix for the handle: the rule applies
@@ -67,5 +73,16 @@ def test_every_forced_lane_count_matches_the_oracle(hz):
     xh = np.random.default_rng(5).standard_normal(A.n) + 1j * np.random.default_rng(6).standard_normal(A.n)
     yo = O.zspmv(A, xh)
     for L in (2, 4, 8, 16, 32, 64):
-        y = forced(hz, L, rp, ci, v, dev(xh))
+        y = forced(hz, L, rp, ci, v, dev(xh), form="rows")
         assert np.linalg.norm(y - yo) / np.linalg.norm(yo) <= 1e-14, L
+    y = forced(hz, 4, rp, ci, v, dev(xh), form="tiles")
+    assert np.linalg.norm(y - yo) / np.linalg.norm(yo) <= 1e-14
+
+
+def test_autotune_of_an_empty_matrix_and_return_forms(hz):
+    rp = dev(np.zeros(4, np.int32))
+    ci = dev(np.zeros(0, np.int32))
+    v = dev(np.zeros(0, complex))
+    tune = hz.autotune_spmv(rp, ci, v, dev(np.ones(3, complex)), details=True)
+    assert tune["form"] == "rows"
+    assert np.array_equal(hz.csr_zspmv(rp, ci, v, dev(np.ones(3, complex))).cpu().numpy(), np.zeros(3))

@@ -47,10 +47,10 @@ def cn(rng, n):
     return rng.standard_normal(n) + 1j * rng.standard_normal(n)
 
 
-def ragged_matrix(n=3001, seed=0):
-    """Random row lengths 0..40, a few empty rows, one row of 600 entries."""
+def ragged_matrix(n=3001, seed=0, maxlen=40):
+    """Random row lengths 0..maxlen, a few empty rows, one row of 600 entries."""
     rng = np.random.default_rng(seed)
-    lens = rng.integers(0, 41, n)
+    lens = rng.integers(0, maxlen + 1, n)
     lens[[5, 17, n - 1]] = 0
     lens[100] = min(600, n)
     rows, cols = [], []
@@ -100,6 +100,45 @@ def test_spmv_every_lane_width_ragged(hz, lanes, monkeypatch):
     x = cn(np.random.default_rng(1), A.n)
     y = check_spmv(hz, A, x)
     assert np.all(y[[5, 17, A.n - 1]] == 0)
+
+
+@pytest.mark.parametrize("form", ["rows", "tiles"])
+@pytest.mark.parametrize("maxlen", [3, 16, 40])
+def test_spmv_both_forms_ragged(hz, form, maxlen, monkeypatch):
+    """Both standalone forms on ragged rows: tiles that fit the LDS buffer
+    (short rows), tiles that do not (long rows: the vector fallback), a
+    600-entry row, empty rows, a ragged last tile (n = 3001)."""
+    monkeypatch.setenv("HZ_SPMV_FORM", form)
+    A = ragged_matrix(seed=maxlen, maxlen=maxlen)
+    x = cn(np.random.default_rng(7), A.n)
+    y = check_spmv(hz, A, x)
+    assert np.all(y[[5, 17, A.n - 1]] == 0)
+    rp, ci, v = dev_csr(A)
+    y2 = hz.csr_zspmv(rp, ci, v, dev(x)).cpu().numpy()
+    assert np.array_equal(y.view(np.float64), y2.view(np.float64))
+
+
+@pytest.mark.parametrize("form", ["rows", "tiles"])
+def test_spmv_both_forms_complex64_and_rect(hz, form, monkeypatch):
+    monkeypatch.setenv("HZ_SPMV_FORM", form)
+    A = ragged_matrix(n=2000, seed=3, maxlen=20)
+    x = cn(np.random.default_rng(8), A.n).astype(np.complex64)
+    rp, ci, v = dev_csr(A, torch.complex64)
+    y = hz.csr_cspmv(rp, ci, v, dev(x)).cpu().numpy()
+    bound = 32 * EPS32 * abs_rowsum(A, x.astype(np.complex128))
+    assert np.all(np.abs(y.astype(complex) - O.cspmv(A, x).astype(complex)) <= bound)
+    # rectangular: the first 700 rows of A restricted to columns < 1500
+    keep = A.col_idx < 1500
+    rows = A.row_of_entry()
+    sel = keep & (rows < 700)
+    rpr = np.zeros(701, np.int32)
+    np.cumsum(np.bincount(rows[sel], minlength=700), out=rpr[1:])
+    R = CSR(rpr, A.col_idx[sel], A.vals[sel])
+    xr = cn(np.random.default_rng(9), 1500)
+    yr = hz.csr_zspmv_rect(dev(R.row_ptr), dev(R.col_idx), dev(R.vals), dev(xr)).cpu().numpy()
+    Rd = np.zeros((700, 1500), complex)
+    Rd[R.row_of_entry(), R.col_idx] = R.vals
+    assert np.allclose(yr, Rd @ xr, rtol=0, atol=1e-13 * np.abs(Rd).sum(1).max() * np.abs(xr).max())
 
 
 @pytest.mark.parametrize("lanes", [2, 8, 16, 64])
