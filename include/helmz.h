@@ -84,8 +84,15 @@ enum {
     HZ_BD_OMEGA = 4   /* omega itself                                     */
 };
 
-/* Handle with scratch for the standalone reductions and the solvers.
- * Allocates device memory once; returns HZ_ERR_HIP if that fails. */
+/* Handle with scratch for the standalone reductions and the solvers, the
+ * autotuned launch shapes, and a cache of up to 32 instantiated HIP graphs of
+ * solver iteration chunks with the stream they are captured on.  A chunk of
+ * iterations with the same kernels and arguments as a cached one (same
+ * matrix, vectors and workspace) is replayed with one hipGraphLaunch on the
+ * caller's stream; results are bitwise those of direct launches, which the
+ * environment variable HZ_NO_GRAPH=1 selects.  Allocates device memory and
+ * the capture stream once; returns HZ_ERR_HIP if that fails.  One handle per
+ * device, used by one host thread at a time. */
 int hz_handle_create(hz_handle **handle);
 int hz_handle_destroy(hz_handle *handle);
 

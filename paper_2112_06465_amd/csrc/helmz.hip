@@ -47,9 +47,18 @@ struct TuneEntry {
     SpPlan sp;
 };
 
+// An instantiated graph of one chunk of solver iterations, keyed by the
+// kernel family, lane count, chunk length and the kernels' argument bytes.
+struct GraphEntry {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec;
+};
+
 struct hz_handle {
     int device;
     std::vector<TuneEntry> tune;  // autotuned lanes per row, newest last
+    hipStream_t cap;                 // stream the iteration graphs are captured on (never runs work)
+    std::vector<GraphEntry> graphs;  // cached iteration graphs, newest last
     double* part;          // kParts * kMaxGrid partials for standalone reductions
     int* dflag;            // device word for CSR validation
     unsigned long long* dcount;  // device counter for the locality test
@@ -77,6 +86,62 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
     do {                                              \
         if ((call) != hipSuccess) return HZ_ERR_HIP;  \
     } while (0)
+
+// ------------------------------------------------------------------ iteration graphs
+
+constexpr size_t kMaxGraphs = 32;  // instantiated chunks kept per handle
+
+bool graphs_on() {
+    const char* e = std::getenv("HZ_NO_GRAPH");
+    return !(e != nullptr && e[0] == '1');
+}
+
+// Key of a chunk: family, lane count, chunk length, whether the concluding
+// kernel is appended, and the bytes of the kernels' argument struct (the
+// structs are value-initialised, so padding bytes are zero).
+template <typename A>
+std::vector<unsigned char> chunk_key(int family, int lanes, int k, int tail, const A& args) {
+    const int hdr[4] = {family, lanes, k, tail};
+    std::vector<unsigned char> key(sizeof(hdr) + sizeof(A));
+    std::memcpy(key.data(), hdr, sizeof(hdr));
+    std::memcpy(key.data() + sizeof(hdr), &args, sizeof(A));
+    return key;
+}
+
+// Enqueues a chunk of solver iterations on s: record(q) issues the chunk's
+// kernels on stream q.  The chunk is captured once into a graph on the
+// handle's capture stream, instantiated and cached under `key`; later chunks
+// with the same key replay it with one hipGraphLaunch.  With HZ_NO_GRAPH=1,
+// or if capture or instantiation fails, the kernels are launched directly.
+// Every caller synchronises s before the next chunk, so no cached graph is
+// in flight when one is evicted.
+template <typename F>
+int launch_chunk(hz_handle* h, hipStream_t s, const std::vector<unsigned char>& key, F&& record) {
+    if (graphs_on() && h->cap != nullptr) {
+        for (const GraphEntry& g : h->graphs)
+            if (g.key == key) return hipGraphLaunch(g.exec, s) == hipSuccess ? HZ_OK : HZ_ERR_HIP;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            record(h->cap);
+            hipError_t e = hipStreamEndCapture(h->cap, &graph);
+            if (e == hipSuccess && graph != nullptr) e = hipGraphInstantiateWithFlags(&exec, graph, 0);
+            if (graph != nullptr) (void)hipGraphDestroy(graph);
+            if (e == hipSuccess && exec != nullptr) {
+                if (h->graphs.size() >= kMaxGraphs) {
+                    (void)hipGraphExecDestroy(h->graphs.front().exec);
+                    h->graphs.erase(h->graphs.begin());
+                }
+                h->graphs.push_back(GraphEntry{key, exec});
+                return hipGraphLaunch(exec, s) == hipSuccess ? HZ_OK : HZ_ERR_HIP;
+            }
+            if (exec != nullptr) (void)hipGraphExecDestroy(exec);
+        }
+        (void)hipGetLastError();  // a failed capture leaves its error; launch directly instead
+    }
+    record(s);
+    return hipGetLastError() == hipSuccess ? HZ_OK : HZ_ERR_HIP;
+}
 
 // Lanes per row for the vector-CSR kernels: the smallest power of two not
 // below half the mean row length, in [2, 64], so each lane holds about two
@@ -363,7 +428,7 @@ template <typename T> size_t ws_bytes_single(int n, int64_t nnz, bool jacobi) {
 template <typename T>
 hz::BicgArgs<T> bicg_args(const WorkMap& m, const int* rp, const int* ci, const cx<T>* av, const cx<T>* b, cx<T>* x,
                           const SolveWs& w) {
-    hz::BicgArgs<T> a;
+    hz::BicgArgs<T> a{};
     a.G = m.G;
     a.stride = m.stride;
     a.bmap = w.bmap;
@@ -404,35 +469,34 @@ template <typename T>
 int iterate(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>& a, int L, int maxiter, bool fused) {
     const dim3 G(m.G), B(kBlock);
     int launched = 0, poll = 8;
-    int err = 0;
-    with_lanes(L, [&]<int LL, int UU>() {
-        while (launched < maxiter) {
-            const int k_n = (maxiter - launched) < poll ? (maxiter - launched) : poll;
-            for (int k = 0; k < k_n; ++k) {
-                if (fused) {
-                    hipLaunchKernelGGL((hz::k_bicg_A<T, LL, UU>), G, B, 0, s, a);
-                    hipLaunchKernelGGL((hz::k_bicg_B<T, LL, UU>), G, B, 0, s, a);
-                } else {
-                    hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, s, a);
-                    hipLaunchKernelGGL((hz::k_bicg_A1<T, LL, UU>), G, B, 0, s, a);
-                    hipLaunchKernelGGL((hz::k_bicg_S<T>), G, B, 0, s, a);
-                    hipLaunchKernelGGL((hz::k_bicg_B1<T, LL, UU>), G, B, 0, s, a);
+    while (launched < maxiter) {
+        const int k_n = (maxiter - launched) < poll ? (maxiter - launched) : poll;
+        const bool tail = launched + k_n == maxiter;
+        const int family = (fused ? 1 : 2) + (sizeof(T) == 4 ? 10 : 0);
+        int rc = launch_chunk(h, s, chunk_key(family, L, k_n, tail, a), [&](hipStream_t q) {
+            with_lanes(L, [&]<int LL, int UU>() {
+                for (int k = 0; k < k_n; ++k) {
+                    if (fused) {
+                        hipLaunchKernelGGL((hz::k_bicg_A<T, LL, UU>), G, B, 0, q, a);
+                        hipLaunchKernelGGL((hz::k_bicg_B<T, LL, UU>), G, B, 0, q, a);
+                    } else {
+                        hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, q, a);
+                        hipLaunchKernelGGL((hz::k_bicg_A1<T, LL, UU>), G, B, 0, q, a);
+                        hipLaunchKernelGGL((hz::k_bicg_S<T>), G, B, 0, q, a);
+                        hipLaunchKernelGGL((hz::k_bicg_B1<T, LL, UU>), G, B, 0, q, a);
+                    }
+                    hipLaunchKernelGGL((hz::k_bicg_C<T>), G, B, 0, q, a);
                 }
-                hipLaunchKernelGGL((hz::k_bicg_C<T>), G, B, 0, s, a);
-            }
-            launched += k_n;
-            if (launched == maxiter) hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, s, a);
-            if (hipGetLastError() != hipSuccess ||
-                hipMemcpyAsync(h->hflag, a.ndone, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess) {
-                err = 1;
-                return;
-            }
-            if (*h->hflag >= m.nsys) break;
-            if (poll < 64) poll *= 2;
-        }
-    });
-    if (err) return HZ_ERR_HIP;
+                if (tail) hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, q, a);
+            });
+        });
+        if (rc) return rc;
+        launched += k_n;
+        HZ_HIP(hipMemcpyAsync(h->hflag, a.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipStreamSynchronize(s));
+        if (*h->hflag >= m.nsys) break;
+        if (poll < 64) poll *= 2;
+    }
     HZ_HIP(hipGetLastError());
     return HZ_OK;
 }
@@ -850,30 +914,30 @@ size_t multi_layout(int B, int n, int64_t nnz, bool jacobi, bool kmb, char* base
 template <int VS>
 int iterate_multi(hz_handle* h, hipStream_t s, const hz::MultiArgs& a, int BL, int maxiter) {
     const dim3 G(a.geo.G), Bk(kBlock);
-    int launched = 0, poll = 8, err = 0;
-    with_multi(BL, [&]<int BB>() {
-        while (launched < maxiter) {
-            const int k_n = (maxiter - launched) < poll ? (maxiter - launched) : poll;
-            for (int k = 0; k < k_n; ++k) {
-                hipLaunchKernelGGL((hz::k_m_P<BB>), G, Bk, 0, s, a);
-                hipLaunchKernelGGL((hz::k_m_A1<BB, kMultiU, VS>), G, Bk, 0, s, a);
-                hipLaunchKernelGGL((hz::k_m_S<BB>), G, Bk, 0, s, a);
-                hipLaunchKernelGGL((hz::k_m_B1<BB, kMultiUt, VS>), G, Bk, 0, s, a);
-                hipLaunchKernelGGL((hz::k_m_C<BB>), G, Bk, 0, s, a);
-            }
-            launched += k_n;
-            if (launched == maxiter) hipLaunchKernelGGL((hz::k_m_P<BB>), G, Bk, 0, s, a);
-            if (hipGetLastError() != hipSuccess ||
-                hipMemcpyAsync(h->hflag, a.ndone, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess) {
-                err = 1;
-                return;
-            }
-            if (*h->hflag >= a.B) break;
-            if (poll < 64) poll *= 2;
-        }
-    });
-    return err ? HZ_ERR_HIP : HZ_OK;
+    int launched = 0, poll = 8;
+    while (launched < maxiter) {
+        const int k_n = (maxiter - launched) < poll ? (maxiter - launched) : poll;
+        const bool tail = launched + k_n == maxiter;
+        int rc = launch_chunk(h, s, chunk_key(100 + VS, BL, k_n, tail, a), [&](hipStream_t q) {
+            with_multi(BL, [&]<int BB>() {
+                for (int k = 0; k < k_n; ++k) {
+                    hipLaunchKernelGGL((hz::k_m_P<BB>), G, Bk, 0, q, a);
+                    hipLaunchKernelGGL((hz::k_m_A1<BB, kMultiU, VS>), G, Bk, 0, q, a);
+                    hipLaunchKernelGGL((hz::k_m_S<BB>), G, Bk, 0, q, a);
+                    hipLaunchKernelGGL((hz::k_m_B1<BB, kMultiUt, VS>), G, Bk, 0, q, a);
+                    hipLaunchKernelGGL((hz::k_m_C<BB>), G, Bk, 0, q, a);
+                }
+                if (tail) hipLaunchKernelGGL((hz::k_m_P<BB>), G, Bk, 0, q, a);
+            });
+        });
+        if (rc) return rc;
+        launched += k_n;
+        HZ_HIP(hipMemcpyAsync(h->hflag, a.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipStreamSynchronize(s));
+        if (*h->hflag >= a.B) break;
+        if (poll < 64) poll *= 2;
+    }
+    return HZ_OK;
 }
 
 // y = b - A xin for every system of the batch (the caller's values).
@@ -1207,21 +1271,25 @@ int solve_mixed(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, cons
 
 // Enqueue k iterations of the single-system BiCGStab (no poll).
 template <typename T>
-void launch_iterations(hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>& a, int L, int k, bool fused) {
+int launch_iterations(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>& a, int L, int k,
+                      bool fused) {
     const dim3 G(m.G), B(kBlock);
-    with_lanes(L, [&]<int LL, int UU>() {
-        for (int i = 0; i < k; ++i) {
-            if (fused) {
-                hipLaunchKernelGGL((hz::k_bicg_A<T, LL, UU>), G, B, 0, s, a);
-                hipLaunchKernelGGL((hz::k_bicg_B<T, LL, UU>), G, B, 0, s, a);
-            } else {
-                hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, s, a);
-                hipLaunchKernelGGL((hz::k_bicg_A1<T, LL, UU>), G, B, 0, s, a);
-                hipLaunchKernelGGL((hz::k_bicg_S<T>), G, B, 0, s, a);
-                hipLaunchKernelGGL((hz::k_bicg_B1<T, LL, UU>), G, B, 0, s, a);
+    const int family = (fused ? 3 : 4) + (sizeof(T) == 4 ? 10 : 0);
+    return launch_chunk(h, s, chunk_key(family, L, k, 0, a), [&](hipStream_t q) {
+        with_lanes(L, [&]<int LL, int UU>() {
+            for (int i = 0; i < k; ++i) {
+                if (fused) {
+                    hipLaunchKernelGGL((hz::k_bicg_A<T, LL, UU>), G, B, 0, q, a);
+                    hipLaunchKernelGGL((hz::k_bicg_B<T, LL, UU>), G, B, 0, q, a);
+                } else {
+                    hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, q, a);
+                    hipLaunchKernelGGL((hz::k_bicg_A1<T, LL, UU>), G, B, 0, q, a);
+                    hipLaunchKernelGGL((hz::k_bicg_S<T>), G, B, 0, q, a);
+                    hipLaunchKernelGGL((hz::k_bicg_B1<T, LL, UU>), G, B, 0, q, a);
+                }
+                hipLaunchKernelGGL((hz::k_bicg_C<T>), G, B, 0, q, a);
             }
-            hipLaunchKernelGGL((hz::k_bicg_C<T>), G, B, 0, s, a);
-        }
+        });
     });
 }
 
@@ -1299,9 +1367,9 @@ int solve_mixed_reliable(hz_handle* h, hipStream_t s, int n, int nnz, const int*
     double ref = ho->relres;
     while (!ho->done) {
         const int k = std::min(poll, std::max(1, maxiter - launched));
-        launch_iterations<float>(s, m, ai, L, k, fused);
+        rc = launch_iterations<float>(h, s, m, ai, L, k, fused);
+        if (rc) return rc;
         launched += k;
-        HZ_HIP(hipGetLastError());
         HZ_HIP(hipMemcpyAsync(hi, mw.in.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
         HZ_HIP(hipStreamSynchronize(s));
         if (hi->pending && !hi->done) {  // conclude a half-step exit
@@ -1392,7 +1460,8 @@ int hz_handle_create(hz_handle** out) {
             hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&h->hflag), sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&h->hsc), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&h->hsc2), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(reinterpret_cast<void**>(&h->hsc2), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess ||
+        hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
         hz_handle_destroy(h);
         return HZ_ERR_HIP;
     }
@@ -1409,6 +1478,8 @@ int hz_handle_destroy(hz_handle* h) {
     if (h->hflag) (void)hipHostFree(h->hflag);
     if (h->hsc) (void)hipHostFree(h->hsc);
     if (h->hsc2) (void)hipHostFree(h->hsc2);
+    for (const GraphEntry& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
     return HZ_OK;
 }
