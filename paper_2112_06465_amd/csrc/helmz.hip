@@ -313,14 +313,19 @@ int enqueue_far_count(hz_handle* h, hipStream_t s, int n, const int* rp, const i
     return HZ_OK;
 }
 
-// The gather-light iteration (p and s materialised, one gathered vector per
-// product) measured faster than or equal to the fused one (p and s formed
-// per gathered column, three gathered vectors) on every workload here: equal
-// on the naturally numbered cylinder, 1.6x faster on the renumbered cabin,
-// 2.4x on the randomly numbered one.  HZ_FUSED=1 selects the fused kernels.
-bool choose_fused(const hz_handle*, int64_t) {
+// Which iteration: the gather-light one (p and s materialised, one gathered
+// vector per product, five kernels) or the fused one (p and s formed per
+// gathered column, three gathered vectors, three kernels).  On large systems
+// the extra gathers cost more than the two launches they save: 1.05x on the
+// cylinder (n = 210k), 1.6x on the renumbered cabin, 2.4x on the randomly
+// numbered one, a tie at n = 262k.  Up to about 10^5 rows every gathered
+// vector sits in L2 and the iteration is launch-bound, so the fused one wins
+// (20^3 cube 24.1 -> 21.0 us, 48^3 cube 32.4 -> 30.6 us per iteration).
+// `rows` is the total over the systems of a launch.  HZ_FUSED=0/1 overrides.
+constexpr int64_t kFusedMaxRows = 131072;
+bool choose_fused(const hz_handle*, int64_t rows) {
     if (const char* env = std::getenv("HZ_FUSED")) return std::atoi(env) != 0;
-    return false;
+    return rows <= kFusedMaxRows;
 }
 
 int check_csr_args(int n, int nnz, const int* rp, const int* ci, const void* vals) {
@@ -557,7 +562,7 @@ int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nn
     if (hs->bad_diag) return HZ_ERR_INVALID;
 
     if (*h->hflag < nsys) {
-        rc = iterate<double>(h, s, m, a, L, maxiter, choose_fused(h, nnz));
+        rc = iterate<double>(h, s, m, a, L, maxiter, choose_fused(h, n));
         if (rc) return rc;
     }
     hipLaunchKernelGGL(hz::k_zero_if<double>, dim3(m.G), dim3(kBlock), 0, s, a);
@@ -1221,7 +1226,7 @@ int solve_mixed(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, cons
     HZ_HIP(hipMemcpyAsync(ho, mw.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
     HZ_HIP(hipStreamSynchronize(s));
     if (ho->bad_diag) return HZ_ERR_INVALID;
-    const bool fused = choose_fused(h, nnz);
+    const bool fused = choose_fused(h, n);
     const hz::BicgArgs<float> ai =
         bicg_args<float>(m, rp, ci, static_cast<const float2*>(mw.in.ahat), mw.b32, mw.d32, mw.in);
 
@@ -1339,7 +1344,7 @@ int solve_mixed_reliable(hz_handle* h, hipStream_t s, int n, int nnz, const int*
     HZ_HIP(hipMemcpyAsync(ho, mw.outer, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
     HZ_HIP(hipStreamSynchronize(s));
     if (ho->bad_diag) return HZ_ERR_INVALID;
-    const bool fused = choose_fused(h, nnz);
+    const bool fused = choose_fused(h, n);
     const hz::BicgArgs<float> ai =
         bicg_args<float>(m, rp, ci, static_cast<const float2*>(mw.in.ahat), mw.b32, mw.d32, mw.in);
     const float2* dinv32 = jacobi ? static_cast<const float2*>(mw.in.dinv) : nullptr;
