@@ -162,13 +162,22 @@ template <int K> __device__ __forceinline__ void block_sum(double (&v)[K]) {
 
 // Sum of K partial components (component k at part[k*kMaxGrid + g], g < G)
 // in a fixed order, delivered to every thread of the block.
+// (G <= kMaxGrid <= kBlock: one partial per thread, the K loads issued
+// together; idle waves load nothing, as in sys_sum.)
 template <int K> __device__ __forceinline__ void head_sum(const double* __restrict__ part, int G, double (&out)[K]) {
+    static_assert(kMaxGrid <= kBlock, "one partial per thread");
     __shared__ double bc[K];
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int g = threadIdx.x; g < G; g += kBlock) s += part[k * kMaxGrid + g];
-        out[k] = s;
+    for (int k = 0; k < K; ++k) out[k] = 0.0;
+    if ((__builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~(kWave - 1)) < G) {
+        const bool mine = t < G;
+        const int g0 = mine ? t : G - 1;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double v = part[k * kMaxGrid + g0];
+            out[k] = mine ? v : 0.0;
+        }
     }
     block_sum<K>(out);
     if (threadIdx.x == 0) {
@@ -431,15 +440,38 @@ __device__ __forceinline__ void finish(SolverScal* sc, int* ndone, int status, i
 
 // Sum of K components over one system's partials [gbeg, gbeg + gcnt), in a
 // fixed order, delivered to every thread of the block.
+// Thread t takes partial t of every component; the K loads are issued
+// together (so their latencies overlap).  Waves wholly past the partials
+// load nothing (a wave-uniform branch); in the wave that straddles the end,
+// the lanes past it read the last partial, a duplicate address that the
+// load instruction merges (clamping every idle thread of every block to one
+// address would make that address a hot spot).  A system's blocks never
+// exceed kMaxGrid <= kBlock (gcnt >= 1); the loop for gcnt > kBlock only
+// keeps the function general.
+__device__ __forceinline__ int wave_base() {
+    return __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~(kWave - 1);
+}
 template <int K>
 __device__ __forceinline__ void sys_sum(const double* __restrict__ part, int stride, int gbeg, int gcnt,
                                         double (&out)[K]) {
+    static_assert(kMaxGrid <= kBlock, "one partial per thread");
     __shared__ double bc[K];
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double s = 0.0;
-        for (int g = threadIdx.x; g < gcnt; g += kBlock) s += part[k * stride + gbeg + g];
-        out[k] = s;
+    for (int k = 0; k < K; ++k) out[k] = 0.0;
+    if (wave_base() < gcnt) {
+        const bool mine = t < gcnt;
+        const int g0 = gbeg + (mine ? t : gcnt - 1);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double v = part[k * stride + g0];
+            out[k] = mine ? v : 0.0;
+        }
+    }
+    if (gcnt > kBlock) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            for (int g = t + kBlock; g < gcnt; g += kBlock) out[k] += part[k * stride + gbeg + g];
     }
     block_sum<K>(out);
     if (threadIdx.x == 0) {
