@@ -121,7 +121,8 @@ enum { HZ_SPMV_FORM_ROWS = 0, HZ_SPMV_FORM_TILES = 1 };
  *    csr_zspmv_rect): vector rows with each L, or block tiles.
  * Each candidate is timed on the caller's matrix and vectors (two rounds of
  * 5 launches after 2 warm-up launches, HIP events on `stream`); the fastest
- * are recorded in the handle for this (row_ptr, col_idx, n, nnz), and later
+ * (the built-in rule's choice unless another is more than 3 % faster) are
+ * recorded in the handle for this (row_ptr, col_idx, n, nnz), and later
  * products and solves on the same handle with the same index arrays use
  * them (results change only by summation order).  Without tuning, both use
  * vector rows with the smallest power of two L not below half the mean row

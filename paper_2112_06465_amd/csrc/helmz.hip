@@ -1553,14 +1553,22 @@ int hz_autotune_spmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* 
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     if (rc) return rc;
+    // The rule's choice stands unless a candidate is more than 3 % faster, so
+    // that near-ties (timing noise) do not flip the choice from run to run.
+    constexpr float kMargin = 0.97f;
+    const int rule = rule_lanes(n, nnz);
     int bc = 0;
     for (int c = 1; c < 6; ++c)
         if (best_ms[c] < best_ms[bc]) bc = c;
-    SpPlan sp{SP_PIPE, rule_lanes(n, nnz)};
+    for (int c = 0; c < 6; ++c)
+        if (kCand[c] == rule && best_ms[bc] >= kMargin * best_ms[c]) bc = c;
+    SpPlan sp{SP_PIPE, rule};
     if (nnz > 0) {
         int bp = 0;
         for (int c = 1; c < kPlans; ++c)
             if (plan_ms[c] < plan_ms[bp]) bp = c;
+        for (int c = 0; c < kPlans; ++c)
+            if (plans[c].form == SP_PIPE && plans[c].L == rule && plan_ms[bp] >= kMargin * plan_ms[c]) bp = c;
         sp = plans[bp];
     }
     for (auto it = h->tune.begin(); it != h->tune.end();)

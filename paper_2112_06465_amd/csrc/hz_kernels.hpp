@@ -574,7 +574,11 @@ struct IterStart {
     int it;
     double2 rho, beta, omega;
 };
-template <typename T>
+// EARLY: the scalars written by earlier kernels are read before the
+// reduction's barriers (a barrier is a fence, so loads after it cannot be
+// hoisted above it), overlapping their latency with the partial loads; the
+// fused A-kernel reads them after, as it has no registers to spare.
+template <typename T, bool EARLY = true>
 __device__ __forceinline__ bool iteration_start(const BicgArgs<T>& a, const SysBlock& q, IterStart& st) {
     if (q.sys < 0) return false;
     SolverScal* sc = a.sc + q.sys;
@@ -584,22 +588,35 @@ __device__ __forceinline__ bool iteration_start(const BicgArgs<T>& a, const SysB
         return false;
     }
     const int it = sc->iter;
+    double bnorm, rtol;
+    int maxiter;
+    double2 om_prev, rho_prev, al_prev;
+    auto read = [&] {
+        bnorm = sc->bnorm;
+        rtol = sc->rtol;
+        maxiter = sc->maxiter;
+        om_prev = sc->omega;
+        rho_prev = sc->rho2[(it - 1) & 1];
+        al_prev = sc->alpha;
+    };
+    if constexpr (EARLY) read();
     double h[3];
     sys_sum<3>(a.part + kPartC * a.stride, a.stride, q.gbeg, q.gcnt, h);
+    if constexpr (!EARLY) read();
     const double2 rho = mk<double>(h[0], h[1]);
     double2 beta = mk<double>(0.0, 0.0), om = mk<double>(0.0, 0.0);
     if (it > 1) {
-        const double rel = __builtin_sqrt(h[2]) / sc->bnorm;
-        om = sc->omega;
+        const double rel = __builtin_sqrt(h[2]) / bnorm;
+        om = om_prev;
         int stt = -1, sit = 0, why = BD_NONE;
         if (!__builtin_isfinite(rel)) stt = ST_NONFINITE, sit = it - 1;
-        else if (rel <= sc->rtol) stt = ST_OK, sit = it - 1;
+        else if (rel <= rtol) stt = ST_OK, sit = it - 1;
         else if (zzero(om)) stt = ST_BREAKDOWN, sit = it - 1, why = BD_OMEGA;
-        else if (it - 1 >= sc->maxiter) stt = ST_NOT_CONVERGED, sit = sc->maxiter;
+        else if (it - 1 >= maxiter) stt = ST_NOT_CONVERGED, sit = maxiter;
         else if (!zfinite(rho)) stt = ST_NONFINITE, sit = it;
         else if (zzero(rho)) stt = ST_BREAKDOWN, sit = it, why = BD_RHO;
         else {
-            beta = zmul(zdiv(rho, sc->rho2[(it - 1) & 1]), zdiv(sc->alpha, om));
+            beta = zmul(zdiv(rho, rho_prev), zdiv(al_prev, om));
             if (!zfinite(beta)) stt = ST_NONFINITE, sit = it;
         }
         if (sys_leader(q)) sc->relres = rel;
@@ -632,7 +649,7 @@ template <typename T, int L, int U>
 __global__ HZ_STREAM_BOUNDS void k_bicg_A(const BicgArgs<T> a) {
     const SysBlock q = sys_block(a);
     IterStart st;
-    if (!iteration_start(a, q, st)) return;
+    if (!iteration_start<T, false>(a, q, st)) return;
     const int it = st.it;
     const bool first = it == 1;
     const cx<T> bt = narrow<T>(st.beta), omt = narrow<T>(st.omega);
@@ -664,6 +681,7 @@ __device__ __forceinline__ bool alpha_step(const BicgArgs<T>& a, const SysBlock&
     SolverScal* sc = a.sc + q.sys;
     if (sc->done) return false;
     it = sc->cur;
+    const double2 rho = sc->rho2[it & 1];  // written by the iteration's first kernel; read before the barriers
     double h[2];
     sys_sum<2>(a.part + kPartA * a.stride, a.stride, q.gbeg, q.gcnt, h);
     const double2 sigma = mk<double>(h[0], h[1]);
@@ -671,7 +689,7 @@ __device__ __forceinline__ bool alpha_step(const BicgArgs<T>& a, const SysBlock&
         if (sys_leader(q)) finish(sc, a.ndone, zzero(sigma) ? ST_BREAKDOWN : ST_NONFINITE, it, zzero(sigma) ? BD_RHAT_V : BD_NONE);
         return false;
     }
-    alpha = zdiv(sc->rho2[it & 1], sigma);
+    alpha = zdiv(rho, sigma);
     if (sys_leader(q)) sc->alpha = alpha;
     return true;
 }
@@ -709,17 +727,18 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_C(const BicgArgs<T> a) {
     SolverScal* sc = a.sc + q.sys;
     if (sc->done) return;
     const int it = sc->cur;
+    const double bnorm = sc->bnorm, rtol = sc->rtol;  // read before the reduction's barriers
+    const double2 alpha = sc->alpha;
     double h[4];
     sys_sum<4>(a.part + kPartB * a.stride, a.stride, q.gbeg, q.gcnt, h);
-    const double rel = __builtin_sqrt(h[0]) / sc->bnorm;
-    const double2 alpha = sc->alpha;
+    const double rel = __builtin_sqrt(h[0]) / bnorm;
     const cx<T> al = narrow<T>(alpha);
     const cx<T>* __restrict__ p = a.p[it & 1];
     if (!__builtin_isfinite(rel)) {
         if (sys_leader(q)) finish(sc, a.ndone, ST_NONFINITE, it);
         return;
     }
-    if (rel <= sc->rtol) {  // half-step exit: x += alpha p (concluded by the next first kernel)
+    if (rel <= rtol) {  // half-step exit: x += alpha p (concluded by the next first kernel)
         HZ_FOR_ELEMS(i, q.rw) a.x[i] = cfma<T>(al, p[i], a.x[i]);
         if (sys_leader(q)) {
             sc->relres = rel;
