@@ -1,8 +1,8 @@
 """The oracle's pins catch plausible mistakes planted in a scratch copy of the oracle (CPU only).
 
 Each mutant copies oracle/, workloads/ and the pin tests into a temporary
-directory, changes one line of the C oracle, and runs the pins there: they
-must fail.  The repository's own oracle is never modified.
+directory, changes one line of the oracle (the C solvers, or the BiCGstab(l)
+module), and runs the pins of that part there: they must fail.  The repository's own oracle is never modified.
 """
 
 import os
@@ -59,13 +59,45 @@ MUTANTS = {
         "x[i].re = x[i].re + rn * (double)d32[i].re;",
         "x[i].re = x[i].re + (double)d32[i].re;",
     ),
+    # BiCGstab(l) (oracle/bicgstabl.py), against its own pins
+    "bicgstabl_beta_inverted": (
+        "bicgstabl.py",
+        "beta = alpha * rho1 / rho0",
+        "beta = alpha * rho0 / rho1",
+        "tests/test_oracle_bicgstabl_pins.py",
+    ),
+    "bicgstabl_direction_sign": (
+        "bicgstabl.py",
+        "uhat[i] = rhat[i] - beta * uhat[i]",
+        "uhat[i] = rhat[i] + beta * uhat[i]",
+        "tests/test_oracle_bicgstabl_pins.py",
+    ),
+    "bicgstabl_x_update_shifted_basis": (
+        "bicgstabl.py",
+        "y = y + np.column_stack(rhat[:ell]) @ g",
+        "y = y + np.column_stack(rhat[1:]) @ g",
+        "tests/test_oracle_bicgstabl_pins.py",
+    ),
+    "bicgstabl_omega_from_first_coefficient": (
+        "bicgstabl.py",
+        "omega = complex(g[-1])",
+        "omega = complex(g[0])",
+        "tests/test_oracle_bicgstabl_pins.py",
+    ),
+    "bicgstabl_rho_not_negated": (
+        "bicgstabl.py",
+        "rho0 = -omega * rho0",
+        "rho0 = omega * rho0",
+        "tests/test_oracle_bicgstabl_pins.py",
+    ),
 }
 
 
 @pytest.mark.slow
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_pins_catch_planted_mistake(name, tmp_path):
-    fname, old, new = MUTANTS[name]
+    fname, old, new = MUTANTS[name][:3]
+    pins = MUTANTS[name][3] if len(MUTANTS[name]) > 3 else "tests/test_oracle_pins.py"
     work = tmp_path / "repo"
     work.mkdir()
     for d in ("oracle", "workloads", "tests"):
@@ -76,7 +108,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     src.write_text(text.replace(old, new))
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     r = subprocess.run(
-        [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "tests/test_oracle_pins.py"],
+        [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", pins],
         cwd=work,
         capture_output=True,
         text=True,
