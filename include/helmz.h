@@ -81,7 +81,8 @@ enum {
     HZ_BD_RHO = 1,    /* rho = <rhat, r>                                  */
     HZ_BD_RHAT_V = 2, /* <rhat, v>, the denominator of alpha              */
     HZ_BD_TT = 3,     /* <t, t>, the denominator of omega                 */
-    HZ_BD_OMEGA = 4   /* omega itself                                     */
+    HZ_BD_OMEGA = 4,  /* omega itself                                     */
+    HZ_BD_MR = 5      /* BiCGstab(l): the minimal-residual system is singular */
 };
 
 /* Handle with scratch for the standalone reductions and the solvers, the
@@ -181,6 +182,26 @@ size_t zbicgstab_workspace_bytes(int n, int nnz, int flags);
 int zbicgstab_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
                     const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol, int maxiter, int flags, void *ws,
                     size_t ws_bytes, hz_solve_info *info);
+
+/*
+ * BiCGstab(l), the paper's P-BiCGSTAB(l) (Section 6, iterative Krylov
+ * methods; l = 8 in its speed-up tables), in Sleijpen and Fokkema's form:
+ * each cycle makes l Bi-CG steps, then takes the coefficients that minimise
+ * ||r_0 - sum_j gamma_j r_j||_2 over its residual basis r_1 .. r_l (normal
+ * equations of the basis' Gram matrix, scaled to unit diagonal, solved by
+ * Cholesky on the device).  Arguments, flags, workspace and return codes as
+ * for zbicgstab_solve, with 1 <= ell <= 8 and maxcycles the limit on cycles
+ * (each cycle is l Bi-CG steps and 2 l products).  The relative recursive
+ * residual is tested at the end of every cycle.  info->iterations counts
+ * cycles; a breakdown is an exact zero rho (HZ_BD_RHO), <r~, A u_j>
+ * (HZ_BD_RHAT_V), omega = gamma_l (HZ_BD_OMEGA), or a minimal-residual system
+ * that is not positive definite in floating point (HZ_BD_MR).  HZ_RELIABLE
+ * is invalid here.
+ */
+size_t zbicgstabl_workspace_bytes(int n, int nnz, int ell, int flags);
+int zbicgstabl_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+                     const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, int ell, double rtol, int maxcycles,
+                     int flags, void *ws, size_t ws_bytes, hz_solve_info *info);
 
 /*
  * Workspace (bytes) for zbicgstab_solve_varbatch.  row_off is a HOST array of

@@ -17,7 +17,7 @@ from ._lib import HelmzError, HzC128, HzInfo, load
 OK, NOT_CONVERGED, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 PRECOND_NONE, PRECOND_JACOBI, X0_ZERO, VALIDATE, SYMMETRIC = 0x0, 0x1, 0x4, 0x8, 0x10
 REORDER, NO_REORDER, RELIABLE = 0x20, 0x40, 0x80
-BD_NONE, BD_RHO, BD_RHAT_V, BD_TT, BD_OMEGA = 0, 1, 2, 3, 4  # info["breakdown"]: the scalar that became 0
+BD_NONE, BD_RHO, BD_RHAT_V, BD_TT, BD_OMEGA, BD_MR = 0, 1, 2, 3, 4, 5  # info["breakdown"]: what became 0 / singular
 
 _handles: dict[int, int] = {}
 _hlock = threading.Lock()
@@ -217,6 +217,37 @@ def zbicgstab_solve(row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxiter=20000,
                                 vals.data_ptr(), b.data_ptr(), x.data_ptr(), float(rtol), int(maxiter), int(flags), wp,
                                 wbytes, C.byref(info))
     _check("zbicgstab_solve", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
+    return x, info.as_dict()
+
+
+def zbicgstabl_workspace_bytes(n: int, nnz: int, ell: int = 8, flags: int = 0) -> int:
+    return int(load().zbicgstabl_workspace_bytes(n, nnz, ell, flags))
+
+
+def zbicgstabl_solve(row_ptr, col_idx, vals, b, x=None, ell=8, rtol=1e-8, maxcycles=2500,
+                     flags=PRECOND_NONE | X0_ZERO, ws=None):
+    """Solve A x = b by BiCGstab(ell) on the GPU (zbicgstabl_solve).  Returns (x, info).
+
+    info["iterations"] counts cycles (each ell Bi-CG steps, 2 ell products).
+    """
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    _need(b, "b", torch.complex128, dev)
+    if b.numel() != n:
+        raise ValueError("b has the wrong length")
+    if x is None:
+        x = torch.zeros(n, dtype=torch.complex128, device=dev)
+        flags |= X0_ZERO
+    _need(x, "x", torch.complex128, dev)
+    need = zbicgstabl_workspace_bytes(n, nnz, ell, flags)
+    if ws is None:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    _need(ws, "ws", torch.uint8, dev)
+    wp, wbytes = _aligned_ptr(ws, need)
+    info = HzInfo()
+    rc = load().zbicgstabl_solve(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                                 vals.data_ptr(), b.data_ptr(), x.data_ptr(), int(ell), float(rtol), int(maxcycles),
+                                 int(flags), wp, wbytes, C.byref(info))
+    _check("zbicgstabl_solve", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
     return x, info.as_dict()
 
 

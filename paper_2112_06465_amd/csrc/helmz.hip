@@ -21,6 +21,7 @@
 #include "hz_multi.hpp"
 #include "hz_reliable.hpp"
 #include "hz_spmv.hpp"
+#include "hz_bicgstabl.hpp"
 
 using hz::cx;
 using hz::Geom;
@@ -814,15 +815,16 @@ size_t single_ws_bytes(int n, int64_t nnz, int flags) {
     return (flags & HZ_NO_REORDER) ? inner : reorder_layout(n, nnz, nullptr, nullptr) + inner;
 }
 
-// Single-system FP64 solve, renumbered by level sets when want_reorder says
-// so: P A P^T (P x) = P b is solved and x is scattered back.
-int solve_single(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci, const double2* A,
-                 const double2* b, double2* x, double rtol, int maxiter, int flags, char* ws, hz_solve_info* info) {
-    const int row_off[2] = {0, n};
+// Runs inner(rp, ci, A, b, x, ws) on the system renumbered by level sets
+// when want_reorder says so (P A P^T (P x) = P b, x scattered back), else on
+// the caller's arrays.
+template <typename Inner>
+int with_renumbering(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci, const double2* A,
+                     const double2* b, double2* x, int flags, char* ws, hz_solve_info* info, Inner&& inner) {
     bool re = false;
     int rc = want_reorder(h, s, n, nnz, rp, ci, flags, &re);
     if (rc) return rc;
-    if (!re) return solve_fp64(h, s, 1, row_off, nnz, rp, ci, A, b, x, rtol, maxiter, flags, ws, &info[0]);
+    if (!re) return inner(rp, ci, A, b, x, ws);
     ReorderWs r;
     const size_t off = reorder_layout(n, nnz, ws, &r);
     rc = level_order(h, s, n, rp, ci, r.lv, r.perm, r.inv, nullptr);
@@ -834,7 +836,7 @@ int solve_single(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, con
         hipLaunchKernelGGL(hz::k_gather_perm<double>, grid1(n), dim3(kBlock), 0, s, n, r.perm,
                            static_cast<const double2*>(x), r.x);
     HZ_HIP(hipGetLastError());
-    rc = solve_fp64(h, s, 1, row_off, nnz, r.rp, r.ci, r.vals, r.b, r.x, rtol, maxiter, flags, ws + off, info);
+    rc = inner(r.rp, r.ci, r.vals, r.b, r.x, ws + off);
     if (rc < 0) return rc;
     info->renumbered = 1;
     hipLaunchKernelGGL(hz::k_scatter_perm<double>, grid1(n), dim3(kBlock), 0, s, n, r.perm,
@@ -842,6 +844,220 @@ int solve_single(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, con
     HZ_HIP(hipGetLastError());
     HZ_HIP(hipStreamSynchronize(s));
     return rc;
+}
+
+// Single-system FP64 solve (renumbered when the matrix wants it).
+int solve_single(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci, const double2* A,
+                 const double2* b, double2* x, double rtol, int maxiter, int flags, char* ws, hz_solve_info* info) {
+    const int row_off[2] = {0, n};
+    return with_renumbering(h, s, n, nnz, rp, ci, A, b, x, flags, ws, info,
+                            [&](const int* rp2, const int* ci2, const double2* A2, const double2* b2, double2* x2,
+                                char* ws2) {
+                                return solve_fp64(h, s, 1, row_off, nnz, rp2, ci2, A2, b2, x2, rtol, maxiter, flags,
+                                                  ws2, info);
+                            });
+}
+
+// ------------------------------------------------------------------ BiCGstab(l)
+
+// Workspace: scalars, partials, the one-system map, the done counter, r~,
+// r_0 .. r_l, u_0 .. u_l, a residual vector, Jacobi D^{-1} and A D^{-1},
+// the Gram partials and the minimal-residual coefficients.
+struct LWs {
+    SolverScal* sc;
+    double* part;
+    BlockMap* bmap;
+    SysMap* smap;
+    int* ndone;
+    double2* rt;
+    double2* r[hz::kLMax + 1];
+    double2* u[hz::kLMax + 1];
+    double2* t;
+    double2* dinv;
+    double2* ahat;
+    double* gpart;
+    double2* gam;
+};
+
+size_t lws_layout(int n, int64_t nnz, int ell, bool jacobi, char* base, LWs* out) {
+    const size_t vb = align_up(sizeof(double2) * size_t(n > 0 ? n : 1));
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    LWs w{};
+    w.sc = static_cast<SolverScal*>(take(sizeof(SolverScal)));
+    w.part = static_cast<double*>(take(sizeof(double) * size_t(hz::kParts) * size_t(kMaxGrid)));
+    w.bmap = static_cast<BlockMap*>(take(sizeof(BlockMap) * size_t(kMaxGrid)));
+    w.smap = static_cast<SysMap*>(take(sizeof(SysMap)));
+    w.ndone = static_cast<int*>(take(sizeof(int)));
+    w.rt = static_cast<double2*>(take(vb));
+    for (int p = 0; p <= ell; ++p) w.r[p] = static_cast<double2*>(take(vb));
+    for (int p = 0; p <= ell; ++p) w.u[p] = static_cast<double2*>(take(vb));
+    w.t = static_cast<double2*>(take(vb));
+    w.dinv = jacobi ? static_cast<double2*>(take(vb)) : nullptr;
+    w.ahat = jacobi ? static_cast<double2*>(take(sizeof(double2) * size_t(nnz > 0 ? nnz : 1))) : nullptr;
+    w.gpart = static_cast<double*>(take(sizeof(double) * 2 * size_t(hz::kGramPairs) * size_t(hz::kGramMaxGrid)));
+    w.gam = static_cast<double2*>(take(sizeof(double2) * (hz::kLMax + 1)));
+    if (out) *out = w;
+    return off;
+}
+
+size_t lsolve_ws_bytes(int n, int64_t nnz, int ell, int flags) {
+    const size_t inner = lws_layout(n, nnz, ell, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr);
+    return (flags & HZ_NO_REORDER) ? inner : reorder_layout(n, nnz, nullptr, nullptr) + inner;
+}
+
+template <typename F> void with_ell(int ell, F&& f) {
+    switch (ell) {
+        case 1: f.template operator()<1>(); break;
+        case 2: f.template operator()<2>(); break;
+        case 3: f.template operator()<3>(); break;
+        case 4: f.template operator()<4>(); break;
+        case 5: f.template operator()<5>(); break;
+        case 6: f.template operator()<6>(); break;
+        case 7: f.template operator()<7>(); break;
+        default: f.template operator()<8>(); break;
+    }
+}
+
+// BiCGstab(l) of one system on (rp, ci, A); cycles in chunks of 1, 2, 4, 8
+// with a poll of the done counter between chunks, each chunk replayed from a
+// cached graph; one more first launch after maxcycles concludes the last.
+int solve_l(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci, const double2* A,
+            const double2* bd, double2* xd, int ell, double rtol, int maxcycles, int flags, char* ws,
+            hz_solve_info* info) {
+    const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
+    const int L = pick_lanes(h, rp, ci, n, nnz);
+    const int row_off[2] = {0, n};
+    const WorkMap m = build_map(1, row_off, L);
+    LWs w;
+    lws_layout(n, nnz, ell, jacobi, ws, &w);
+    HZ_HIP(hipMemcpyAsync(w.bmap, m.blocks.data(), sizeof(BlockMap) * m.blocks.size(), hipMemcpyHostToDevice, s));
+    HZ_HIP(hipMemcpyAsync(w.smap, m.systems.data(), sizeof(SysMap) * m.systems.size(), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(hz::k_sc_init, dim3(1), dim3(256), 0, s, w.sc, 1, rtol, maxcycles);
+    const double2* Aop = A;
+    if (jacobi) {
+        hipLaunchKernelGGL(hz::k_jacobi_diag<double>, grid1(n), dim3(kBlock), 0, s, n, rp, ci, A, w.dinv, w.sc);
+        if (nnz > 0)
+            hipLaunchKernelGGL(hz::k_colscale<double>, grid1(nnz), dim3(kBlock), 0, s, int64_t(nnz), ci, A,
+                               static_cast<const double2*>(w.dinv), w.ahat);
+        Aop = w.ahat;
+    }
+    // the BiCGStab set-up and finishing kernels on the same map, scalars and partials
+    hz::BicgArgs<double> ba{};
+    ba.G = m.G;
+    ba.stride = m.stride;
+    ba.bmap = w.bmap;
+    ba.smap = w.smap;
+    ba.ndone = w.ndone;
+    ba.row_ptr = rp;
+    ba.col_idx = ci;
+    ba.vals = Aop;
+    ba.b = bd;
+    ba.r = w.r[0];
+    ba.rh = w.rt;
+    ba.x = xd;
+    ba.part = w.part;
+    ba.sc = w.sc;
+    HZ_HIP(hipMemsetAsync(w.ndone, 0, sizeof(int), s));
+    HZ_HIP(hipMemsetAsync(w.u[0], 0, 16 * size_t(n), s));
+    const double2* rsrc = bd;
+    if (flags & HZ_X0_ZERO) {
+        HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
+    } else {
+        if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, w.dinv, xd, 1);
+        launch_sys_resid<double>(L, m, ba, Aop, xd, w.t, s);
+        rsrc = w.t;
+    }
+    hipLaunchKernelGGL(hz::k_init<double>, dim3(m.G), dim3(kBlock), 0, s, ba, rsrc);
+    hipLaunchKernelGGL(hz::k_fin_init<double>, dim3(1), dim3(kBlock), 0, s, ba);
+    HZ_HIP(hipGetLastError());
+    SolverScal* hs = h->hsc;
+    HZ_HIP(hipMemcpyAsync(hs, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipMemcpyAsync(h->hflag, w.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    if (hs->bad_diag) return HZ_ERR_INVALID;
+
+    hz::LArgs la{};
+    la.G = m.G;
+    la.stride = m.stride;
+    la.bmap = w.bmap;
+    la.smap = w.smap;
+    la.ndone = w.ndone;
+    la.row_ptr = rp;
+    la.col_idx = ci;
+    la.vals = Aop;
+    la.rt = w.rt;
+    for (int p = 0; p <= ell; ++p) {
+        la.r[p] = w.r[p];
+        la.u[p] = w.u[p];
+    }
+    la.x = xd;
+    la.part = w.part;
+    la.gpart = w.gpart;
+    la.gam = w.gam;
+    la.sc = w.sc;
+    la.n = n;
+    la.ell = ell;
+    la.gG = int(std::min<int64_t>(hz::kGramMaxGrid, (int64_t(n) + hz::kGramBlock - 1) / hz::kGramBlock));
+    const dim3 G(m.G), B(kBlock);
+    auto cycle = [&](hipStream_t q) {
+        with_lanes(L, [&]<int LL, int UU>() {
+            for (int j = 0; j < ell; ++j) {
+                hz::LArgs aj = la;
+                aj.j = j;
+                hipLaunchKernelGGL(hz::k_l_U, G, B, 0, q, aj);
+                hipLaunchKernelGGL((hz::k_l_AU<LL, UU>), G, B, 0, q, aj);
+                hipLaunchKernelGGL(hz::k_l_R, G, B, 0, q, aj);
+                hipLaunchKernelGGL((hz::k_l_AR<LL, UU>), G, B, 0, q, aj);
+            }
+        });
+        with_ell(ell, [&]<int EL>() {
+            hipLaunchKernelGGL((hz::k_l_gram<EL>), dim3(la.gG), dim3(hz::kGramBlock), 0, q, la);
+            hipLaunchKernelGGL((hz::k_l_mr<EL>), dim3(1), B, 0, q, la);
+        });
+        hipLaunchKernelGGL(hz::k_l_update, G, B, 0, q, la);
+    };
+    int launched = 0, poll = 1;
+    int rc = HZ_OK;
+    if (*h->hflag < 1) {
+        while (launched < maxcycles) {
+            const int k_n = (maxcycles - launched) < poll ? (maxcycles - launched) : poll;
+            const bool tail = launched + k_n == maxcycles;
+            hz::LArgs a0 = la;
+            a0.j = 0;
+            rc = launch_chunk(h, s, chunk_key(40 + ell, L, k_n, tail, la), [&](hipStream_t q) {
+                for (int k = 0; k < k_n; ++k) cycle(q);
+                if (tail) hipLaunchKernelGGL(hz::k_l_U, G, B, 0, q, a0);
+            });
+            if (rc) return rc;
+            launched += k_n;
+            HZ_HIP(hipMemcpyAsync(h->hflag, w.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+            HZ_HIP(hipStreamSynchronize(s));
+            if (*h->hflag >= 1) break;
+            if (poll < 8) poll *= 2;
+        }
+    }
+    hipLaunchKernelGGL(hz::k_zero_if<double>, G, B, 0, s, ba);
+    if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, w.dinv, xd, 0);
+    hz::BicgArgs<double> b0 = ba;  // true residual with the caller's matrix
+    b0.vals = A;
+    launch_sys_resid<double>(L, m, b0, A, xd, w.t, s);
+    hipLaunchKernelGGL(hz::k_fin_true<double>, dim3(1), B, 0, s, b0);
+    HZ_HIP(hipGetLastError());
+    SolverScal out;
+    HZ_HIP(hipMemcpyAsync(&out, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    info->status = out.status;
+    info->iterations = out.iters;
+    info->outer_steps = 0;
+    info->relres_recursive = out.relres;
+    info->relres_true = out.relres_true;
+    info->breakdown = out.why;
+    return out.status;
 }
 
 // ------------------------------------------------------------------ shared-pattern batches
@@ -1673,6 +1889,42 @@ int zbicgstab_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* r
     return solve_single(h, s, n, nnz, rp, ci, reinterpret_cast<const double2*>(vals),
                         reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxiter, flags,
                         static_cast<char*>(ws), info);
+}
+
+size_t zbicgstabl_workspace_bytes(int n, int nnz, int ell, int flags) {
+    if (n < 0 || nnz < 0 || ell < 1 || ell > hz::kLMax) return 0;
+    return lsolve_ws_bytes(n, nnz, ell, flags);
+}
+
+int zbicgstabl_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci,
+                     const hz_c128* vals, const hz_c128* b, hz_c128* x, int ell, double rtol, int maxcycles,
+                     int flags, void* ws, size_t ws_bytes, hz_solve_info* info) {
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (h == nullptr || info == nullptr) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (!(rtol >= 0.0) || maxcycles < 0 || ell < 1 || ell > hz::kLMax) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
+        return HZ_ERR_INVALID;
+    if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
+    if ((flags & HZ_REORDER) && (flags & HZ_NO_REORDER)) return HZ_ERR_INVALID;
+    if (flags & HZ_RELIABLE) return HZ_ERR_INVALID;  // a flag of the mixed solve only
+    const size_t need = lsolve_ws_bytes(n, nnz, ell, flags);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (flags & HZ_VALIDATE) {
+        rc = validate_csr(h, s, n, nnz, rp, ci);
+        if (rc) return rc;
+    }
+    return with_renumbering(h, s, n, nnz, rp, ci, reinterpret_cast<const double2*>(vals),
+                            reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), flags,
+                            static_cast<char*>(ws), info,
+                            [&](const int* rp2, const int* ci2, const double2* A2, const double2* b2, double2* x2,
+                                char* ws2) {
+                                return solve_l(h, s, n, nnz, rp2, ci2, A2, b2, x2, ell, rtol, maxcycles, flags, ws2,
+                                               info);
+                            });
 }
 
 static int check_row_off(int nsys, const int* row_off, int* n_total) {

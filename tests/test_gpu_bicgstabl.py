@@ -1,0 +1,139 @@
+"""GPU parity of BiCGstab(l) (zbicgstabl_solve) against the oracle and dense LU.
+
+The GPU takes the minimal-residual coefficients from the normal equations of
+the residual basis' Gram matrix (scaled to unit diagonal, Cholesky); the
+oracle from a least-squares solve.  Both are the same minimiser, so iterates
+agree to rounding amplified by the basis' conditioning: bitwise-close for
+l = 1, close for a few cycles for l > 1; converged solutions are compared by
+their true residuals (recomputed with the oracle's SpMV) and against LU.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from oracle.bicgstabl import bicgstab_l
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hz():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    import paper_2112_06465_amd as hz
+
+    return hz
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def solve(hz, A, b, **kw):
+    x, info = hz.zbicgstabl_solve(dev(A.row_ptr), dev(A.col_idx), dev(A.vals), dev(b), **kw)
+    return x.cpu().numpy(), info
+
+
+def true_relres(A, x, b):
+    return np.linalg.norm(b - O.zspmv(A, x)) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("ell", [1, 2, 4, 8])
+def test_small_cube_matches_dense_lu(hz, ell):
+    A, b, _ = W.config_cube(10, seed=1)
+    x, info = solve(hz, A, b, ell=ell, rtol=1e-10)
+    assert info["status"] == hz.OK, info
+    assert true_relres(A, x, b) <= 1e-10 * (1 + 1e-3)
+    xd = np.linalg.solve(O.to_dense(A), b)
+    assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)
+    xo, io = bicgstab_l(A, b, ell=ell, tol=1e-10)
+    print(f"cube10 l={ell}: cycles gpu {info['iterations']} oracle {io['iterations']}")
+    assert abs(info["iterations"] - io["iterations"]) <= max(2, io["iterations"] // 5)
+
+
+@pytest.mark.parametrize("ell,cycles,bound", [(1, 6, 1e-10), (4, 2, 1e-7), (8, 1, 1e-7)])
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_iterates_follow_the_oracle(hz, ell, cycles, bound, jacobi):
+    A, b, _ = W.config_cylinder(h=0.1)
+    flags = (hz.PRECOND_JACOBI if jacobi else hz.PRECOND_NONE) | hz.X0_ZERO | hz.NO_REORDER
+    x, info = solve(hz, A, b, ell=ell, rtol=1e-30, maxcycles=cycles, flags=flags)
+    xo, io = bicgstab_l(A, b, ell=ell, tol=1e-30, maxcycles=cycles, jacobi=jacobi)
+    assert info["status"] == hz.NOT_CONVERGED and info["iterations"] == cycles == io["iterations"]
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(f"l={ell} jacobi={jacobi} after {cycles} cycles: rel diff {err:.2e}")
+    assert err <= bound
+    assert abs(info["relres_recursive"] - io["relres_recursive"]) <= 1e-6 * io["relres_recursive"] + 1e-14
+
+
+def test_jacobi_cylinder_converges_like_the_oracle(hz):
+    A, b, _ = W.config_cylinder(h=0.08)
+    flags = hz.PRECOND_JACOBI | hz.X0_ZERO
+    x, info = solve(hz, A, b, ell=8, rtol=1e-10, flags=flags)
+    xo, io = bicgstab_l(A, b, ell=8, tol=1e-10, jacobi=True)
+    assert info["status"] == hz.OK and io["status"] == O.OK
+    assert true_relres(A, x, b) <= 1e-10 * (1 + 1e-2)
+    assert np.linalg.norm(x - xo) <= 1e-6 * np.linalg.norm(xo)
+    print(f"cylinder h=0.08 l=8: cycles gpu {info['iterations']} oracle {io['iterations']}")
+
+
+def test_full_size_cylinder(hz):
+    A, b, _ = W.config_cylinder()
+    assert A.n == 209777
+    x, info = solve(hz, A, b, ell=8, rtol=1e-8, flags=hz.PRECOND_JACOBI | hz.X0_ZERO)
+    assert info["status"] == hz.OK, info
+    rr = true_relres(A, x, b)
+    assert rr <= 1e-8 * (1 + 1e-2)
+    print(f"full cylinder l=8: cycles {info['iterations']} true relres {rr:.3e}")
+
+
+def test_renumbered_scrambled_mesh(hz):
+    A, b, _ = W.config_cube(14, seed=4)
+    rng = np.random.default_rng(9)
+    from workloads.csr import permute_symmetric
+
+    perm = rng.permutation(A.n)
+    P = permute_symmetric(A, perm)
+    bp = np.empty_like(b)
+    bp[perm] = b  # row perm[i] of P is row i of A
+    x, info = solve(hz, P, bp, ell=4, rtol=1e-10, flags=hz.REORDER | hz.X0_ZERO)
+    assert info["status"] == hz.OK and info["renumbered"] == 1
+    assert true_relres(P, x, bp) <= 1e-10 * (1 + 1e-2)
+
+
+def test_special_cases_and_invalid_arguments(hz):
+    A, b, _ = W.config_cube(6, seed=2)
+    x, info = solve(hz, A, np.zeros(A.n, complex), ell=8)
+    assert info["status"] == hz.OK and info["iterations"] == 0 and not np.any(x)
+    xd = np.linalg.solve(O.to_dense(A), b)
+    rp, ci, v = dev(A.row_ptr), dev(A.col_idx), dev(A.vals)
+    xg, info = hz.zbicgstabl_solve(rp, ci, v, dev(b), x=dev(xd), ell=4, rtol=1e-8, flags=hz.PRECOND_NONE)
+    assert info["status"] == hz.OK and info["iterations"] == 0
+    xh, info = hz.zbicgstabl_solve(rp, ci, v, dev(b), x=dev(0.5 * xd), ell=4, rtol=1e-11, flags=hz.PRECOND_NONE)
+    assert info["status"] == hz.OK and true_relres(A, xh.cpu().numpy(), b) <= 1e-11 * (1 + 1e-2)
+    _, info = solve(hz, A, b, ell=4, maxcycles=0)
+    assert info["status"] == hz.NOT_CONVERGED and info["iterations"] == 0
+    for bad in (dict(ell=0), dict(ell=9), dict(ell=4, flags=hz.RELIABLE), dict(ell=4, rtol=-1.0)):
+        with pytest.raises(hz.HelmzError):
+            solve(hz, A, b, **bad)
+
+
+def test_deterministic_and_graph_replays_equal_direct_launches(hz):
+    A, b, _ = W.config_cylinder(h=0.1)
+    rp, ci, v, bd = dev(A.row_ptr), dev(A.col_idx), dev(A.vals), dev(b)
+    flags = hz.PRECOND_JACOBI | hz.X0_ZERO
+    ws = torch.empty(hz.zbicgstabl_workspace_bytes(A.n, A.nnz, 8, flags) + 256, dtype=torch.uint8, device="cuda:0")
+    os.environ["HZ_NO_GRAPH"] = "1"
+    try:
+        xe, ie = hz.zbicgstabl_solve(rp, ci, v, bd, ell=8, rtol=1e-10, flags=flags, ws=ws)
+        xe = xe.cpu().numpy()
+    finally:
+        del os.environ["HZ_NO_GRAPH"]
+    for _ in range(3):
+        xg, ig = hz.zbicgstabl_solve(rp, ci, v, bd, ell=8, rtol=1e-10, flags=flags, ws=ws)
+        assert ig == ie
+        assert np.array_equal(xg.cpu().numpy().view(np.float64), xe.view(np.float64))
+        torch.cuda.synchronize()
