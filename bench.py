@@ -119,6 +119,7 @@ def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10, caller_orde
     flags = hz.PRECOND_JACOBI | hz.X0_ZERO
     ws = hz.workspace(n, nnz, flags, dev)
     wsm = hz.mixed_workspace(n, nnz, flags, dev)
+    wsl = torch.empty(hz.zbicgstabl_workspace_bytes(n, nnz, 8, flags) + 256, dtype=torch.uint8, device=dev)
     x = torch.zeros_like(b)
     res = {"workload": f"{name} (n={n}, nnz={nnz})", "tol": tol}
     runs = [
@@ -127,6 +128,9 @@ def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10, caller_orde
                                                    flags=flags, ws=wsm)),
         ("mixed_reliable", lambda: hz.zbicgstab_solve_mixed(rp, ci, vals, b, x=x, rtol=tol, maxiter=50000,
                                                             flags=flags | hz.RELIABLE, ws=wsm)),
+        # BiCGstab(8), the paper's second solver: iterations are cycles of 8 Bi-CG steps (16 products)
+        ("bicgstab_l8", lambda: hz.zbicgstabl_solve(rp, ci, vals, b, x=x, ell=8, rtol=tol, maxcycles=5000,
+                                                    flags=flags, ws=wsl)),
     ]
     if caller_order_too:
         # the same FP64 solve kept in the caller's numbering (no level-set renumbering)
@@ -150,6 +154,7 @@ def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10, caller_orde
             res[label]["rel_err_vs_fp64"] = float(np.linalg.norm(xh - x64) / np.linalg.norm(x64))
     res["mixed_speedup"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)
     res["mixed_reliable_speedup"] = round(res["fp64"]["ms"] / res["mixed_reliable"]["ms"], 3)
+    res["bicgstab_l8_speedup"] = round(res["fp64"]["ms"] / res["bicgstab_l8"]["ms"], 3)
     return res
 
 
