@@ -1,8 +1,8 @@
 """The oracle's pins catch plausible mistakes planted in a scratch copy of the oracle (CPU only).
 
 Each mutant copies oracle/, workloads/ and the pin tests into a temporary
-directory, changes one line of the oracle (the C solvers, or the BiCGstab(l)
-module), and runs the pins of that part there: they must fail.  The repository's own oracle is never modified.
+directory, changes one line of the oracle (the C solvers, the BiCGstab(l) or
+the TFQMR module), and runs the pins of that part there: they must fail.  The repository's own oracle is never modified.
 """
 
 import os
@@ -90,6 +90,22 @@ MUTANTS = {
         "rho0 = omega * rho0",
         "tests/test_oracle_bicgstabl_pins.py",
     ),
+    # TFQMR (oracle/tfqmr.py), against its own pins
+    "tfqmr_beta_inverted": ("tfqmr.py", "beta = rho_new / rho", "beta = rho / rho_new", "tests/test_oracle_tfqmr_pins.py"),
+    "tfqmr_d_drops_eta": (
+        "tfqmr.py",
+        "d = u + (theta * theta / alpha) * eta * d",
+        "d = u + (theta * theta / alpha) * d",
+        "tests/test_oracle_tfqmr_pins.py",
+    ),
+    "tfqmr_tau_without_c": ("tfqmr.py", "tau = tau * theta * c", "tau = tau * theta", "tests/test_oracle_tfqmr_pins.py"),
+    "tfqmr_v_update_sign": (
+        "tfqmr.py",
+        "v = Au + beta * (Au_odd + beta * v_prev)",
+        "v = Au + beta * (Au_odd - beta * v_prev)",
+        "tests/test_oracle_tfqmr_pins.py",
+    ),
+    "tfqmr_eta_without_c_squared": ("tfqmr.py", "eta = c * c * alpha", "eta = c * alpha", "tests/test_oracle_tfqmr_pins.py"),
 }
 
 
