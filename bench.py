@@ -120,6 +120,7 @@ def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10, caller_orde
     ws = hz.workspace(n, nnz, flags, dev)
     wsm = hz.mixed_workspace(n, nnz, flags, dev)
     wsl = torch.empty(hz.zbicgstabl_workspace_bytes(n, nnz, 8, flags) + 256, dtype=torch.uint8, device=dev)
+    wsq = torch.empty(hz.ztfqmr_workspace_bytes(n, nnz, flags) + 256, dtype=torch.uint8, device=dev)
     x = torch.zeros_like(b)
     res = {"workload": f"{name} (n={n}, nnz={nnz})", "tol": tol}
     runs = [
@@ -131,6 +132,8 @@ def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10, caller_orde
         # BiCGstab(8), the paper's second solver: iterations are cycles of 8 Bi-CG steps (16 products)
         ("bicgstab_l8", lambda: hz.zbicgstabl_solve(rp, ci, vals, b, x=x, ell=8, rtol=tol, maxcycles=5000,
                                                     flags=flags, ws=wsl)),
+        # TFQMR, the paper's third solver: two products per iteration, stopped on the quasi-residual bound
+        ("tfqmr", lambda: hz.ztfqmr_solve(rp, ci, vals, b, x=x, rtol=tol, maxiter=50000, flags=flags, ws=wsq)),
     ]
     if caller_order_too:
         # the same FP64 solve kept in the caller's numbering (no level-set renumbering)
@@ -155,6 +158,7 @@ def time_to_tol(hz, torch, dev, name, rp, ci, vals, b, A, tol=1e-10, caller_orde
     res["mixed_speedup"] = round(res["fp64"]["ms"] / res["mixed"]["ms"], 3)
     res["mixed_reliable_speedup"] = round(res["fp64"]["ms"] / res["mixed_reliable"]["ms"], 3)
     res["bicgstab_l8_speedup"] = round(res["fp64"]["ms"] / res["bicgstab_l8"]["ms"], 3)
+    res["tfqmr_speedup"] = round(res["fp64"]["ms"] / res["tfqmr"]["ms"], 3)
     return res
 
 

@@ -204,6 +204,23 @@ int zbicgstabl_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const 
                      int flags, void *ws, size_t ws_bytes, hz_solve_info *info);
 
 /*
+ * TFQMR, the paper's P-TFQMR (Section 6, iterative Krylov methods): Freund's
+ * transpose-free QMR in the form of Saad's book, two products per iteration,
+ * right Jacobi preconditioning as for zbicgstab_solve.  The stopping test is
+ * the quasi-residual bound sqrt(m + 2) tau_{m+1} <= rtol ||b|| after every
+ * half step m, which bounds the true relative residual (reported in
+ * info->relres_true); info->relres_recursive is the bound, info->iterations
+ * counts full iterations (an exit after the first half step counts the
+ * iteration).  Arguments, flags, workspace and return codes as for
+ * zbicgstab_solve; a breakdown is an exact zero <r~, v> (HZ_BD_RHAT_V) or rho
+ * (HZ_BD_RHO).  HZ_RELIABLE is invalid here.
+ */
+size_t ztfqmr_workspace_bytes(int n, int nnz, int flags);
+int ztfqmr_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+                 const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol, int maxiter, int flags, void *ws,
+                 size_t ws_bytes, hz_solve_info *info);
+
+/*
  * Workspace (bytes) for zbicgstab_solve_varbatch.  row_off is a HOST array of
  * nsys+1 row offsets (row_off[0] = 0, non-decreasing).
  */

@@ -60,6 +60,8 @@ SIGNATURES = {
     "zbicgstab_solve": (I, [P, P, I, I, P, P, P, P, P, D, I, I, P, SZ, C.POINTER(HzInfo)]),
     "zbicgstabl_workspace_bytes": (SZ, [I, I, I, I]),
     "zbicgstabl_solve": (I, [P, P, I, I, P, P, P, P, P, I, D, I, I, P, SZ, C.POINTER(HzInfo)]),
+    "ztfqmr_workspace_bytes": (SZ, [I, I, I]),
+    "ztfqmr_solve": (I, [P, P, I, I, P, P, P, P, P, D, I, I, P, SZ, C.POINTER(HzInfo)]),
     "zbicgstab_mixed_workspace_bytes": (SZ, [I, I, I]),
     "zbicgstab_varbatch_workspace_bytes": (SZ, [I, P, I, I]),
     "zbicgstab_solve_varbatch": (I, [P, P, I, P, I, P, P, P, P, P, D, I, I, P, SZ, P]),

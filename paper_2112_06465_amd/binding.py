@@ -251,6 +251,38 @@ def zbicgstabl_solve(row_ptr, col_idx, vals, b, x=None, ell=8, rtol=1e-8, maxcyc
     return x, info.as_dict()
 
 
+def ztfqmr_workspace_bytes(n: int, nnz: int, flags: int = 0) -> int:
+    return int(load().ztfqmr_workspace_bytes(n, nnz, flags))
+
+
+def ztfqmr_solve(row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxiter=20000, flags=PRECOND_NONE | X0_ZERO,
+                 ws=None):
+    """Solve A x = b by TFQMR on the GPU (ztfqmr_solve).  Returns (x, info).
+
+    The stopping test is the quasi-residual bound (info["relres_recursive"]);
+    info["iterations"] counts full iterations (two products each).
+    """
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    _need(b, "b", torch.complex128, dev)
+    if b.numel() != n:
+        raise ValueError("b has the wrong length")
+    if x is None:
+        x = torch.zeros(n, dtype=torch.complex128, device=dev)
+        flags |= X0_ZERO
+    _need(x, "x", torch.complex128, dev)
+    need = ztfqmr_workspace_bytes(n, nnz, flags)
+    if ws is None:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    _need(ws, "ws", torch.uint8, dev)
+    wp, wbytes = _aligned_ptr(ws, need)
+    info = HzInfo()
+    rc = load().ztfqmr_solve(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                             vals.data_ptr(), b.data_ptr(), x.data_ptr(), float(rtol), int(maxiter), int(flags), wp,
+                             wbytes, C.byref(info))
+    _check("ztfqmr_solve", rc, ok=(OK, NOT_CONVERGED, BREAKDOWN, NONFINITE))
+    return x, info.as_dict()
+
+
 def zbicgstab_mixed_workspace_bytes(n: int, nnz: int, flags: int = 0) -> int:
     return int(load().zbicgstab_mixed_workspace_bytes(int(n), int(nnz), int(flags)))
 

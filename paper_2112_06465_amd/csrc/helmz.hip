@@ -22,6 +22,7 @@
 #include "hz_reliable.hpp"
 #include "hz_spmv.hpp"
 #include "hz_bicgstabl.hpp"
+#include "hz_tfqmr.hpp"
 
 using hz::cx;
 using hz::Geom;
@@ -1060,6 +1061,173 @@ int solve_l(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const in
     return out.status;
 }
 
+// ------------------------------------------------------------------ TFQMR
+
+// Workspace: scalars, partials, the one-system map, the done counter, the
+// TFQMR scalars, r_0, r~, w, u, u', A u, A u', v, d, a residual vector,
+// Jacobi D^{-1} and A D^{-1}.
+struct QWs {
+    SolverScal* sc;
+    double* part;
+    BlockMap* bmap;
+    SysMap* smap;
+    int* ndone;
+    hz::TScal* tq;
+    double2 *r0, *rt, *w, *u, *u1, *au, *au1, *v, *d, *t;
+    double2* dinv;
+    double2* ahat;
+};
+
+size_t qws_layout(int n, int64_t nnz, bool jacobi, char* base, QWs* out) {
+    const size_t vb = align_up(sizeof(double2) * size_t(n > 0 ? n : 1));
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    QWs w{};
+    w.sc = static_cast<SolverScal*>(take(sizeof(SolverScal)));
+    w.part = static_cast<double*>(take(sizeof(double) * size_t(hz::kParts) * size_t(kMaxGrid)));
+    w.bmap = static_cast<BlockMap*>(take(sizeof(BlockMap) * size_t(kMaxGrid)));
+    w.smap = static_cast<SysMap*>(take(sizeof(SysMap)));
+    w.ndone = static_cast<int*>(take(sizeof(int)));
+    w.tq = static_cast<hz::TScal*>(take(sizeof(hz::TScal)));
+    for (double2** v : {&w.r0, &w.rt, &w.w, &w.u, &w.u1, &w.au, &w.au1, &w.v, &w.d, &w.t})
+        *v = static_cast<double2*>(take(vb));
+    w.dinv = jacobi ? static_cast<double2*>(take(vb)) : nullptr;
+    w.ahat = jacobi ? static_cast<double2*>(take(sizeof(double2) * size_t(nnz > 0 ? nnz : 1))) : nullptr;
+    if (out) *out = w;
+    return off;
+}
+
+size_t qsolve_ws_bytes(int n, int64_t nnz, int flags) {
+    const size_t inner = qws_layout(n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, nullptr, nullptr);
+    return (flags & HZ_NO_REORDER) ? inner : reorder_layout(n, nnz, nullptr, nullptr) + inner;
+}
+
+// TFQMR of one system on (rp, ci, A); iterations in chunks of 8, 16, ..., 64
+// (three launches each) with a poll of the done counter between chunks,
+// each chunk replayed from a cached graph.
+int solve_q(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci, const double2* A,
+            const double2* bd, double2* xd, double rtol, int maxiter, int flags, char* ws, hz_solve_info* info) {
+    const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
+    const int L = pick_lanes(h, rp, ci, n, nnz);
+    const int row_off[2] = {0, n};
+    const WorkMap m = build_map(1, row_off, L);
+    QWs w;
+    qws_layout(n, nnz, jacobi, ws, &w);
+    HZ_HIP(hipMemcpyAsync(w.bmap, m.blocks.data(), sizeof(BlockMap) * m.blocks.size(), hipMemcpyHostToDevice, s));
+    HZ_HIP(hipMemcpyAsync(w.smap, m.systems.data(), sizeof(SysMap) * m.systems.size(), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(hz::k_sc_init, dim3(1), dim3(256), 0, s, w.sc, 1, rtol, maxiter);
+    const double2* Aop = A;
+    if (jacobi) {
+        hipLaunchKernelGGL(hz::k_jacobi_diag<double>, grid1(n), dim3(kBlock), 0, s, n, rp, ci, A, w.dinv, w.sc);
+        if (nnz > 0)
+            hipLaunchKernelGGL(hz::k_colscale<double>, grid1(nnz), dim3(kBlock), 0, s, int64_t(nnz), ci, A,
+                               static_cast<const double2*>(w.dinv), w.ahat);
+        Aop = w.ahat;
+    }
+    hz::BicgArgs<double> ba{};  // the BiCGStab set-up and finishing kernels on the same map and scalars
+    ba.G = m.G;
+    ba.stride = m.stride;
+    ba.bmap = w.bmap;
+    ba.smap = w.smap;
+    ba.ndone = w.ndone;
+    ba.row_ptr = rp;
+    ba.col_idx = ci;
+    ba.vals = Aop;
+    ba.b = bd;
+    ba.r = w.r0;
+    ba.rh = w.rt;
+    ba.x = xd;
+    ba.part = w.part;
+    ba.sc = w.sc;
+    HZ_HIP(hipMemsetAsync(w.ndone, 0, sizeof(int), s));
+    const double2* rsrc = bd;
+    if (flags & HZ_X0_ZERO) {
+        HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
+    } else {
+        if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, w.dinv, xd, 1);
+        launch_sys_resid<double>(L, m, ba, Aop, xd, w.t, s);
+        rsrc = w.t;
+    }
+    hipLaunchKernelGGL(hz::k_init<double>, dim3(m.G), dim3(kBlock), 0, s, ba, rsrc);
+    hipLaunchKernelGGL(hz::k_fin_init<double>, dim3(1), dim3(kBlock), 0, s, ba);
+    hz::QArgs qa{};
+    qa.G = m.G;
+    qa.stride = m.stride;
+    qa.bmap = w.bmap;
+    qa.smap = w.smap;
+    qa.ndone = w.ndone;
+    qa.row_ptr = rp;
+    qa.col_idx = ci;
+    qa.vals = Aop;
+    qa.rt = w.rt;
+    qa.w = w.w;
+    qa.u = w.u;
+    qa.u1 = w.u1;
+    qa.au = w.au;
+    qa.au1 = w.au1;
+    qa.v = w.v;
+    qa.d = w.d;
+    qa.x = xd;
+    qa.part = w.part;
+    qa.sc = w.sc;
+    qa.tq = w.tq;
+    const dim3 G(m.G), B(kBlock);
+    hipLaunchKernelGGL(hz::k_q_fin_init, dim3(1), B, 0, s, qa);
+    with_lanes(L, [&]<int LL, int UU>() {
+        hipLaunchKernelGGL((hz::k_q_init<LL, UU>), G, B, 0, s, qa, static_cast<const double2*>(w.r0));
+    });
+    HZ_HIP(hipGetLastError());
+    SolverScal* hs = h->hsc;
+    HZ_HIP(hipMemcpyAsync(hs, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipMemcpyAsync(h->hflag, w.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    if (hs->bad_diag) return HZ_ERR_INVALID;
+    int launched = 0, poll = 8, rc = HZ_OK;
+    if (*h->hflag < 1) {
+        while (launched < maxiter) {
+            const int k_n = (maxiter - launched) < poll ? (maxiter - launched) : poll;
+            rc = launch_chunk(h, s, chunk_key(60, L, k_n, 0, qa), [&](hipStream_t q) {
+                with_lanes(L, [&]<int LL, int UU>() {
+                    for (int k = 0; k < k_n; ++k) {
+                        hipLaunchKernelGGL(hz::k_q_even, G, B, 0, q, qa);
+                        hipLaunchKernelGGL((hz::k_q_odd<LL, UU>), G, B, 0, q, qa);
+                        hipLaunchKernelGGL((hz::k_q_next<LL, UU>), G, B, 0, q, qa);
+                    }
+                });
+            });
+            if (rc) return rc;
+            launched += k_n;
+            HZ_HIP(hipMemcpyAsync(h->hflag, w.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+            HZ_HIP(hipStreamSynchronize(s));
+            if (*h->hflag >= 1) break;
+            if (poll < 64) poll *= 2;
+        }
+        hipLaunchKernelGGL(hz::k_q_conclude, dim3(1), dim3(64), 0, s, qa);
+    }
+    hipLaunchKernelGGL(hz::k_zero_if<double>, G, B, 0, s, ba);
+    if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, w.dinv, xd, 0);
+    hz::BicgArgs<double> b0 = ba;  // true residual with the caller's matrix
+    b0.vals = A;
+    launch_sys_resid<double>(L, m, b0, A, xd, w.t, s);
+    hipLaunchKernelGGL(hz::k_fin_true<double>, dim3(1), B, 0, s, b0);
+    HZ_HIP(hipGetLastError());
+    SolverScal out;
+    HZ_HIP(hipMemcpyAsync(&out, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    info->status = out.status;
+    info->iterations = out.iters;
+    info->outer_steps = 0;
+    info->relres_recursive = out.relres;
+    info->relres_true = out.relres_true;
+    info->breakdown = out.why;
+    return out.status;
+}
+
+
 // ------------------------------------------------------------------ shared-pattern batches
 
 // Lanes reserved per row for B systems: 16, 64 or 256.
@@ -1924,6 +2092,41 @@ int zbicgstabl_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* 
                                 char* ws2) {
                                 return solve_l(h, s, n, nnz, rp2, ci2, A2, b2, x2, ell, rtol, maxcycles, flags, ws2,
                                                info);
+                            });
+}
+
+size_t ztfqmr_workspace_bytes(int n, int nnz, int flags) {
+    if (n < 0 || nnz < 0) return 0;
+    return qsolve_ws_bytes(n, nnz, flags);
+}
+
+int ztfqmr_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c128* vals,
+                 const hz_c128* b, hz_c128* x, double rtol, int maxiter, int flags, void* ws, size_t ws_bytes,
+                 hz_solve_info* info) {
+    if (info) std::memset(info, 0, sizeof(*info));
+    if (h == nullptr || info == nullptr) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (!(rtol >= 0.0) || maxiter < 0) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
+        return HZ_ERR_INVALID;
+    if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
+    if ((flags & HZ_REORDER) && (flags & HZ_NO_REORDER)) return HZ_ERR_INVALID;
+    if (flags & HZ_RELIABLE) return HZ_ERR_INVALID;
+    const size_t need = qsolve_ws_bytes(n, nnz, flags);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (flags & HZ_VALIDATE) {
+        rc = validate_csr(h, s, n, nnz, rp, ci);
+        if (rc) return rc;
+    }
+    return with_renumbering(h, s, n, nnz, rp, ci, reinterpret_cast<const double2*>(vals),
+                            reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), flags,
+                            static_cast<char*>(ws), info,
+                            [&](const int* rp2, const int* ci2, const double2* A2, const double2* b2, double2* x2,
+                                char* ws2) {
+                                return solve_q(h, s, n, nnz, rp2, ci2, A2, b2, x2, rtol, maxiter, flags, ws2, info);
                             });
 }
 
