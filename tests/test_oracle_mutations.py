@@ -1,8 +1,8 @@
 """The oracle's pins catch plausible mistakes planted in a scratch copy of the oracle (CPU only).
 
 Each mutant copies oracle/, workloads/ and the pin tests into a temporary
-directory, changes one line of the oracle (the C solvers, the BiCGstab(l) or
-the TFQMR module), and runs the pins of that part there: they must fail.  The repository's own oracle is never modified.
+directory, changes one line of the oracle (the C solvers, the BiCGstab(l), TFQMR or
+storage-format module), and runs the pins of that part there: they must fail.  The repository's own oracle is never modified.
 """
 
 import os
@@ -106,6 +106,37 @@ MUTANTS = {
         "tests/test_oracle_tfqmr_pins.py",
     ),
     "tfqmr_eta_without_c_squared": ("tfqmr.py", "eta = c * c * alpha", "eta = c * alpha", "tests/test_oracle_tfqmr_pins.py"),
+    # storage formats (oracle/formats.py), against their own pins
+    "sell_sorted_ascending": (
+        "formats.py",
+        "rows.sort(key=lambda i: -lens[i])",
+        "rows.sort(key=lambda i: lens[i])",
+        "tests/test_oracle_formats_pins.py",
+    ),
+    "sell_lanes_transposed": (
+        "formats.py",
+        "q = int(chunk_ptr[c]) + (k // t) * C * t + r * t + (k % t)\n            col[q]",
+        "q = int(chunk_ptr[c]) + (k // t) * C * t + r + (k % t) * C\n            col[q]",
+        "tests/test_oracle_formats_pins.py",
+    ),
+    "sell_width_not_rounded_to_lanes": (
+        "formats.py",
+        "w = -(-longest // t) * t",
+        "w = longest",
+        "tests/test_oracle_formats_pins.py",
+    ),
+    "ell_row_major": (
+        "formats.py",
+        "col[k * n + i] = A.col_idx[lo + k]\n                val[k * n + i] = A.vals[lo + k]",
+        "col[i * K + k] = A.col_idx[lo + k]\n                val[i * K + k] = A.vals[lo + k]",
+        "tests/test_oracle_formats_pins.py",
+    ),
+    "hyb_width_strict": (
+        "formats.py",
+        "if np.count_nonzero(lens >= k) >= need:",
+        "if np.count_nonzero(lens >= k) > need:",
+        "tests/test_oracle_formats_pins.py",
+    ),
 }
 
 
