@@ -33,6 +33,7 @@
 #define HELMZ_H
 
 #include <stddef.h>
+#include <stdint.h>
 
 #ifdef __cplusplus
 extern "C" {
@@ -219,6 +220,62 @@ size_t ztfqmr_workspace_bytes(int n, int nnz, int flags);
 int ztfqmr_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
                  const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol, int maxiter, int flags, void *ws,
                  size_t ws_bytes, hz_solve_info *info);
+
+/*
+ * Storage formats beside CSR (Section 3.2 names coordinate, ELLPACK and
+ * hybrid storage as the alternatives to its CSR; SELL-C-sigma is Kreutzer et
+ * al.'s sliced ELLPACK).  All arrays are device memory owned by the caller,
+ * indices 0-based int32, values interleaved complex128.  Conversions are
+ * set-up calls: they validate the CSR arrays (HZ_ERR_INVALID), synchronise the
+ * stream and may be slow; the products are ordinary stream-ordered launches
+ * that trust the arrays the conversions wrote.
+ *
+ * ELL of width K: entry k of row i at k*n + i (column-major), padding column
+ * -1 and value 0.  HYB of width K: that ELL part holding the first
+ * min(len_i, K) entries of each row, plus the rest as COO triplets (row,
+ * column, value) in CSR order.  SELL-C-sigma with t lanes per row: rows
+ * sorted by decreasing length within windows of sigma rows (ties keep row
+ * order; sigma = 1 keeps CSR order), sorted position p holding row perm[p];
+ * chunk c = p / C, row r = p % C; chunk width w_c = its longest row rounded
+ * up to a multiple of t, chunk_ptr[c + 1] - chunk_ptr[c] = C w_c, entry k at
+ * chunk_ptr[c] + (k / t) C t + r t + k % t; padding column -1, value 0, the
+ * last chunk padded with empty rows.  t = 1 is Kreutzer et al.'s layout,
+ * t > 1 gives each row t neighbouring slots (Anzt et al.'s SELL-P).
+ *
+ * csr_format_workspace_bytes: scratch for csr_row_stats, csr_to_hyb and
+ * csr_sell_analyze on n rows (256-byte aligned).
+ * csr_row_stats: the longest row and the default HYB width (the largest K
+ * that at least ceil(n/3) rows reach: Bell and Garland's rule).
+ * csr_to_hyb: writes ELL(K) (K*n slots; K = the longest row gives plain ELL)
+ * and the COO remainder; *coo_nnz receives the remainder's size, and if it
+ * exceeds coo_cap nothing is written and HZ_ERR_WORKSPACE is returned (call
+ * with coo_cap = 0 to query).
+ * hyb_zspmv: y = A x from ELL(K) + COO (coo_nnz may be 0); x, y of n entries,
+ * no overlap.  Row sums: the ELL slots in order, plus the COO entries'.
+ * csr_sell_analyze: perm (n entries) and chunk_ptr (ceil(n/C) + 1 entries);
+ * *slots receives chunk_ptr's last entry, the length of the value and
+ * column arrays.  1 <= C <= 1024, t in {1, 2, 4, 8}, sigma = 1 or a
+ * multiple of C.
+ * csr_to_sell: fills sell_col / sell_val (slots entries) from CSR, perm and
+ * chunk_ptr; HZ_ERR_INVALID if they do not fit the matrix or slots.
+ * sell_zspmv: y = A x; y[perm[p]] receives sorted row p's sum.
+ */
+size_t csr_format_workspace_bytes(int n);
+int csr_row_stats(hz_handle *handle, hz_stream stream, int n, const int *row_ptr, void *ws, size_t ws_bytes,
+                  int *max_len, int *hyb_width);
+int csr_to_hyb(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+               const hz_c128 *vals, int K, int *ell_col, hz_c128 *ell_val, int coo_cap, int *coo_row, int *coo_col,
+               hz_c128 *coo_val, void *ws, size_t ws_bytes, int *coo_nnz);
+int hyb_zspmv(hz_handle *handle, hz_stream stream, int n, int K, const int *ell_col, const hz_c128 *ell_val,
+              int coo_nnz, const int *coo_row, const int *coo_col, const hz_c128 *coo_val, const hz_c128 *x,
+              hz_c128 *y);
+int csr_sell_analyze(hz_handle *handle, hz_stream stream, int n, const int *row_ptr, int C, int sigma, int t,
+                     int *perm, int64_t *chunk_ptr, void *ws, size_t ws_bytes, int64_t *slots);
+int csr_to_sell(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+                const hz_c128 *vals, int C, int t, const int *perm, const int64_t *chunk_ptr, int64_t slots,
+                int *sell_col, hz_c128 *sell_val);
+int sell_zspmv(hz_handle *handle, hz_stream stream, int n, int C, int t, const int *perm, const int64_t *chunk_ptr,
+               const int *sell_col, const hz_c128 *sell_val, const hz_c128 *x, hz_c128 *y);
 
 /*
  * Workspace (bytes) for zbicgstab_solve_varbatch.  row_off is a HOST array of

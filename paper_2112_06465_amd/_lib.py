@@ -62,6 +62,13 @@ SIGNATURES = {
     "zbicgstabl_solve": (I, [P, P, I, I, P, P, P, P, P, I, D, I, I, P, SZ, C.POINTER(HzInfo)]),
     "ztfqmr_workspace_bytes": (SZ, [I, I, I]),
     "ztfqmr_solve": (I, [P, P, I, I, P, P, P, P, P, D, I, I, P, SZ, C.POINTER(HzInfo)]),
+    "csr_format_workspace_bytes": (SZ, [I]),
+    "csr_row_stats": (I, [P, P, I, P, P, SZ, C.POINTER(I), C.POINTER(I)]),
+    "csr_to_hyb": (I, [P, P, I, I, P, P, P, I, P, P, I, P, P, P, P, SZ, C.POINTER(I)]),
+    "hyb_zspmv": (I, [P, P, I, I, P, P, I, P, P, P, P, P]),
+    "csr_sell_analyze": (I, [P, P, I, P, I, I, I, P, P, P, SZ, C.POINTER(C.c_int64)]),
+    "csr_to_sell": (I, [P, P, I, I, P, P, P, I, I, P, P, C.c_int64, P, P]),
+    "sell_zspmv": (I, [P, P, I, I, I, P, P, P, P, P, P]),
     "zbicgstab_mixed_workspace_bytes": (SZ, [I, I, I]),
     "zbicgstab_varbatch_workspace_bytes": (SZ, [I, P, I, I]),
     "zbicgstab_solve_varbatch": (I, [P, P, I, P, I, P, P, P, P, P, D, I, I, P, SZ, P]),

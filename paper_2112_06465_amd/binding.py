@@ -8,6 +8,7 @@ of the method happens here; every step runs in the library's kernels.
 from __future__ import annotations
 
 import ctypes as C
+from ctypes import byref as C_byref, c_int64 as C_int64
 import threading
 
 import torch
@@ -15,6 +16,7 @@ import torch
 from ._lib import HelmzError, HzC128, HzInfo, load
 
 OK, NOT_CONVERGED, BREAKDOWN, NONFINITE = 0, 1, 2, 3
+ERR_WORKSPACE = -3
 PRECOND_NONE, PRECOND_JACOBI, X0_ZERO, VALIDATE, SYMMETRIC = 0x0, 0x1, 0x4, 0x8, 0x10
 REORDER, NO_REORDER, RELIABLE = 0x20, 0x40, 0x80
 BD_NONE, BD_RHO, BD_RHAT_V, BD_TT, BD_OMEGA, BD_MR = 0, 1, 2, 3, 4, 5  # info["breakdown"]: what became 0 / singular
@@ -594,6 +596,116 @@ def _reorder_ws(n: int, nnz: int, dev, ws):
         ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
     _need(ws, "ws", torch.uint8, dev)
     return _aligned_ptr(ws, need), ws
+
+
+# ------------------------------------------------------------------ storage formats (ELL / HYB, SELL-C-sigma)
+
+
+def _fmt_ws(n, dev, ws):
+    need = int(load().csr_format_workspace_bytes(n))
+    if ws is None:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    _need(ws, "ws", torch.uint8, dev)
+    return _aligned_ptr(ws, need), ws
+
+
+def csr_row_stats(row_ptr, ws=None):
+    """(longest row, default HYB width) of a CSR pattern (csr_row_stats)."""
+    dev = row_ptr.device
+    _need(row_ptr, "row_ptr", torch.int32, dev)
+    n = row_ptr.numel() - 1
+    (wp, wbytes), _ws = _fmt_ws(n, dev, ws)
+    mx, K = C.c_int(), C.c_int()
+    rc = load().csr_row_stats(handle(dev), _stream(dev), n, row_ptr.data_ptr(), wp, wbytes, C.byref(mx), C.byref(K))
+    _check("csr_row_stats", rc)
+    return mx.value, K.value
+
+
+def csr_to_hyb(row_ptr, col_idx, vals, K=None, ws=None):
+    """HYB (ELL of width K plus COO remainder) of a CSR matrix (csr_to_hyb).
+
+    K=None takes the default width, K="ell" the longest row (plain ELL).
+    Returns a dict with n, K, ell_col [K*n], ell_val [K*n], coo_row, coo_col, coo_val.
+    """
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    mx, Kd = csr_row_stats(row_ptr, ws)
+    K = Kd if K is None else (mx if K == "ell" else int(K))
+    (wp, wbytes), _ws = _fmt_ws(n, dev, ws)
+    ell_col = torch.empty(K * n, dtype=torch.int32, device=dev)
+    ell_val = torch.empty(K * n, dtype=torch.complex128, device=dev)
+    cnt = C.c_int()
+    lib, h, st = load(), handle(dev), _stream(dev)
+    args = (h, st, n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(), vals.data_ptr(), K, ell_col.data_ptr(),
+            ell_val.data_ptr())
+    rc = lib.csr_to_hyb(*args, 0, None, None, None, wp, wbytes, C.byref(cnt))
+    _check("csr_to_hyb", rc, ok=(OK, ERR_WORKSPACE))
+    m = cnt.value
+    coo_row = torch.empty(m, dtype=torch.int32, device=dev)
+    coo_col = torch.empty(m, dtype=torch.int32, device=dev)
+    coo_val = torch.empty(m, dtype=torch.complex128, device=dev)
+    if rc != OK:
+        rc = lib.csr_to_hyb(*args, m, coo_row.data_ptr(), coo_col.data_ptr(), coo_val.data_ptr(), wp, wbytes,
+                            C.byref(cnt))
+        _check("csr_to_hyb", rc)
+    return {"n": n, "K": K, "ell_col": ell_col, "ell_val": ell_val, "coo_row": coo_row, "coo_col": coo_col,
+            "coo_val": coo_val}
+
+
+def hyb_zspmv(hyb, x, y=None):
+    """y = A x with A in HYB storage (hyb_zspmv)."""
+    dev, n = x.device, hyb["n"]
+    _need(x, "x", torch.complex128, dev)
+    if x.numel() != n:
+        raise ValueError("x has the wrong length")
+    if y is None:
+        y = torch.empty_like(x)
+    _need(y, "y", torch.complex128, dev)
+    m = hyb["coo_row"].numel()
+    rc = load().hyb_zspmv(handle(dev), _stream(dev), n, hyb["K"], hyb["ell_col"].data_ptr(),
+                          hyb["ell_val"].data_ptr(), m, hyb["coo_row"].data_ptr(), hyb["coo_col"].data_ptr(),
+                          hyb["coo_val"].data_ptr(), x.data_ptr(), y.data_ptr())
+    _check("hyb_zspmv", rc)
+    return y
+
+
+def csr_to_sell(row_ptr, col_idx, vals, C=64, sigma=None, t=1, ws=None):
+    """SELL-C-sigma with t lanes per row (csr_sell_analyze + csr_to_sell).
+
+    sigma=None sorts within windows of 32 chunks (32 C rows).  Returns a dict
+    with n, C, t, sigma, perm [n], chunk_ptr [ceil(n/C)+1] (int64), col, val.
+    """
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    sigma = 32 * C if sigma is None else int(sigma)
+    (wp, wbytes), _ws = _fmt_ws(n, dev, ws)
+    perm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)[:n]
+    chunk_ptr = torch.empty((n + C - 1) // C + 1 if C >= 1 else 1, dtype=torch.int64, device=dev)
+    slots = C_int64()
+    lib, h, st = load(), handle(dev), _stream(dev)
+    rc = lib.csr_sell_analyze(h, st, n, row_ptr.data_ptr(), C, sigma, t, perm.data_ptr(), chunk_ptr.data_ptr(), wp,
+                              wbytes, C_byref(slots))
+    _check("csr_sell_analyze", rc)
+    col = torch.empty(slots.value, dtype=torch.int32, device=dev)
+    val = torch.empty(slots.value, dtype=torch.complex128, device=dev)
+    rc = lib.csr_to_sell(h, st, n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(), vals.data_ptr(), C, t,
+                         perm.data_ptr(), chunk_ptr.data_ptr(), slots.value, col.data_ptr(), val.data_ptr())
+    _check("csr_to_sell", rc)
+    return {"n": n, "C": C, "t": t, "sigma": sigma, "perm": perm, "chunk_ptr": chunk_ptr, "col": col, "val": val}
+
+
+def sell_zspmv(sell, x, y=None):
+    """y = A x with A in SELL-C-sigma storage (sell_zspmv)."""
+    dev, n = x.device, sell["n"]
+    _need(x, "x", torch.complex128, dev)
+    if x.numel() != n:
+        raise ValueError("x has the wrong length")
+    if y is None:
+        y = torch.empty_like(x)
+    _need(y, "y", torch.complex128, dev)
+    rc = load().sell_zspmv(handle(dev), _stream(dev), n, sell["C"], sell["t"], sell["perm"].data_ptr(),
+                           sell["chunk_ptr"].data_ptr(), sell["col"].data_ptr(), sell["val"].data_ptr(),
+                           x.data_ptr(), y.data_ptr())
+    _check("sell_zspmv", rc)
+    return y
 
 
 def csr_level_order(row_ptr, col_idx, ws=None):

@@ -23,6 +23,7 @@
 #include "hz_spmv.hpp"
 #include "hz_bicgstabl.hpp"
 #include "hz_tfqmr.hpp"
+#include "hz_formats.hpp"
 
 using hz::cx;
 using hz::Geom;
@@ -1226,6 +1227,79 @@ int solve_q(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const in
     info->breakdown = out.why;
     return out.status;
 }
+
+
+// ------------------------------------------------------------------ storage formats (ELL / HYB, SELL-C-sigma)
+
+// Scratch of the format set-up calls: row lengths and their sorted copy, the
+// SELL sort keys and row indices, chunk sizes, HYB remainders and offsets, a
+// few result words and the rocPRIM scratch.
+struct FmtWs {
+    unsigned* len;
+    unsigned* len2;
+    unsigned long long* key;
+    unsigned long long* key2;
+    int* idx;
+    long long* cw;
+    int* rem;
+    int* off;
+    int* out;
+    void* tmp;
+    size_t tmp_bytes;
+};
+
+size_t fmt_tmp_bytes(int n) {
+    size_t a = 0, b = 0, c = 0, d = 0;
+    const unsigned* ku = nullptr;
+    unsigned* ko = nullptr;
+    const unsigned long long* k64 = nullptr;
+    unsigned long long* k64o = nullptr;
+    const int* vi = nullptr;
+    int* vo = nullptr;
+    const long long* li = nullptr;
+    long long* lo = nullptr;
+    if (rocprim::radix_sort_keys_desc(nullptr, a, ku, ko, unsigned(n), 0u, 32u) != hipSuccess) return 0;
+    if (rocprim::radix_sort_pairs(nullptr, b, k64, k64o, vi, vo, unsigned(n), 0u, 64u) != hipSuccess) return 0;
+    if (rocprim::exclusive_scan(nullptr, c, vi, vo, 0, size_t(n) + 1, rocprim::plus<int>()) != hipSuccess) return 0;
+    if (rocprim::exclusive_scan(nullptr, d, li, lo, 0LL, size_t(n) + 1, rocprim::plus<long long>()) != hipSuccess)
+        return 0;
+    return std::max<size_t>(std::max(std::max(a, b), std::max(c, d)), 1);
+}
+
+size_t fmt_layout(int n, char* base, FmtWs* out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const size_t nn = size_t(n > 0 ? n : 1);
+    FmtWs w{};
+    w.len = static_cast<unsigned*>(take(sizeof(unsigned) * nn));
+    w.len2 = static_cast<unsigned*>(take(sizeof(unsigned) * nn));
+    w.key = static_cast<unsigned long long*>(take(sizeof(unsigned long long) * nn));
+    w.key2 = static_cast<unsigned long long*>(take(sizeof(unsigned long long) * nn));
+    w.idx = static_cast<int*>(take(sizeof(int) * nn));
+    w.cw = static_cast<long long*>(take(sizeof(long long) * (nn + 1)));
+    w.rem = static_cast<int*>(take(sizeof(int) * (nn + 1)));
+    w.off = static_cast<int*>(take(sizeof(int) * (nn + 1)));
+    w.out = static_cast<int*>(take(sizeof(int) * 4));
+    w.tmp_bytes = fmt_tmp_bytes(n > 0 ? n : 1);
+    w.tmp = take(w.tmp_bytes);
+    if (out) *out = w;
+    return w.tmp_bytes ? off : 0;
+}
+
+// Blocks of a one-thread-per-item format launch: a multiple of 8 when at least 8, for the XCD-contiguous mapping.
+int fmt_grid(int64_t threads) {
+    const int64_t b = (threads + hz::kFmtBlock - 1) / hz::kFmtBlock;
+    return int(b >= 8 ? (b + 7) / 8 * 8 : b);
+}
+
+// Blocks of kFmtBlock threads covering n items (the set-up kernels index by kFmtBlock, not the solvers' kBlock).
+dim3 fgrid(int64_t n) { return dim3(unsigned((n + hz::kFmtBlock - 1) / hz::kFmtBlock)); }
+
+bool sell_shape_ok(int C, int t) { return C >= 1 && C <= 1024 && (t == 1 || t == 2 || t == 4 || t == 8); }
 
 
 // ------------------------------------------------------------------ shared-pattern batches
@@ -2550,6 +2624,203 @@ int csr_zpermute(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, 
                      reinterpret_cast<double2*>(vals_out));
     if (rc) return rc;
     HZ_HIP(hipStreamSynchronize(s));
+    return HZ_OK;
+}
+
+
+// ------------------------------------------------------------------ storage formats: C-ABI
+
+size_t csr_format_workspace_bytes(int n) {
+    if (n < 0) return 0;
+    return fmt_layout(n, nullptr, nullptr);
+}
+
+int csr_row_stats(hz_handle* h, hz_stream stream, int n, const int* rp, void* ws, size_t ws_bytes, int* max_len,
+                  int* hyb_width) {
+    if (h == nullptr || n < 0 || max_len == nullptr || hyb_width == nullptr) return HZ_ERR_INVALID;
+    *max_len = *hyb_width = 0;
+    if (n == 0) return HZ_OK;
+    if (rp == nullptr || misaligned(rp, 4)) return HZ_ERR_INVALID;
+    FmtWs w;
+    const size_t need = fmt_layout(n, static_cast<char*>(ws), &w);
+    if (need == 0) return HZ_ERR_HIP;
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(hz::k_fmt_len, fgrid(n), dim3(hz::kFmtBlock), 0, s, n, rp, w.len);
+    size_t tb = w.tmp_bytes;
+    HZ_HIP(rocprim::radix_sort_keys_desc(w.tmp, tb, static_cast<const unsigned*>(w.len), w.len2, unsigned(n), 0u,
+                                         32u, s));
+    hipLaunchKernelGGL(hz::k_fmt_stats, dim3(1), dim3(64), 0, s, n, static_cast<const unsigned*>(w.len2), w.out);
+    HZ_HIP(hipGetLastError());
+    int hv[2];
+    HZ_HIP(hipMemcpyAsync(hv, w.out, sizeof(hv), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    *max_len = hv[0];
+    *hyb_width = hv[1];
+    return HZ_OK;
+}
+
+int csr_to_hyb(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c128* vals,
+               int K, int* ell_col, hz_c128* ell_val, int coo_cap, int* coo_row, int* coo_col, hz_c128* coo_val,
+               void* ws, size_t ws_bytes, int* coo_nnz) {
+    if (h == nullptr || coo_nnz == nullptr || K < 0 || coo_cap < 0) return HZ_ERR_INVALID;
+    *coo_nnz = 0;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (n == 0) return HZ_OK;
+    if (K > 0 && (ell_col == nullptr || ell_val == nullptr)) return HZ_ERR_INVALID;
+    if (misaligned(vals, 16) || misaligned(ell_col, 4) || misaligned(ell_val, 16) || misaligned(coo_row, 4) ||
+        misaligned(coo_col, 4) || misaligned(coo_val, 16))
+        return HZ_ERR_INVALID;
+    FmtWs w;
+    const size_t need = fmt_layout(n, static_cast<char*>(ws), &w);
+    if (need == 0) return HZ_ERR_HIP;
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = validate_csr(h, s, n, nnz, rp, ci);
+    if (rc) return rc;
+    hipLaunchKernelGGL(hz::k_hyb_rem, fgrid(int64_t(n) + 1), dim3(hz::kFmtBlock), 0, s, n, rp, K, w.rem);
+    size_t tb = w.tmp_bytes;
+    HZ_HIP(rocprim::exclusive_scan(w.tmp, tb, static_cast<const int*>(w.rem), w.off, 0, size_t(n) + 1,
+                                   rocprim::plus<int>(), s));
+    int total = 0;
+    HZ_HIP(hipMemcpyAsync(&total, w.off + n, sizeof(int), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    *coo_nnz = total;
+    if (total > coo_cap) return HZ_ERR_WORKSPACE;
+    if (total > 0 && (coo_row == nullptr || coo_col == nullptr || coo_val == nullptr)) return HZ_ERR_INVALID;
+    hipLaunchKernelGGL(hz::k_hyb_fill, fgrid(n), dim3(hz::kFmtBlock), 0, s, n, rp, ci,
+                       reinterpret_cast<const double2*>(vals), K, static_cast<const int*>(w.off), ell_col,
+                       reinterpret_cast<double2*>(ell_val), coo_row, coo_col, reinterpret_cast<double2*>(coo_val));
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+int hyb_zspmv(hz_handle* h, hz_stream stream, int n, int K, const int* ell_col, const hz_c128* ell_val, int coo_nnz,
+              const int* coo_row, const int* coo_col, const hz_c128* coo_val, const hz_c128* x, hz_c128* y) {
+    if (h == nullptr || n < 0 || K < 0 || coo_nnz < 0) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (x == nullptr || y == nullptr || misaligned(x, 16) || misaligned(y, 16)) return HZ_ERR_INVALID;
+    if (K > 0 && (ell_col == nullptr || ell_val == nullptr)) return HZ_ERR_INVALID;
+    if (coo_nnz > 0 && (coo_row == nullptr || coo_col == nullptr || coo_val == nullptr)) return HZ_ERR_INVALID;
+    if (misaligned(ell_col, 4) || misaligned(ell_val, 16) || misaligned(coo_row, 4) || misaligned(coo_col, 4) ||
+        misaligned(coo_val, 16))
+        return HZ_ERR_INVALID;
+    if (overlap(x, 16 * size_t(n), y, 16 * size_t(n))) return HZ_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int G = fmt_grid(n);
+    hipLaunchKernelGGL((hz::k_ell_spmv<4>), dim3(G), dim3(hz::kFmtBlock), 0, s, n, K, G, ell_col,
+                       reinterpret_cast<const double2*>(ell_val), reinterpret_cast<const double2*>(x),
+                       reinterpret_cast<double2*>(y));
+    if (coo_nnz > 0)
+        hipLaunchKernelGGL(hz::k_coo_add, fgrid(coo_nnz), dim3(hz::kFmtBlock), 0, s, coo_nnz, coo_row, coo_col,
+                           reinterpret_cast<const double2*>(coo_val), reinterpret_cast<const double2*>(x),
+                           reinterpret_cast<double2*>(y));
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+int csr_sell_analyze(hz_handle* h, hz_stream stream, int n, const int* rp, int C, int sigma, int t, int* perm,
+                     int64_t* chunk_ptr, void* ws, size_t ws_bytes, int64_t* slots) {
+    if (h == nullptr || n < 0 || slots == nullptr || !sell_shape_ok(C, t)) return HZ_ERR_INVALID;
+    if (sigma < 1 || (sigma > 1 && sigma % C != 0)) return HZ_ERR_INVALID;
+    *slots = 0;
+    if (chunk_ptr == nullptr || misaligned(chunk_ptr, 8)) return HZ_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n == 0) {
+        HZ_HIP(hipMemsetAsync(chunk_ptr, 0, sizeof(int64_t), s));
+        return HZ_OK;
+    }
+    if (rp == nullptr || perm == nullptr || misaligned(rp, 4) || misaligned(perm, 4)) return HZ_ERR_INVALID;
+    FmtWs w;
+    const size_t need = fmt_layout(n, static_cast<char*>(ws), &w);
+    if (need == 0) return HZ_ERR_HIP;
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    const int nch = (n + C - 1) / C;
+    if (sigma == 1) {
+        hipLaunchKernelGGL(hz::k_iota, fgrid(n), dim3(hz::kFmtBlock), 0, s, n, perm);
+    } else {
+        hipLaunchKernelGGL(hz::k_sell_keys, fgrid(n), dim3(hz::kFmtBlock), 0, s, n, rp, sigma, w.key, w.idx);
+        size_t tb = w.tmp_bytes;
+        HZ_HIP(rocprim::radix_sort_pairs(w.tmp, tb, static_cast<const unsigned long long*>(w.key), w.key2,
+                                         static_cast<const int*>(w.idx), perm, unsigned(n), 0u, 64u, s));
+    }
+    long long* cp = reinterpret_cast<long long*>(chunk_ptr);
+    hipLaunchKernelGGL(hz::k_sell_widths, fgrid(int64_t(nch) + 1), dim3(hz::kFmtBlock), 0, s, n, nch, C, t, rp,
+                       static_cast<const int*>(perm), w.cw);
+    size_t tb = w.tmp_bytes;
+    HZ_HIP(rocprim::exclusive_scan(w.tmp, tb, static_cast<const long long*>(w.cw), cp, 0LL, size_t(nch) + 1,
+                                   rocprim::plus<long long>(), s));
+    HZ_HIP(hipGetLastError());
+    long long total = 0;
+    HZ_HIP(hipMemcpyAsync(&total, cp + nch, sizeof(long long), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    *slots = total;
+    return HZ_OK;
+}
+
+int csr_to_sell(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c128* vals,
+                int C, int t, const int* perm, const int64_t* chunk_ptr, int64_t slots, int* sell_col,
+                hz_c128* sell_val) {
+    if (h == nullptr || !sell_shape_ok(C, t) || slots < 0) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (n == 0) return HZ_OK;
+    if (perm == nullptr || chunk_ptr == nullptr || misaligned(perm, 4) || misaligned(chunk_ptr, 8) ||
+        misaligned(vals, 16))
+        return HZ_ERR_INVALID;
+    if (slots > 0 && (sell_col == nullptr || sell_val == nullptr || misaligned(sell_col, 4) ||
+                      misaligned(sell_val, 16)))
+        return HZ_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = validate_csr(h, s, n, nnz, rp, ci);
+    if (rc) return rc;
+    const int nch = (n + C - 1) / C;
+    HZ_HIP(hipMemsetAsync(h->dflag, 0, sizeof(int), s));
+    hipLaunchKernelGGL(hz::k_sell_fill, fgrid(int64_t(nch) * C), dim3(hz::kFmtBlock), 0, s, n, nch, C, t, rp, ci,
+                       reinterpret_cast<const double2*>(vals), perm, reinterpret_cast<const long long*>(chunk_ptr),
+                       (long long)slots, sell_col, reinterpret_cast<double2*>(sell_val), h->dflag);
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipMemcpyAsync(h->hflag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    return *h->hflag ? HZ_ERR_INVALID : HZ_OK;
+}
+
+int sell_zspmv(hz_handle* h, hz_stream stream, int n, int C, int t, const int* perm, const int64_t* chunk_ptr,
+               const int* sell_col, const hz_c128* sell_val, const hz_c128* x, hz_c128* y) {
+    if (h == nullptr || n < 0 || !sell_shape_ok(C, t)) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (perm == nullptr || chunk_ptr == nullptr || x == nullptr || y == nullptr) return HZ_ERR_INVALID;
+    if (misaligned(perm, 4) || misaligned(chunk_ptr, 8) || misaligned(sell_col, 4) || misaligned(sell_val, 16) ||
+        misaligned(x, 16) || misaligned(y, 16))
+        return HZ_ERR_INVALID;
+    if (overlap(x, 16 * size_t(n), y, 16 * size_t(n))) return HZ_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nch = (n + C - 1) / C;
+    const int G = fmt_grid(int64_t(nch) * C * t);
+    const auto* cp = reinterpret_cast<const long long*>(chunk_ptr);
+    const auto* sv = reinterpret_cast<const double2*>(sell_val);
+    const auto* xv = reinterpret_cast<const double2*>(x);
+    auto* yv = reinterpret_cast<double2*>(y);
+    switch (t) {
+        case 1:
+            hipLaunchKernelGGL((hz::k_sell_spmv<1, 4>), dim3(G), dim3(hz::kFmtBlock), 0, s, n, nch, C, G, perm, cp,
+                               sell_col, sv, xv, yv);
+            break;
+        case 2:
+            hipLaunchKernelGGL((hz::k_sell_spmv<2, 4>), dim3(G), dim3(hz::kFmtBlock), 0, s, n, nch, C, G, perm, cp,
+                               sell_col, sv, xv, yv);
+            break;
+        case 4:
+            hipLaunchKernelGGL((hz::k_sell_spmv<4, 4>), dim3(G), dim3(hz::kFmtBlock), 0, s, n, nch, C, G, perm, cp,
+                               sell_col, sv, xv, yv);
+            break;
+        default:
+            hipLaunchKernelGGL((hz::k_sell_spmv<8, 4>), dim3(G), dim3(hz::kFmtBlock), 0, s, n, nch, C, G, perm, cp,
+                               sell_col, sv, xv, yv);
+            break;
+    }
+    HZ_HIP(hipGetLastError());
     return HZ_OK;
 }
 
