@@ -195,6 +195,54 @@ def spmv_cabin(hz, torch, dev, A, rp, ci, vals, reps=10):
     res["level_sets"] = timed(rp2, ci2, v2, xp)
     tune = hz.autotune_spmv(rp2, ci2, v2, xp, details=True)
     res["level_sets_tuned"] = dict(timed(rp2, ci2, v2, xp), form=tune["form"], lanes=tune["form_lanes"])
+    # the same renumbered matrix in ELL (its longest row: 15 entries against a mean of 14.6)
+    ell = hz.csr_to_hyb(rp2, ci2, v2, K="ell")
+    for _ in range(2):
+        hz.hyb_zspmv(ell, xp, y)
+    ev[0].record()
+    for _ in range(reps):
+        hz.hyb_zspmv(ell, xp, y)
+    ev[1].record()
+    torch.cuda.synchronize()
+    us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    gbs = spmv_bytes(n, nnz) / (us * 1e-6) / 1e9
+    res["level_sets_ell"] = {"us": round(us, 2), "GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                             "K": ell["K"]}
+    return res
+
+
+def spmv_formats(hz, torch, dev, A, rp, ci, vals, replicas=6, reps=30):
+    """Cold zSpMV of the cylinder in ELL (HYB at the longest row) and SELL-64-1, beside CSR.
+
+    The same replica cycling as the roofline loop (every launch reads cold data); GB/s on the CSR byte model, so
+    the figures compare the operation, and each format's stored bytes beside them.
+    """
+    n, nnz = A.n, A.nnz
+    rng = np.random.default_rng(3)
+    x = torch.from_numpy(rng.standard_normal(n) + 1j * rng.standard_normal(n)).to(dev)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    res = {"workload": f"cylinder (n={n}, nnz={nnz}), {replicas} replicas, {reps} launches"}
+    for label, conv, prod, stored in (
+        ("ell", lambda r, c, v: hz.csr_to_hyb(r, c, v, K="ell"), hz.hyb_zspmv,
+         lambda f: 20 * f["K"] * n + 32 * n),
+        ("sell_64_1", lambda r, c, v: hz.csr_to_sell(r, c, v, C=64, sigma=1, t=1), hz.sell_zspmv,
+         lambda f: 20 * f["col"].numel() + 4 * n + 8 * f["chunk_ptr"].numel() + 32 * n),
+    ):
+        reps_ = [(conv(rp.clone(), ci.clone(), vals.clone()), x.clone(), torch.empty_like(x)) for _ in range(replicas)]
+        for f, xx, yy in reps_:
+            prod(f, xx, yy)
+        ev[0].record()
+        for k in range(reps):
+            f, xx, yy = reps_[k % replicas]
+            prod(f, xx, yy)
+        ev[1].record()
+        torch.cuda.synchronize()
+        us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+        gbs = spmv_bytes(n, nnz) / (us * 1e-6) / 1e9
+        res[label] = {"us": round(us, 2), "GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                      "stored_bytes": int(stored(reps_[0][0]))}
+        del reps_
+        torch.cuda.empty_cache()
     return res
 
 
@@ -510,6 +558,7 @@ def main():
             "step_ms": [round(s, 3) for s in step_ms],
         },
     }
+    out["spmv_formats"] = spmv_formats(hz, torch, dev, A, rp, ci, vals)
     if not args.no_time_to_tol:
         out["time_to_tol"] = [time_to_tol(hz, torch, dev, "cylinder", rp, ci, vals, b, A)]
         if not args.no_cabin:

@@ -2709,9 +2709,17 @@ int hyb_zspmv(hz_handle* h, hz_stream stream, int n, int K, const int* ell_col, 
     if (overlap(x, 16 * size_t(n), y, 16 * size_t(n))) return HZ_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int G = fmt_grid(n);
-    hipLaunchKernelGGL((hz::k_ell_spmv<4>), dim3(G), dim3(hz::kFmtBlock), 0, s, n, K, G, ell_col,
-                       reinterpret_cast<const double2*>(ell_val), reinterpret_cast<const double2*>(x),
-                       reinterpret_cast<double2*>(y));
+    const auto* ev = reinterpret_cast<const double2*>(ell_val);
+    const auto* xv = reinterpret_cast<const double2*>(x);
+    auto* yv = reinterpret_cast<double2*>(y);
+    static const bool looped = std::getenv("HZ_ELL_LOOP") != nullptr;  // the generic loop for every width
+    if (K >= 1 && K <= 8 && !looped)
+        hipLaunchKernelGGL((hz::k_ell_spmv_full<8>), dim3(G), dim3(hz::kFmtBlock), 0, s, n, K, G, ell_col, ev, xv, yv);
+    else if (K >= 1 && K <= 16 && !looped)
+        hipLaunchKernelGGL((hz::k_ell_spmv_full<16>), dim3(G), dim3(hz::kFmtBlock), 0, s, n, K, G, ell_col, ev, xv,
+                           yv);
+    else
+        hipLaunchKernelGGL((hz::k_ell_spmv<4>), dim3(G), dim3(hz::kFmtBlock), 0, s, n, K, G, ell_col, ev, xv, yv);
     if (coo_nnz > 0)
         hipLaunchKernelGGL(hz::k_coo_add, fgrid(coo_nnz), dim3(hz::kFmtBlock), 0, s, coo_nnz, coo_row, coo_col,
                            reinterpret_cast<const double2*>(coo_val), reinterpret_cast<const double2*>(x),

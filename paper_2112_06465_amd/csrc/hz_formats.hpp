@@ -120,6 +120,41 @@ __global__ __launch_bounds__(kFmtBlock) void k_ell_spmv(int n, int K, int G, con
     y[i] = mk<double>(ax, ay);
 }
 
+// Rows of at most U slots (1 <= K <= U): all of a thread's slot loads in one
+// straight-line batch (slot indices clamped to K - 1, the extra ones
+// zeroed), so the whole row is in flight at once.  One thread per row leaves
+// few waves per SIMD on these matrices, so the loads in flight per thread
+// set the product's bandwidth.
+template <int U>
+__global__ __launch_bounds__(kFmtBlock) void k_ell_spmv_full(int n, int K, int G, const int* __restrict__ col,
+                                                             const double2* __restrict__ val,
+                                                             const double2* __restrict__ x,
+                                                             double2* __restrict__ y) {
+    const int64_t i = fmt_thread(G);
+    if (i >= n) return;
+    int c[U];
+    double2 v[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t q = (int64_t)(u < K ? u : K - 1) * n + i;
+        c[u] = col[q];
+        v[u] = val[q];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) xv[u] = x[c[u] < 0 ? i : c[u]];
+    double ax = 0.0, ay = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool pad = u >= K || c[u] < 0;
+        const double vx = pad ? 0.0 : v[u].x, vy = pad ? 0.0 : v[u].y;
+        ax = __builtin_fma(vx, xv[u].x, ax);
+        ax = __builtin_fma(-vy, xv[u].y, ax);
+        ay = __builtin_fma(vx, xv[u].y, ay);
+        ay = __builtin_fma(vy, xv[u].x, ay);
+    }
+    y[i] = mk<double>(ax, ay);
+}
+
 // COO part of a HYB product: the thread of a row's first COO entry sums the
 // row's COO entries in order and adds them to y (one writer per row).
 __global__ __launch_bounds__(kFmtBlock) void k_coo_add(int m, const int* __restrict__ row, const int* __restrict__ col,
