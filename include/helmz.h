@@ -185,6 +185,25 @@ int zbicgstab_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const i
                     size_t ws_bytes, hz_solve_info *info);
 
 /*
+ * zbicgstab_solve_async: the same solve with nothing on the host waiting for
+ * the stream (Section 7's iteration control kept on the device): every
+ * launch of up to maxiter iterations is enqueued in chunks of 64 (kernels
+ * after the exit return at entry, a few microseconds each, so maxiter should
+ * be near the expected count), and the result is written by a kernel to
+ * info_dev, a device hz_solve_info (8-byte aligned), when the stream reaches
+ * it.  b, x, ws and info_dev must stay valid until then.  One system, FP64,
+ * caller's numbering: HZ_REORDER, HZ_VALIDATE and HZ_RELIABLE are invalid,
+ * renumbering never happens (workspace as for zbicgstab_solve with
+ * HZ_NO_REORDER).  The first call for a matrix size uploads its launch map
+ * to a copy kept by the handle (one synchronisation); later calls only
+ * enqueue.  A zero diagonal under Jacobi is reported as info_dev->status =
+ * HZ_ERR_INVALID.  Returns HZ_OK once enqueued, or an argument error.
+ */
+int zbicgstab_solve_async(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+                          const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol, int maxiter, int flags,
+                          void *ws, size_t ws_bytes, hz_solve_info *info_dev);
+
+/*
  * BiCGstab(l), the paper's P-BiCGSTAB(l) (Section 6, iterative Krylov
  * methods; l = 8 in its speed-up tables), in Sleijpen and Fokkema's form:
  * each cycle makes l Bi-CG steps, then takes the coefficients that minimise

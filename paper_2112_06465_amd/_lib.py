@@ -61,6 +61,7 @@ SIGNATURES = {
     "zbicgstabl_workspace_bytes": (SZ, [I, I, I, I]),
     "zbicgstabl_solve": (I, [P, P, I, I, P, P, P, P, P, I, D, I, I, P, SZ, C.POINTER(HzInfo)]),
     "ztfqmr_workspace_bytes": (SZ, [I, I, I]),
+    "zbicgstab_solve_async": (I, [P, P, I, I, P, P, P, P, P, D, I, I, P, SZ, P]),
     "ztfqmr_solve": (I, [P, P, I, I, P, P, P, P, P, D, I, I, P, SZ, C.POINTER(HzInfo)]),
     "csr_format_workspace_bytes": (SZ, [I]),
     "csr_row_stats": (I, [P, P, I, P, P, SZ, C.POINTER(I), C.POINTER(I)]),

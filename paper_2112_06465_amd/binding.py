@@ -253,6 +253,45 @@ def zbicgstabl_solve(row_ptr, col_idx, vals, b, x=None, ell=8, rtol=1e-8, maxcyc
     return x, info.as_dict()
 
 
+def zbicgstab_solve_async(row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxiter=20000,
+                          flags=PRECOND_NONE | X0_ZERO, ws=None, info=None):
+    """Enqueue a BiCGStab solve with no host wait (zbicgstab_solve_async).
+
+    Returns (x, info) where info is a device tensor holding an hz_solve_info,
+    filled when the stream reaches the end of the solve; ``read_info(info)``
+    decodes it (and waits for it).
+    """
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    _need(b, "b", torch.complex128, dev)
+    if b.numel() != n:
+        raise ValueError("b has the wrong length")
+    if x is None:
+        x = torch.zeros(n, dtype=torch.complex128, device=dev)
+        flags |= X0_ZERO
+    _need(x, "x", torch.complex128, dev)
+    need = zbicgstab_workspace_bytes(n, nnz, flags | NO_REORDER)
+    if ws is None:
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    _need(ws, "ws", torch.uint8, dev)
+    wp, wbytes = _aligned_ptr(ws, need)
+    if info is None:
+        info = torch.empty(C.sizeof(HzInfo), dtype=torch.uint8, device=dev)
+    _need(info, "info", torch.uint8, dev)
+    if info.numel() < C.sizeof(HzInfo):
+        raise ValueError("info is too small")
+    rc = load().zbicgstab_solve_async(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                                      vals.data_ptr(), b.data_ptr(), x.data_ptr(), float(rtol), int(maxiter),
+                                      int(flags), wp, wbytes, info.data_ptr())
+    _check("zbicgstab_solve_async", rc)
+    return x, info
+
+
+def read_info(info) -> dict:
+    """Decode a device hz_solve_info written by an asynchronous solve (copies it to the host)."""
+    raw = bytes(info[: C.sizeof(HzInfo)].cpu().numpy().tobytes())
+    return HzInfo.from_buffer_copy(raw).as_dict()
+
+
 def ztfqmr_workspace_bytes(n: int, nnz: int, flags: int = 0) -> int:
     return int(load().ztfqmr_workspace_bytes(n, nnz, flags))
 

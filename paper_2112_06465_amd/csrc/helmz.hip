@@ -57,6 +57,12 @@ struct GraphEntry {
     hipGraphExec_t exec;
 };
 
+// A single-system work map kept on the device: blocks then the system entry.
+struct MapEntry {
+    int n, L;
+    void* dev;
+};
+
 struct hz_handle {
     int device;
     std::vector<TuneEntry> tune;  // autotuned lanes per row, newest last
@@ -69,6 +75,7 @@ struct hz_handle {
     int* hflag;            // pinned host word
     SolverScal* hsc;       // pinned host copy of the solver scalars
     SolverScal* hsc2;      // pinned host copy of the refinement's outer scalars
+    std::vector<MapEntry> maps;  // device copies of single-system work maps (the asynchronous solve)
 };
 
 namespace {
@@ -474,9 +481,10 @@ int upload_map(hipStream_t s, const WorkMap& m, const SolveWs& w) {
 // one more first kernel that concludes the last iteration; polls the
 // done-counter between chunks of 8, 16, ..., 64 iterations.
 template <typename T>
-int iterate(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>& a, int L, int maxiter, bool fused) {
+int iterate(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>& a, int L, int maxiter, bool fused,
+            bool poll_done = true) {
     const dim3 G(m.G), B(kBlock);
-    int launched = 0, poll = 8;
+    int launched = 0, poll = poll_done ? 8 : 64;
     while (launched < maxiter) {
         const int k_n = (maxiter - launched) < poll ? (maxiter - launched) : poll;
         const bool tail = launched + k_n == maxiter;
@@ -500,6 +508,7 @@ int iterate(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>
         });
         if (rc) return rc;
         launched += k_n;
+        if (!poll_done) continue;  // every chunk enqueued; kernels after the exit return at entry
         HZ_HIP(hipMemcpyAsync(h->hflag, a.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
         HZ_HIP(hipStreamSynchronize(s));
         if (*h->hflag >= m.nsys) break;
@@ -507,6 +516,41 @@ int iterate(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>
     }
     HZ_HIP(hipGetLastError());
     return HZ_OK;
+}
+
+// The single-system map for (n, L) copied device to device from the handle's
+// cache (uploaded, with one synchronisation, the first time): no host wait
+// on the caller's stream afterwards.
+int upload_map_cached(hz_handle* h, hipStream_t s, int n, int L, const WorkMap& m, const SolveWs& w) {
+    const size_t nb = sizeof(BlockMap) * m.blocks.size(), ns = sizeof(SysMap) * m.systems.size();
+    void* dev = nullptr;
+    for (const MapEntry& e : h->maps)
+        if (e.n == n && e.L == L) dev = e.dev;
+    if (dev == nullptr) {
+        HZ_HIP(hipMalloc(&dev, nb + ns));
+        h->maps.push_back(MapEntry{n, L, dev});
+        HZ_HIP(hipMemcpy(dev, m.blocks.data(), nb, hipMemcpyHostToDevice));
+        HZ_HIP(hipMemcpy(static_cast<char*>(dev) + nb, m.systems.data(), ns, hipMemcpyHostToDevice));
+    }
+    HZ_HIP(hipMemcpyAsync(w.bmap, dev, nb, hipMemcpyDeviceToDevice, s));
+    HZ_HIP(hipMemcpyAsync(w.smap, static_cast<char*>(dev) + nb, ns, hipMemcpyDeviceToDevice, s));
+    HZ_HIP(hipMemsetAsync(w.ndone, 0, sizeof(int), s));
+    return HZ_OK;
+}
+
+// hz_solve_info of system 0 from its device scalars (asynchronous solve).
+__global__ void k_info_out(const SolverScal* sc, hz_solve_info* info) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    hz_solve_info o;
+    o.status = sc->bad_diag ? HZ_ERR_INVALID : sc->status;
+    o.iterations = sc->bad_diag ? 0 : sc->iters;
+    o.outer_steps = 0;
+    o.renumbered = 0;
+    o.relres_recursive = sc->relres;
+    o.relres_true = sc->relres_true;
+    o.breakdown = sc->why;
+    o.reserved = 0;
+    *info = o;
 }
 
 template <typename T>
@@ -522,14 +566,15 @@ void launch_sys_resid(int L, const WorkMap& m, const hz::BicgArgs<T>& a, const c
 // in/out; infos[j] receives system j's result.  Returns the largest status.
 int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nnz, const int* rp, const int* ci,
                const double2* A, const double2* bd, double2* xd, double rtol, int maxiter, int flags, char* ws,
-               hz_solve_info* infos) {
+               hz_solve_info* infos, hz_solve_info* info_dev = nullptr) {
+    const bool async = info_dev != nullptr;  // one system; nothing waits for the stream
     const int n = row_off[nsys] - row_off[0];
     const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
     const int L = pick_lanes(h, rp, ci, n, nnz);
     const WorkMap m = build_map(nsys, row_off, L);
     SolveWs w;
     ws_layout<double>(n, nnz, jacobi, nsys, m.G, ws, &w);
-    int rc = upload_map(s, m, w);
+    int rc = async ? upload_map_cached(h, s, n, L, m, w) : upload_map(s, m, w);
     if (rc) return rc;
     double2* r = static_cast<double2*>(w.vec[0]);
     double2* t = static_cast<double2*>(w.vec[7]);
@@ -558,6 +603,18 @@ int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nn
     hipLaunchKernelGGL(hz::k_init<double>, dim3(m.G), dim3(kBlock), 0, s, a, rsrc);
     hipLaunchKernelGGL(hz::k_fin_init<double>, dim3(nsys), dim3(kBlock), 0, s, a);
     HZ_HIP(hipGetLastError());
+    if (async) {
+        rc = iterate<double>(h, s, m, a, L, maxiter, choose_fused(h, n), false);
+        if (rc) return rc;
+        hipLaunchKernelGGL(hz::k_zero_if<double>, dim3(m.G), dim3(kBlock), 0, s, a);
+        if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, dinv, xd, 0);
+        const hz::BicgArgs<double> a0 = bicg_args<double>(m, rp, ci, A, bd, xd, w);
+        launch_sys_resid<double>(L, m, a0, A, xd, t, s);
+        hipLaunchKernelGGL(hz::k_fin_true<double>, dim3(1), dim3(kBlock), 0, s, a0);
+        hipLaunchKernelGGL(k_info_out, dim3(1), dim3(64), 0, s, static_cast<const SolverScal*>(w.sc), info_dev);
+        HZ_HIP(hipGetLastError());
+        return HZ_OK;
+    }
     SolverScal* hs = h->hsc;
     HZ_HIP(hipMemcpyAsync(hs, w.sc, sizeof(SolverScal), hipMemcpyDeviceToHost, s));
     HZ_HIP(hipMemcpyAsync(h->hflag, w.ndone, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1942,6 +1999,7 @@ int hz_handle_destroy(hz_handle* h) {
     if (h->hsc) (void)hipHostFree(h->hsc);
     if (h->hsc2) (void)hipHostFree(h->hsc2);
     for (const GraphEntry& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    for (const MapEntry& e : h->maps) (void)hipFree(e.dev);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
     return HZ_OK;
@@ -2131,6 +2189,27 @@ int zbicgstab_solve(hz_handle* h, hz_stream stream, int n, int nnz, const int* r
     return solve_single(h, s, n, nnz, rp, ci, reinterpret_cast<const double2*>(vals),
                         reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxiter, flags,
                         static_cast<char*>(ws), info);
+}
+
+int zbicgstab_solve_async(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci,
+                          const hz_c128* vals, const hz_c128* b, hz_c128* x, double rtol, int maxiter, int flags,
+                          void* ws, size_t ws_bytes, hz_solve_info* info_dev) {
+    if (h == nullptr || info_dev == nullptr || misaligned(info_dev, 8)) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (!(rtol >= 0.0) || maxiter < 0 || n == 0) return HZ_ERR_INVALID;
+    if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
+        return HZ_ERR_INVALID;
+    if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
+    if (flags & (HZ_REORDER | HZ_VALIDATE | HZ_RELIABLE)) return HZ_ERR_INVALID;
+    const int f = flags | HZ_NO_REORDER;
+    const size_t need = single_ws_bytes(n, nnz, f);
+    if (ws == nullptr || ws_bytes < need || misaligned(ws, kAlign)) return HZ_ERR_WORKSPACE;
+    const int row_off[2] = {0, n};
+    hz_solve_info unused;
+    return solve_fp64(h, static_cast<hipStream_t>(stream), 1, row_off, nnz, rp, ci,
+                      reinterpret_cast<const double2*>(vals), reinterpret_cast<const double2*>(b),
+                      reinterpret_cast<double2*>(x), rtol, maxiter, f, static_cast<char*>(ws), &unused, info_dev);
 }
 
 size_t zbicgstabl_workspace_bytes(int n, int nnz, int ell, int flags) {
