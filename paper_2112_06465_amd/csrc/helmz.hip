@@ -1245,15 +1245,21 @@ int solve_q(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const in
     HZ_HIP(hipStreamSynchronize(s));
     if (hs->bad_diag) return HZ_ERR_INVALID;
     int launched = 0, poll = 8, rc = HZ_OK;
+    const bool fused = choose_fused(h, n);  // K3 in one launch (two gathered vectors) or gather-light
     if (*h->hflag < 1) {
         while (launched < maxiter) {
             const int k_n = (maxiter - launched) < poll ? (maxiter - launched) : poll;
-            rc = launch_chunk(h, s, chunk_key(60, L, k_n, 0, qa), [&](hipStream_t q) {
+            rc = launch_chunk(h, s, chunk_key(fused ? 60 : 61, L, k_n, 0, qa), [&](hipStream_t q) {
                 with_lanes(L, [&]<int LL, int UU>() {
                     for (int k = 0; k < k_n; ++k) {
                         hipLaunchKernelGGL(hz::k_q_even, G, B, 0, q, qa);
                         hipLaunchKernelGGL((hz::k_q_odd<LL, UU>), G, B, 0, q, qa);
-                        hipLaunchKernelGGL((hz::k_q_next<LL, UU>), G, B, 0, q, qa);
+                        if (fused) {
+                            hipLaunchKernelGGL((hz::k_q_next<LL, UU>), G, B, 0, q, qa);
+                        } else {
+                            hipLaunchKernelGGL(hz::k_q_dir, G, B, 0, q, qa);
+                            hipLaunchKernelGGL((hz::k_q_next_light<LL, UU>), G, B, 0, q, qa);
+                        }
                     }
                 });
             });

@@ -15,6 +15,8 @@
 //       beta = rho_new / rho; per gathered column u'' = w + beta u'
 //       (formed on the fly); per row: x += eta d, u = u'', Au = A u'',
 //       v = A u'' + beta (A u' + beta v); partial <r~, v>
+// Above about 10^5 rows K3 runs as two launches (k_q_dir, k_q_next_light) so
+// that its product gathers one vector, as the BiCGStab iteration does there.
 // tau, theta, eta of half step m live in slot m & 1 of the TFQMR scalars,
 // rho of iteration k in rho2[(k - 1) & 1]: a launch never reads a slot its
 // own leader writes.  K1 reads the iteration number `iter` and publishes it
@@ -315,6 +317,84 @@ __global__ HZ_STREAM_BOUNDS void k_q_next(const QArgs a) {
         e[0] = c.x;
         e[1] = c.y;
     });
+    store_sys_partials<2>(a.part + kPartA * a.stride, a.stride, q.lb, e);
+}
+
+// Gather-light form of K3 for large systems (two launches instead of one,
+// one gathered vector instead of two): K3a takes the scalars, tests and exit
+// records of K3 and forms u'' = w + beta u' and x += eta d element-wise;
+// K3b gathers u'' alone for A u'' and updates Au, v and the <r~, v>
+// partials.  Same arithmetic per element as K3.
+__global__ HZ_STREAM_BOUNDS void k_q_dir(const QArgs a) {
+    const SysBlock q = qblock(a);
+    if (q.sys < 0) return;
+    SolverScal* sc = a.sc;
+    if (sc->done || a.tq->half_exit) return;
+    const int it = sc->cur;
+    const double bnorm = sc->bnorm, rtol = sc->rtol, tau1 = a.tq->tau[1];
+    const int maxit = sc->maxiter;
+    const double2 alpha = sc->alpha, rho_old = sc->rho2[(it - 1) & 1];
+    double h[3];
+    sys_sum<3>(a.part + kPartC * a.stride, a.stride, q.gbeg, q.gcnt, h);
+    const QStep s2 = q_step(h[0], tau1, alpha);
+    const double2 rho_new = mk<double>(h[1], h[2]);
+    const double bound = __builtin_sqrt((double)(2 * it + 1)) * s2.tau / bnorm;
+    int st = -1, why = BD_NONE;
+    double2 beta = mk<double>(0.0, 0.0);
+    if (!__builtin_isfinite(bound) || !zfinite(rho_new)) st = ST_NONFINITE;
+    else if (bound <= rtol) st = ST_OK;
+    else if (it >= maxit) st = ST_NOT_CONVERGED;
+    else if (zzero(rho_old)) st = ST_BREAKDOWN, why = BD_RHO;
+    else {
+        beta = zdiv(rho_new, rho_old);
+        if (!zfinite(beta)) st = ST_NONFINITE;
+    }
+    if (st >= 0) {
+        if (st != ST_NONFINITE) HZ_FOR_ELEMS(i, q.rw) a.x[i] = cfma<double>(s2.eta, a.d[i], a.x[i]);
+        if (sys_leader(q)) {
+            sc->relres = bound;
+            a.tq->end_status = st;
+            a.tq->end_why = why;
+            a.tq->end_exit = it;
+        }
+        return;
+    }
+    if (sys_leader(q)) {
+        a.tq->tau[0] = s2.tau;
+        a.tq->theta[0] = s2.theta;
+        a.tq->eta[0] = s2.eta;
+        sc->rho2[it & 1] = rho_new;
+        sc->beta = beta;
+        sc->relres = bound;
+        sc->iter = it + 1;
+        sc->iters = it;
+    }
+    HZ_FOR_ELEMS(i, q.rw) {
+        a.x[i] = cfma<double>(s2.eta, a.d[i], a.x[i]);
+        a.u[i] = cfma<double>(beta, a.u1[i], a.w[i]);
+    }
+}
+
+template <int L, int U>
+__global__ HZ_STREAM_BOUNDS void k_q_next_light(const QArgs a) {
+    const SysBlock q = qblock(a);
+    if (q.sys < 0) return;
+    SolverScal* sc = a.sc;
+    if (sc->done || a.tq->half_exit || a.tq->end_exit) return;
+    const double2 beta = sc->beta;
+    const double2* __restrict__ u = a.u;
+    double e[2] = {0.0, 0.0};
+    for_rows<double, L, U>(q.rw, a.row_ptr, a.col_idx, a.vals, [u](int c) { return u[c]; },
+                           [&](int64_t row, double2 acc) {
+                               a.au[row] = acc;
+                               const double2 inner = cfma<double>(beta, a.v[row], a.au1[row]);
+                               const double2 vv = cfma<double>(beta, inner, acc);
+                               a.v[row] = vv;
+                               const double2 t = a.rt[row];
+                               const double2 c = cdotacc(t.x, t.y, vv.x, vv.y, mk<double>(e[0], e[1]));
+                               e[0] = c.x;
+                               e[1] = c.y;
+                           });
     store_sys_partials<2>(a.part + kPartA * a.stride, a.stride, q.lb, e);
 }
 

@@ -181,3 +181,25 @@ def test_deterministic_and_graph_replays_equal_direct_launches(hz):
         assert ig == ie
         assert np.array_equal(xg.cpu().numpy().view(np.float64), xe.view(np.float64))
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_gather_light_equals_fused(hz, jacobi):
+    """Above about 1e5 rows the third launch splits in two (one gathered vector): same arithmetic, same bits."""
+    A, b, _ = W.config_cylinder(h=0.1)
+    rp, ci, v, bd = dev(A.row_ptr), dev(A.col_idx), dev(A.vals), dev(b)
+    flags = (hz.PRECOND_JACOBI if jacobi else hz.PRECOND_NONE) | hz.X0_ZERO | hz.NO_REORDER
+    out = {}
+    for fused in ("1", "0"):
+        os.environ["HZ_FUSED"] = fused
+        try:
+            for maxiter in (7, 5000):
+                x, info = hz.ztfqmr_solve(rp, ci, v, bd, rtol=1e-10, maxiter=maxiter, flags=flags)
+                out[fused, maxiter] = (x.cpu().numpy(), info)
+        finally:
+            del os.environ["HZ_FUSED"]
+    for maxiter in (7, 5000):
+        (x1, i1), (x0, i0) = out["1", maxiter], out["0", maxiter]
+        assert i1 == i0
+        assert np.array_equal(x1.view(np.float64), x0.view(np.float64))
+    assert out["0", 5000][1]["status"] == hz.OK
