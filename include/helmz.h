@@ -276,8 +276,11 @@ int ztfqmr_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const int 
  * column arrays.  1 <= C <= 1024, t in {1, 2, 4, 8}, sigma = 1 or a
  * multiple of C.
  * csr_to_sell: fills sell_col / sell_val (slots entries) from CSR, perm and
- * chunk_ptr; HZ_ERR_INVALID if they do not fit the matrix or slots.
- * sell_zspmv: y = A x; y[perm[p]] receives sorted row p's sum.
+ * chunk_ptr; HZ_ERR_INVALID if they do not fit the matrix or slots.  C and t
+ * must be those of the csr_sell_analyze call that wrote perm and chunk_ptr
+ * (chunk_ptr is read at ceil(n/C) + 1 entries).
+ * sell_zspmv: y = A x; y[perm[p]] receives sorted row p's sum (C and t as
+ * for csr_to_sell).
  */
 size_t csr_format_workspace_bytes(int n);
 int csr_row_stats(hz_handle *handle, hz_stream stream, int n, const int *row_ptr, void *ws, size_t ws_bytes,
