@@ -271,9 +271,64 @@ def blas1(hz, torch, dev, sizes=(100_000, 209_777, 1_000_000, 5_000_000, 15_000_
             torch.cuda.synchronize()
             us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
             row[name] = {"us": round(us, 2), "GBs": round(nbytes / (us * 1e-6) / 1e9, 1)}
+        if n == 209_777:
+            row["in_graph"] = blas1_in_graph(hz, torch, x, y, d, nr, ev)
         out.append(row)
         del x, y
     return out
+
+
+def blas1_in_graph(hz, torch, x, y, d, nr, ev, calls=20, replays=5):
+    """Per-call time of zdotc / dznrm2 / zaxpy captured `calls` times in one CUDA graph, replayed `replays` times.
+
+    These kernels record no memset nodes; every replay's dot and norm are checked against the eager result (the
+    zaxpy graph is checked once, against the same calls run eagerly on a copy of y).
+    """
+    n = x.numel()
+    res = {}
+    ref_d = hz.zdotc(x, y, out=torch.empty_like(d)).item()
+    ref_n = hz.dznrm2(x, out=torch.empty_like(nr)).item()
+    for name, fn, nbytes, check in (
+        ("zdotc", lambda: hz.zdotc(x, y, out=d), 32 * n, lambda: d.item() == ref_d),
+        ("dznrm2", lambda: hz.dznrm2(x, out=nr), 16 * n, lambda: nr.item() == ref_n),
+        ("zaxpy", lambda: hz.zaxpy(1e-9 - 1e-9j, x, y), 48 * n, None),
+    ):
+        y0 = y.clone()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(calls):
+                fn()
+        torch.cuda.synchronize()
+        ok = True
+        if name == "zaxpy":
+            y.copy_(y0)
+            yy = y0.clone()
+            for _ in range(calls):
+                hz.zaxpy(1e-9 - 1e-9j, x, yy)
+            g.replay()
+            torch.cuda.synchronize()
+            ok = bool(torch.equal(y, yy))
+        ev[0].record()
+        for _ in range(replays):
+            g.replay()
+        ev[1].record()
+        torch.cuda.synchronize()
+        if check is not None:
+            for _ in range(replays):
+                g.replay()
+                torch.cuda.synchronize()
+                ok = ok and check()
+        us = ev[0].elapsed_time(ev[1]) * 1e3 / (calls * replays)
+        res[name] = {"us": round(us, 2), "GBs": round(nbytes / (us * 1e-6) / 1e9, 1), "replays_match_eager": ok}
+        y.copy_(y0)
+        del g
+    return res
 
 
 def batched_sweep(hz, torch, dev, B=64, tol=1e-10):
