@@ -253,8 +253,13 @@ __device__ __forceinline__ RowRange rows_of_block(int n, Geom geo) {
 // sum_p vals_p * op(col_p) over one row, computed by L lanes: lane l takes
 // entries beg+l, beg+l+L, ...; each lane issues U (col, value) loads, then U
 // operand gathers, then U complex FMAs, so U independent loads of each kind
-// are in flight per lane.  Returns the lane's partial (the caller sums the
-// group).  Entry order per lane is sequential, so results are deterministic.
+// are in flight per lane.  The loads are straight-line: an entry past the
+// row's end is read at the row's last entry (in bounds, since the loop runs
+// only while base < end) and its product is dropped by selects on the
+// accumulator, so no load is exec-masked (a masked load makes the compiler
+// wait for every load in flight).  Returns the lane's partial (the caller
+// sums the group).  Entry order per lane is sequential, so results are
+// deterministic.
 template <typename T, int L, int U, typename Op>
 __device__ __forceinline__ cx<T> row_partial(int beg, int end, int lane, const int* __restrict__ ci,
                                              const cx<T>* __restrict__ vals, Op op) {
@@ -264,20 +269,19 @@ __device__ __forceinline__ cx<T> row_partial(int beg, int end, int lane, const i
         cx<T> a[U], o[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int p = base + u * L;
-            if (p < end) {
-                c[u] = ci[p];
-                a[u] = vals[p];
-            } else {
-                c[u] = -1;
-                a[u] = mk<T>(T(0), T(0));
-            }
+            const int p = base + u * L < end ? base + u * L : end - 1;
+            c[u] = ci[p];
+            a[u] = vals[p];
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) o[u] = c[u] >= 0 ? op(c[u]) : mk<T>(T(0), T(0));
+        for (int u = 0; u < U; ++u) o[u] = op(c[u]);
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (c[u] >= 0) acc = cfma<T>(a[u], o[u], acc);
+        for (int u = 0; u < U; ++u) {
+            const bool in = base + u * L < end;
+            const cx<T> nx = cfma<T>(a[u], o[u], acc);
+            acc.x = in ? nx.x : acc.x;
+            acc.y = in ? nx.y : acc.y;
+        }
     }
     return acc;
 }
