@@ -163,13 +163,14 @@ __global__ HZ_STREAM_BOUNDS void k_q_even(const QArgs a) {
     if (q.sys < 0) return;
     SolverScal* sc = a.sc;
     if (sc->done || q_conclude(a, sys_leader(q))) return;
+    double h[2];
+    sys_sum<2>(a.part + kPartA * a.stride, a.stride, q.gbeg, q.gcnt, h);
+    const double2 sigma = mk<double>(h[0], h[1]);
+    // the scalars are read after the reduction: held across it they spilled under the 64-register cap
     const int it = sc->iter;
     const double2 rho = sc->rho2[(it - 1) & 1];
     const double theta = a.tq->theta[0];
     const double2 eta = a.tq->eta[0];
-    double h[2];
-    sys_sum<2>(a.part + kPartA * a.stride, a.stride, q.gbeg, q.gcnt, h);
-    const double2 sigma = mk<double>(h[0], h[1]);
     int st = -1, why = BD_NONE;
     double2 alpha = mk<double>(0.0, 0.0);
     if (!zfinite(sigma) || !zfinite(rho)) st = ST_NONFINITE;
