@@ -67,7 +67,8 @@ enum {
 
 typedef struct {
     int status;              /* HZ_OK / HZ_NOT_CONVERGED / HZ_BREAKDOWN / HZ_NONFINITE */
-    int iterations;          /* BiCGStab iterations (inner total for mixed) */
+    int iterations;          /* iterations: BiCGStab's (inner total for mixed),
+                                BiCGstab(l)'s cycles, TFQMR's full iterations */
     int outer_steps;         /* refinement corrections (mixed only)         */
     int renumbered;          /* 1 if solved in the level-set numbering      */
     double relres_recursive; /* last ||r||/||b|| of the recursive residual  */
