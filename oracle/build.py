@@ -3,6 +3,11 @@
 Test infrastructure only.  Flags: -O2 -ffp-contract=off (no fused
 multiply-add, so the oracle rounds exactly as its source reads), no
 -ffast-math, no OpenMP.
+
+A second library, ``oracle/liboracle_omp.so``, is the complex128 part of the
+same source built with -fopenmp -DOR_OMP (threaded row and element-wise
+loops, per-thread sums): it is used only to time the oracle on all host
+cores.
 """
 
 from __future__ import annotations
@@ -14,6 +19,7 @@ import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 SOURCES = ["krylov.c", "refine.c", "oracle.h"]
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-std=c11", "-Wall", "-Wextra", "-Wno-unused-function"]
 
@@ -37,13 +43,22 @@ def build(verbose: bool = False) -> str:
         tmp_lib = LIB + ".tmp"
         subprocess.run([cc, "-shared", "-o", tmp_lib, *objs, "-lm"], check=True)
         os.replace(tmp_lib, LIB)
+        out = os.path.join(tmp, "krylov_omp.o")
+        cmd = [cc, *CFLAGS, "-fopenmp", "-DOR_OMP", "-DOR_REAL=double", "-DOR_PFX=z", "-c",
+               os.path.join(HERE, "krylov.c"), "-o", out]
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.run(cmd, check=True)
+        tmp_lib = LIB_OMP + ".tmp"
+        subprocess.run([cc, "-shared", "-fopenmp", "-o", tmp_lib, out, "-lm"], check=True)
+        os.replace(tmp_lib, LIB_OMP)
     return LIB
 
 
 def stale() -> bool:
-    if not os.path.exists(LIB):
+    if not (os.path.exists(LIB) and os.path.exists(LIB_OMP)):
         return True
-    t = os.path.getmtime(LIB)
+    t = min(os.path.getmtime(LIB), os.path.getmtime(LIB_OMP))
     return any(os.path.getmtime(os.path.join(HERE, s)) > t for s in SOURCES)
 
 

@@ -14,6 +14,13 @@
  *
  * Complex numbers are pairs (re, im) with no padding, the memory layout of
  * the paper's complex structure (Section 4).
+ *
+ * A third build (OR_OMP, complex128 only, -fopenmp) exists only to time the
+ * oracle on all host cores: it splits the row loop of the product and the
+ * element-wise loops across threads, which changes no result, and lets
+ * OpenMP sum the dot products and norms per thread, which changes their
+ * rounding order.  Tests check the sequential build; the threaded one is
+ * checked against it.
  */
 #include <math.h>
 #include <stddef.h>
@@ -30,6 +37,16 @@
 #include "oracle.h"
 
 typedef OR_REAL real;
+
+#ifdef OR_OMP
+#define OR_PAR_FOR _Pragma("omp parallel for schedule(static)")
+#define OR_PAR_SUM2 _Pragma("omp parallel for schedule(static) reduction(+ : ar, ai)")
+#define OR_PAR_SUM1 _Pragma("omp parallel for schedule(static) reduction(+ : acc)")
+#else
+#define OR_PAR_FOR
+#define OR_PAR_SUM2
+#define OR_PAR_SUM1
+#endif
 
 /* ---- scalar complex arithmetic (textbook formulas, no FMA) ---- */
 static CPLX cmk(real re, real im) { CPLX z; z.re = re; z.im = im; return z; }
@@ -53,6 +70,7 @@ static int czero(CPLX a) { return a.re == 0 && a.im == 0; }
  */
 void FN(spmv)(int n, const int *row_ptr, const int *col_idx, const CPLX *vals, const CPLX *x, CPLX *y)
 {
+    OR_PAR_FOR
     for (int i = 0; i < n; ++i) {
         CPLX acc = cmk(0, 0);
         for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
@@ -64,16 +82,21 @@ void FN(spmv)(int n, const int *row_ptr, const int *col_idx, const CPLX *vals, c
 /* Dot product (Section 5) with the first argument conjugated: sum conj(x_i) y_i. */
 CPLX FN(dotc)(int n, const CPLX *x, const CPLX *y)
 {
-    CPLX acc = cmk(0, 0);
-    for (int i = 0; i < n; ++i)
-        acc = cadd(acc, cmulc(x[i], y[i]));
-    return acc;
+    real ar = 0, ai = 0;
+    OR_PAR_SUM2
+    for (int i = 0; i < n; ++i) {
+        CPLX t = cmulc(x[i], y[i]);
+        ar += t.re;
+        ai += t.im;
+    }
+    return cmk(ar, ai);
 }
 
 /* Euclidean norm (Section 5, NormL2): sqrt(sum re^2 + im^2). */
 real FN(nrm2)(int n, const CPLX *x)
 {
     real acc = 0;
+    OR_PAR_SUM1
     for (int i = 0; i < n; ++i)
         acc += x[i].re * x[i].re + x[i].im * x[i].im;
     return sqrt(acc);
@@ -82,6 +105,7 @@ real FN(nrm2)(int n, const CPLX *x)
 /* y <- alpha x + y (Section 5, the complex axpy). */
 void FN(axpy)(int n, CPLX alpha, const CPLX *x, CPLX *y)
 {
+    OR_PAR_FOR
     for (int i = 0; i < n; ++i)
         y[i] = cadd(cmul(alpha, x[i]), y[i]);
 }
@@ -89,6 +113,7 @@ void FN(axpy)(int n, CPLX alpha, const CPLX *x, CPLX *y)
 /* y <- alpha x (Section 5, scale). */
 void FN(scal)(int n, CPLX alpha, CPLX *x)
 {
+    OR_PAR_FOR
     for (int i = 0; i < n; ++i)
         x[i] = cmul(alpha, x[i]);
 }
@@ -96,6 +121,7 @@ void FN(scal)(int n, CPLX alpha, CPLX *x)
 /* y_i <- x_i * y_i (Section 5, element-wise product). */
 void FN(xmy)(int n, const CPLX *x, CPLX *y)
 {
+    OR_PAR_FOR
     for (int i = 0; i < n; ++i)
         y[i] = cmul(x[i], y[i]);
 }
@@ -107,6 +133,7 @@ static void apply_prec(int n, const CPLX *dinv, const CPLX *w, CPLX *z)
         memcpy(z, w, sizeof(CPLX) * (size_t)n);
         return;
     }
+    OR_PAR_FOR
     for (int i = 0; i < n; ++i)
         z[i] = cmul(dinv[i], w[i]);
 }
@@ -161,6 +188,7 @@ int FN(bicgstab)(int n, const int *row_ptr, const int *col_idx, const CPLX *vals
     }
     /* r = b - A x ; rhat = r */
     FN(spmv)(n, row_ptr, col_idx, vals, x, r);
+    OR_PAR_FOR
     for (int i = 0; i < n; ++i)
         r[i] = csub(b[i], r[i]);
     memcpy(rhat, r, sizeof(CPLX) * (size_t)n);
@@ -183,6 +211,7 @@ int FN(bicgstab)(int n, const int *row_ptr, const int *col_idx, const CPLX *vals
         } else {
             CPLX beta = cmul(cdiv(rho, rho_prev), cdiv(alpha, omega));
             if (!cfinite(beta)) { status = OR_NONFINITE; break; }
+            OR_PAR_FOR
             for (int i = 0; i < n; ++i)
                 p[i] = cadd(r[i], cmul(beta, csub(p[i], cmul(omega, v[i]))));
         }
@@ -192,11 +221,13 @@ int FN(bicgstab)(int n, const int *row_ptr, const int *col_idx, const CPLX *vals
         if (!cfinite(sigma)) { status = OR_NONFINITE; break; }
         if (czero(sigma)) { status = OR_BREAKDOWN; break; }
         alpha = cdiv(rho, sigma);
+        OR_PAR_FOR
         for (int i = 0; i < n; ++i)
             s[i] = csub(r[i], cmul(alpha, v[i]));
         resid = FN(nrm2)(n, s) / bn;
         if (!isfinite(resid)) { status = OR_NONFINITE; break; }
         if (resid <= tol) {
+            OR_PAR_FOR
             for (int i = 0; i < n; ++i)
                 x[i] = cadd(x[i], cmul(alpha, phat[i]));
             status = OR_OK;
@@ -209,6 +240,7 @@ int FN(bicgstab)(int n, const int *row_ptr, const int *col_idx, const CPLX *vals
         if (czero(tt)) { status = OR_BREAKDOWN; break; }
         omega = cdiv(FN(dotc)(n, t, s), tt);
         if (!cfinite(omega)) { status = OR_NONFINITE; break; }
+        OR_PAR_FOR
         for (int i = 0; i < n; ++i) {
             x[i] = cadd(cadd(x[i], cmul(alpha, phat[i])), cmul(omega, shat[i]));
             r[i] = csub(s[i], cmul(omega, t[i]));
@@ -226,6 +258,7 @@ int FN(bicgstab)(int n, const int *row_ptr, const int *col_idx, const CPLX *vals
     info->relres_recursive = resid;
     /* true residual ||b - A x|| / ||b|| in this instantiation's precision */
     FN(spmv)(n, row_ptr, col_idx, vals, x, t);
+    OR_PAR_FOR
     for (int i = 0; i < n; ++i)
         t[i] = csub(b[i], t[i]);
     info->relres_true = FN(nrm2)(n, t) / bn;

@@ -237,7 +237,57 @@ def dense_solve(A, b) -> np.ndarray:
 
 
 def threads_used() -> int:
+    """Threads of the sequential oracle (the functions above)."""
     return 1
+
+
+# ---------------------------------------------------------------- threaded build (timing only)
+
+_omp = None
+
+
+def omp_lib():
+    """The OpenMP build of the complex128 oracle (liboracle_omp.so), for timing on all host cores."""
+    global _omp
+    if _omp is None:
+        lib()  # builds both libraries when stale
+        L = C.CDLL(_build.LIB_OMP)
+        P = C.c_void_p
+        L.or_zspmv.argtypes = [C.c_int, P, P, P, P, P]
+        L.or_zbicgstab_work_elems.argtypes = [C.c_int]
+        L.or_zbicgstab_work_elems.restype = C.c_size_t
+        L.or_zbicgstab.argtypes = [C.c_int, P, P, P, P, P, C.c_double, C.c_int, C.c_int, C.c_int, P, C.POINTER(_Info)]
+        L.or_zbicgstab.restype = C.c_int
+        _omp = L
+    return _omp
+
+
+def omp_threads() -> int:
+    """Threads the OpenMP build runs with (OMP_NUM_THREADS, else the affinity cores)."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return int(env) if env.isdigit() and int(env) > 0 else affinity_cores()
+
+
+def zspmv_omp(A, x: np.ndarray) -> np.ndarray:
+    """y = A x by the threaded build (rows split across threads; every row sums as in zspmv)."""
+    rp, ci, v = _csr(A)
+    x = np.ascontiguousarray(x, dtype=np.complex128)
+    y = np.empty(A.n, dtype=np.complex128)
+    omp_lib().or_zspmv(A.n, _p(rp), _p(ci), _p(v), _p(x), _p(y))
+    return y
+
+
+def zbicgstab_omp(A, b, x0=None, tol=1e-8, maxiter=20000, jacobi=False):
+    """zbicgstab by the threaded build: the same algorithm, dot products summed per thread."""
+    rp, ci, v = _csr(A)
+    b = np.ascontiguousarray(b, dtype=np.complex128)
+    x = np.zeros(A.n, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    L = omp_lib()
+    work = np.empty(L.or_zbicgstab_work_elems(A.n), dtype=np.complex128)
+    info = _Info()
+    L.or_zbicgstab(A.n, _p(rp), _p(ci), _p(v), _p(b), _p(x), float(tol), int(maxiter), int(bool(jacobi)),
+                   int(x0 is None), _p(work), C.byref(info))
+    return x, info.as_dict()
 
 
 def cpu_model() -> str:
