@@ -2,7 +2,7 @@
 
 Only ``tests/``, the package smoke check and the CPU-baseline leg of
 ``bench.py`` may import this module.  The paper runs a preconditioned
-BiCGSTAB(l) with l = 8 beside P-BiCGSTAB (Section 6, iterative Krylov
+BiCGSTAB(l) with l = 8 beside P-BiCGSTAB (Section 7, iterative Krylov
 methods, and its speed-up tables for Audi3D, Twingo3D and Cylinder3D) without
 printing the algorithm; this is the method of Sleijpen and Fokkema (1993),
 written from its published steps in complex128:

@@ -3,7 +3,7 @@
 Only ``tests/``, the package smoke check and the CPU-baseline leg of
 ``bench.py`` may import this module.  The paper runs a preconditioned
 transpose-free QMR (P-TFQMR; "P-QMR" in its Cylinder3D table) beside
-P-BiCGSTAB, citing Saad's book for its solvers (Section 6, iterative Krylov
+P-BiCGSTAB, citing Saad's book for its solvers (Section 7, iterative Krylov
 methods, and its speed-up tables), without printing the algorithm.  This is
 Freund's TFQMR in the form of Saad's "Iterative methods for sparse linear
 systems", written from its steps in complex128, with half steps m = 0, 1, ...:

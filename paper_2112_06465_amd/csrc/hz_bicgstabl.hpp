@@ -1,4 +1,4 @@
-// BiCGstab(l): the paper's P-BiCGSTAB(l) (Section 6, iterative Krylov
+// BiCGstab(l): the paper's P-BiCGSTAB(l) (Section 7, iterative Krylov
 // methods; l = 8 in its speed-up tables), in the form of Sleijpen and
 // Fokkema.  One system, on the one-system work map of the BiCGStab kernels
 // and with the same device scalars (SolverScal) and partial regions.

@@ -1,4 +1,4 @@
-// TFQMR: the paper's P-TFQMR (Section 6, iterative Krylov methods), Freund's
+// TFQMR: the paper's P-TFQMR (Section 7, iterative Krylov methods), Freund's
 // transpose-free QMR in the form of Saad's book.  One system, on the
 // one-system work map of the BiCGStab kernels, their device scalars
 // (SolverScal: rho, alpha, bnorm, rtol, status ...) and partial regions.
