@@ -195,9 +195,10 @@ int zbicgstab_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const i
  * it.  b, x, ws and info_dev must stay valid until then.  One system, FP64,
  * caller's numbering: HZ_REORDER, HZ_VALIDATE and HZ_RELIABLE are invalid,
  * renumbering never happens (workspace as for zbicgstab_solve with
- * HZ_NO_REORDER).  The first call for a matrix size uploads its launch map
- * to a copy kept by the handle (one synchronisation); later calls only
- * enqueue.  A zero diagonal under Jacobi is reported as info_dev->status =
+ * HZ_NO_REORDER).  The launch map is written into ws by a kernel, so the
+ * call allocates nothing and never waits; iteration graphs cached by the
+ * handle are evicted only after their last launch has completed.  A zero
+ * diagonal under Jacobi is reported as info_dev->status =
  * HZ_ERR_INVALID.  Returns HZ_OK once enqueued, or an argument error.
  */
 int zbicgstab_solve_async(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
@@ -205,7 +206,7 @@ int zbicgstab_solve_async(hz_handle *handle, hz_stream stream, int n, int nnz, c
                           void *ws, size_t ws_bytes, hz_solve_info *info_dev);
 
 /*
- * BiCGstab(l), the paper's P-BiCGSTAB(l) (Section 6, iterative Krylov
+ * BiCGstab(l), the paper's P-BiCGSTAB(l) (Section 7, iterative Krylov
  * methods; l = 8 in its speed-up tables), in Sleijpen and Fokkema's form:
  * each cycle makes l Bi-CG steps, then takes the coefficients that minimise
  * ||r_0 - sum_j gamma_j r_j||_2 over its residual basis r_1 .. r_l (normal
@@ -225,7 +226,7 @@ int zbicgstabl_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const 
                      int flags, void *ws, size_t ws_bytes, hz_solve_info *info);
 
 /*
- * TFQMR, the paper's P-TFQMR (Section 6, iterative Krylov methods): Freund's
+ * TFQMR, the paper's P-TFQMR (Section 7, iterative Krylov methods): Freund's
  * transpose-free QMR in the form of Saad's book, two products per iteration,
  * right Jacobi preconditioning as for zbicgstab_solve.  The stopping test is
  * the quasi-residual bound sqrt(m + 2) tau_{m+1} <= rtol ||b|| after every
@@ -487,6 +488,22 @@ int csr_level_order(hz_handle *handle, hz_stream stream, int n, int nnz, const i
 int csr_zpermute(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
                  const hz_c128 *vals, const int *perm, const int *inv, int *row_ptr_out, int *col_idx_out,
                  hz_c128 *vals_out, void *ws, size_t ws_bytes);
+
+/*
+ * Memory-bandwidth calibration (measurement only; the paper repeats every
+ * operation and averages its time, Section 3.3, and these give the ceiling
+ * that the bandwidth-bound kernels above are compared against on the same
+ * part).  hz_stream_read reads `bytes` bytes of buf (device, 16-byte aligned,
+ * bytes a multiple of 16) as doubles, each thread keeping eight independent
+ * 16-byte loads in flight, and writes their sum, in a fixed order, to *out
+ * (device double).  hz_stream_copy copies `bytes` bytes from src to dst
+ * (device, 16-byte aligned, not overlapping) the same way.  Both enqueue on
+ * the stream and return HZ_ERR_INVALID for bad pointers or sizes.  The read
+ * uses the handle's partial-sum buffer: calls on one handle must not
+ * overlap.
+ */
+int hz_stream_read(hz_handle *handle, hz_stream stream, const void *buf, size_t bytes, double *out);
+int hz_stream_copy(hz_handle *handle, hz_stream stream, const void *src, void *dst, size_t bytes);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,7 @@
 #include "hz_bicgstabl.hpp"
 #include "hz_tfqmr.hpp"
 #include "hz_formats.hpp"
+#include "hz_stream.hpp"
 
 using hz::cx;
 using hz::Geom;
@@ -52,15 +53,13 @@ struct TuneEntry {
 
 // An instantiated graph of one chunk of solver iterations, keyed by the
 // kernel family, lane count, chunk length and the kernels' argument bytes.
+// `last` is recorded on the launch stream after every launch of the graph, so
+// evicting it can first wait for a launch that may still be queued (the
+// asynchronous solve enqueues chunks without waiting).
 struct GraphEntry {
     std::vector<unsigned char> key;
     hipGraphExec_t exec;
-};
-
-// A single-system work map kept on the device: blocks then the system entry.
-struct MapEntry {
-    int n, L;
-    void* dev;
+    hipEvent_t last;
 };
 
 struct hz_handle {
@@ -75,7 +74,6 @@ struct hz_handle {
     int* hflag;            // pinned host word
     SolverScal* hsc;       // pinned host copy of the solver scalars
     SolverScal* hsc2;      // pinned host copy of the refinement's outer scalars
-    std::vector<MapEntry> maps;  // device copies of single-system work maps (the asynchronous solve)
 };
 
 namespace {
@@ -123,27 +121,41 @@ std::vector<unsigned char> chunk_key(int family, int lanes, int k, int tail, con
 // handle's capture stream, instantiated and cached under `key`; later chunks
 // with the same key replay it with one hipGraphLaunch.  With HZ_NO_GRAPH=1,
 // or if capture or instantiation fails, the kernels are launched directly.
-// Every caller synchronises s before the next chunk, so no cached graph is
-// in flight when one is evicted.
+// The cache keeps kMaxGraphs graphs; the oldest is evicted only after its
+// last launch has completed (its event), since the asynchronous solve leaves
+// chunks queued on the caller's stream.
+int graph_launch(GraphEntry& g, hipStream_t s) {
+    if (hipGraphLaunch(g.exec, s) != hipSuccess) return HZ_ERR_HIP;
+    return hipEventRecord(g.last, s) == hipSuccess ? HZ_OK : HZ_ERR_HIP;
+}
+
+void graph_release(GraphEntry& g) {
+    (void)hipEventSynchronize(g.last);
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipEventDestroy(g.last);
+}
+
 template <typename F>
 int launch_chunk(hz_handle* h, hipStream_t s, const std::vector<unsigned char>& key, F&& record) {
     if (graphs_on() && h->cap != nullptr) {
-        for (const GraphEntry& g : h->graphs)
-            if (g.key == key) return hipGraphLaunch(g.exec, s) == hipSuccess ? HZ_OK : HZ_ERR_HIP;
+        for (GraphEntry& g : h->graphs)
+            if (g.key == key) return graph_launch(g, s);
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
+        hipEvent_t last = nullptr;
         if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
             record(h->cap);
             hipError_t e = hipStreamEndCapture(h->cap, &graph);
             if (e == hipSuccess && graph != nullptr) e = hipGraphInstantiateWithFlags(&exec, graph, 0);
             if (graph != nullptr) (void)hipGraphDestroy(graph);
-            if (e == hipSuccess && exec != nullptr) {
+            if (e == hipSuccess && exec != nullptr) e = hipEventCreateWithFlags(&last, hipEventDisableTiming);
+            if (e == hipSuccess && exec != nullptr && last != nullptr) {
                 if (h->graphs.size() >= kMaxGraphs) {
-                    (void)hipGraphExecDestroy(h->graphs.front().exec);
+                    graph_release(h->graphs.front());
                     h->graphs.erase(h->graphs.begin());
                 }
-                h->graphs.push_back(GraphEntry{key, exec});
-                return hipGraphLaunch(exec, s) == hipSuccess ? HZ_OK : HZ_ERR_HIP;
+                h->graphs.push_back(GraphEntry{key, exec, last});
+                return graph_launch(h->graphs.back(), s);
             }
             if (exec != nullptr) (void)hipGraphExecDestroy(exec);
         }
@@ -518,24 +530,27 @@ int iterate(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>
     return HZ_OK;
 }
 
-// The single-system map for (n, L) copied device to device from the handle's
-// cache (uploaded, with one synchronisation, the first time): no host wait
-// on the caller's stream afterwards.
-int upload_map_cached(hz_handle* h, hipStream_t s, int n, int L, const WorkMap& m, const SolveWs& w) {
-    const size_t nb = sizeof(BlockMap) * m.blocks.size(), ns = sizeof(SysMap) * m.systems.size();
-    void* dev = nullptr;
-    for (const MapEntry& e : h->maps)
-        if (e.n == n && e.L == L) dev = e.dev;
-    if (dev == nullptr) {
-        HZ_HIP(hipMalloc(&dev, nb + ns));
-        h->maps.push_back(MapEntry{n, L, dev});
-        HZ_HIP(hipMemcpy(dev, m.blocks.data(), nb, hipMemcpyHostToDevice));
-        HZ_HIP(hipMemcpy(static_cast<char*>(dev) + nb, m.systems.data(), ns, hipMemcpyHostToDevice));
+// The single-system map of build_map(1, {0, n}, L) written by a kernel into
+// the workspace (the asynchronous solve: no host buffer has to outlive the
+// call, nothing is allocated and nothing waits), and the done-counter zeroed.
+__global__ void k_map_one(BlockMap* bm, SysMap* sm, int* ndone, int n, int G, int groups, int K) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < G) {
+        const int x = b / K;
+        const int64_t x0 = int64_t(n) * x / groups, x1 = int64_t(n) * (x + 1) / groups;
+        bm[b] = BlockMap{0, int(x0), int(x1), b % K, K, b};
     }
-    HZ_HIP(hipMemcpyAsync(w.bmap, dev, nb, hipMemcpyDeviceToDevice, s));
-    HZ_HIP(hipMemcpyAsync(w.smap, static_cast<char*>(dev) + nb, ns, hipMemcpyDeviceToDevice, s));
-    HZ_HIP(hipMemsetAsync(w.ndone, 0, sizeof(int), s));
-    return HZ_OK;
+    if (b == 0) {
+        sm[0] = SysMap{0, G, 0, n};
+        *ndone = 0;
+    }
+}
+
+int write_map_one(hipStream_t s, int n, const WorkMap& m, const SolveWs& w) {
+    const int groups = (m.G % hz::kXcd == 0) ? hz::kXcd : 1, K = m.G / groups;
+    hipLaunchKernelGGL(k_map_one, dim3((m.G + 255) / 256), dim3(256), 0, s, w.bmap, w.smap, w.ndone, n, m.G, groups,
+                       K);
+    return hipGetLastError() == hipSuccess ? HZ_OK : HZ_ERR_HIP;
 }
 
 // hz_solve_info of system 0 from its device scalars (asynchronous solve).
@@ -574,7 +589,7 @@ int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nn
     const WorkMap m = build_map(nsys, row_off, L);
     SolveWs w;
     ws_layout<double>(n, nnz, jacobi, nsys, m.G, ws, &w);
-    int rc = async ? upload_map_cached(h, s, n, L, m, w) : upload_map(s, m, w);
+    int rc = async ? write_map_one(s, n, m, w) : upload_map(s, m, w);
     if (rc) return rc;
     double2* r = static_cast<double2*>(w.vec[0]);
     double2* t = static_cast<double2*>(w.vec[7]);
@@ -2004,8 +2019,7 @@ int hz_handle_destroy(hz_handle* h) {
     if (h->hflag) (void)hipHostFree(h->hflag);
     if (h->hsc) (void)hipHostFree(h->hsc);
     if (h->hsc2) (void)hipHostFree(h->hsc2);
-    for (const GraphEntry& g : h->graphs) (void)hipGraphExecDestroy(g.exec);
-    for (const MapEntry& e : h->maps) (void)hipFree(e.dev);
+    for (GraphEntry& g : h->graphs) graph_release(g);
     if (h->cap) (void)hipStreamDestroy(h->cap);
     delete h;
     return HZ_OK;
@@ -2163,6 +2177,31 @@ int zaxpy(hz_handle* h, hz_stream stream, int n, hz_c128 alpha, const hz_c128* x
     if (blocks > 8 * kMaxGrid) blocks = 8 * kMaxGrid;
     hipLaunchKernelGGL(hz::k_zaxpy, dim3(unsigned(blocks)), dim3(kBlock), 0, s, int64_t(n), a,
                        reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+int hz_stream_read(hz_handle* h, hz_stream stream, const void* buf, size_t bytes, double* out) {
+    if (h == nullptr || out == nullptr || bytes % 16 != 0 || (bytes > 0 && buf == nullptr)) return HZ_ERR_INVALID;
+    if (misaligned(buf, 16) || misaligned(out, 8)) return HZ_ERR_INVALID;
+    static_assert(hz::kStreamGrid <= kParts * kMaxGrid, "partials of the stream read fit the handle's buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(hz::k_stream_read, dim3(hz::kStreamGrid), dim3(hz::kStreamBlock), 0, s,
+                       static_cast<const double2*>(buf), int64_t(bytes / 16), h->part);
+    hipLaunchKernelGGL(hz::k_stream_fin, dim3(1), dim3(hz::kStreamBlock), 0, s, static_cast<const double*>(h->part),
+                       hz::kStreamGrid, out);
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
+}
+
+int hz_stream_copy(hz_handle* h, hz_stream stream, const void* src, void* dst, size_t bytes) {
+    if (h == nullptr || bytes % 16 != 0) return HZ_ERR_INVALID;
+    if (bytes == 0) return HZ_OK;
+    if (src == nullptr || dst == nullptr || misaligned(src, 16) || misaligned(dst, 16)) return HZ_ERR_INVALID;
+    if (overlap(src, bytes, dst, bytes)) return HZ_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(hz::k_stream_copy, dim3(hz::kStreamGrid), dim3(hz::kStreamBlock), 0, s,
+                       static_cast<const double2*>(src), int64_t(bytes / 16), static_cast<double2*>(dst));
     HZ_HIP(hipGetLastError());
     return HZ_OK;
 }

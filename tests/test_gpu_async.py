@@ -78,3 +78,22 @@ def test_iteration_limit_zero_diagonal_and_invalid(hz):
     for bad in (hz.REORDER, hz.VALIDATE, hz.RELIABLE):
         with pytest.raises(hz.HelmzError):
             hz.zbicgstab_solve_async(rp, ci, v, bd, flags=bad)
+
+
+def test_many_queued_solves_evict_graphs_safely(hz):
+    """20 solves on distinct buffers enqueued before any host wait: about 40 chunk graphs for a cache of 32, so
+    graphs are evicted while earlier chunks may still be queued.  Every solution must equal the synchronous
+    solve of the same system bit for bit."""
+    A, _, _ = W.config_cube(10, seed=3)
+    rng = np.random.default_rng(9)
+    rp, ci, v = dev(A.row_ptr), dev(A.col_idx), dev(A.vals)
+    rhs = [rng.standard_normal(A.n) + 1j * rng.standard_normal(A.n) for _ in range(20)]
+    bs = [dev(r) for r in rhs]  # kept alive: distinct buffers give distinct graph keys
+    queued = [hz.zbicgstab_solve_async(rp, ci, v, bd, rtol=1e-10, maxiter=400) for bd in bs]
+    torch.cuda.synchronize()
+    for r, (xa, info) in zip(rhs, queued):
+        xs, is_ = hz.zbicgstab_solve(rp, ci, v, dev(r), rtol=1e-10, maxiter=400, flags=hz.X0_ZERO | hz.NO_REORDER)
+        ia = hz.read_info(info)
+        assert ia == is_, (ia, is_)
+        assert np.array_equal(xa.cpu().numpy().view(np.float64), xs.cpu().numpy().view(np.float64))
+        assert ia["status"] == hz.OK and true_relres(A, xa.cpu().numpy(), r) <= 1e-10 * (1 + 1e-2)
