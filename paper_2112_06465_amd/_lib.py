@@ -88,6 +88,8 @@ SIGNATURES = {
     "zbicgstab_adjoint_batched": (I, [P, P, I, I, I, P, P, P, P, P, P, P, D, I, I, P, SZ, P]),
     "csr_level_order": (I, [P, P, I, I, P, P, P, P, P, P, SZ]),
     "csr_zpermute": (I, [P, P, I, I, P, P, P, P, P, P, P, P, P, SZ]),
+    "hz_stream_read": (I, [P, P, P, SZ, P]),
+    "hz_stream_copy": (I, [P, P, P, P, SZ]),
 }
 
 

@@ -149,6 +149,30 @@ def zdotc(x, y, out=None):
     return out
 
 
+def stream_read(buf, out=None):
+    """Sum of a device buffer's doubles by the bandwidth-calibration read (hz_stream_read)."""
+    dev = buf.device
+    if not buf.is_contiguous() or buf.numel() * buf.element_size() % 16:
+        raise ValueError("buf must be contiguous with a size that is a multiple of 16 bytes")
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=dev)
+    _need(out, "out", torch.float64, dev)
+    rc = load().hz_stream_read(handle(dev), _stream(dev), buf.data_ptr(), buf.numel() * buf.element_size(),
+                               out.data_ptr())
+    _check("hz_stream_read", rc)
+    return out
+
+
+def stream_copy(src, dst):
+    """dst <- src bytewise by the bandwidth-calibration copy (hz_stream_copy)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous buffers of one size")
+    rc = load().hz_stream_copy(handle(src.device), _stream(src.device), src.data_ptr(), dst.data_ptr(), nbytes)
+    _check("hz_stream_copy", rc)
+    return dst
+
+
 def dznrm2(x, out=None):
     """||x||_2 as a 0-d float64 GPU tensor (dznrm2)."""
     dev = x.device
