@@ -52,7 +52,8 @@ enum {
     HZ_NONFINITE = 3,     /* a NaN/Inf scalar appeared                      */
     HZ_ERR_INVALID = -1,  /* bad argument or malformed CSR (validated)      */
     HZ_ERR_HIP = -2,      /* a HIP runtime call failed                      */
-    HZ_ERR_WORKSPACE = -3 /* workspace missing, misaligned or too small     */
+    HZ_ERR_WORKSPACE = -3, /* workspace missing, misaligned or too small    */
+    HZ_ERR_TOO_LARGE = -4  /* beyond the static scratch (noalloc solve)     */
 };
 
 /* solver flags (bitwise or) */
@@ -204,6 +205,29 @@ int zbicgstab_solve(hz_handle *handle, hz_stream stream, int n, int nnz, const i
 int zbicgstab_solve_async(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
                           const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol, int maxiter, int flags,
                           void *ws, size_t ws_bytes, hz_solve_info *info_dev);
+
+/*
+ * zbicgstab_solve_noalloc: for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The solve of zbicgstab_solve_async (same kernels, same
+ * arguments and flags, same device-side info_dev) with no workspace
+ * argument: its workspace is a static device array of
+ * zbicgstab_noalloc_max_bytes() bytes (96 MiB) in the library, one per GPU,
+ * held until the process ends.  The call allocates nothing, records no
+ * memset and captures no graph (its iterations are launched directly), and
+ * never waits on the host.  Systems whose workspace (zbicgstab_workspace_bytes
+ * with HZ_NO_REORDER) exceeds the array return HZ_ERR_TOO_LARGE: that is
+ * about 780,000 rows with no preconditioner (128 bytes per row), or about
+ * 260,000 rows of 15 entries under Jacobi (the 210k-row cylinder fits).
+ * Every call on one GPU uses the same array
+ * and initialises all of it that it reads, so results do not depend on
+ * earlier calls; calls that overlap in time on one GPU (other streams, or
+ * other threads) race on it and must be serialised by the caller.
+ */
+size_t zbicgstab_noalloc_max_bytes(void);
+int zbicgstab_solve_noalloc(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr,
+                            const int *col_idx, const hz_c128 *vals, const hz_c128 *b, hz_c128 *x, double rtol,
+                            int maxiter, int flags, hz_solve_info *info_dev);
 
 /*
  * BiCGstab(l), the paper's P-BiCGSTAB(l) (Section 7, iterative Krylov

@@ -89,6 +89,8 @@ SIGNATURES = {
     "csr_level_order": (I, [P, P, I, I, P, P, P, P, P, P, SZ]),
     "csr_zpermute": (I, [P, P, I, I, P, P, P, P, P, P, P, P, P, SZ]),
     "hz_stream_read": (I, [P, P, P, SZ, P]),
+    "zbicgstab_noalloc_max_bytes": (SZ, []),
+    "zbicgstab_solve_noalloc": (I, [P, P, I, I, P, P, P, P, P, D, I, I, P]),
     "hz_stream_copy": (I, [P, P, P, P, SZ]),
 }
 

@@ -17,6 +17,7 @@ from ._lib import HelmzError, HzC128, HzInfo, load
 
 OK, NOT_CONVERGED, BREAKDOWN, NONFINITE = 0, 1, 2, 3
 ERR_WORKSPACE = -3
+ERR_TOO_LARGE = -4
 PRECOND_NONE, PRECOND_JACOBI, X0_ZERO, VALIDATE, SYMMETRIC = 0x0, 0x1, 0x4, 0x8, 0x10
 REORDER, NO_REORDER, RELIABLE = 0x20, 0x40, 0x80
 BD_NONE, BD_RHO, BD_RHAT_V, BD_TT, BD_OMEGA, BD_MR = 0, 1, 2, 3, 4, 5  # info["breakdown"]: what became 0 / singular
@@ -248,6 +249,38 @@ def zbicgstab_solve(row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxiter=20000,
 
 def zbicgstabl_workspace_bytes(n: int, nnz: int, ell: int = 8, flags: int = 0) -> int:
     return int(load().zbicgstabl_workspace_bytes(n, nnz, ell, flags))
+
+
+def zbicgstab_solve_noalloc(row_ptr, col_idx, vals, b, x=None, rtol=1e-8, maxiter=20000,
+                            flags=PRECOND_NONE | X0_ZERO, info=None):
+    """Enqueue a BiCGStab solve that allocates nothing (zbicgstab_solve_noalloc).
+
+    The library's static scratch is the workspace; x and info (a device
+    hz_solve_info, decoded by ``read_info``) are the caller's.  Pass both to
+    make the call itself free of allocations.
+    """
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    _need(b, "b", torch.complex128, dev)
+    if b.numel() != n:
+        raise ValueError("b has the wrong length")
+    if x is None:
+        x = torch.zeros(n, dtype=torch.complex128, device=dev)
+        flags |= X0_ZERO
+    _need(x, "x", torch.complex128, dev)
+    if info is None:
+        info = torch.empty(C.sizeof(HzInfo), dtype=torch.uint8, device=dev)
+    _need(info, "info", torch.uint8, dev)
+    if info.numel() < C.sizeof(HzInfo):
+        raise ValueError("info is too small")
+    rc = load().zbicgstab_solve_noalloc(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                                        vals.data_ptr(), b.data_ptr(), x.data_ptr(), float(rtol), int(maxiter),
+                                        int(flags), info.data_ptr())
+    _check("zbicgstab_solve_noalloc", rc)
+    return x, info
+
+
+def zbicgstab_noalloc_max_bytes() -> int:
+    return int(load().zbicgstab_noalloc_max_bytes())
 
 
 def zbicgstabl_solve(row_ptr, col_idx, vals, b, x=None, ell=8, rtol=1e-8, maxcycles=2500,

@@ -62,8 +62,18 @@ struct GraphEntry {
     hipEvent_t last;
 };
 
+// Static scratch of the allocation-free solve (zbicgstab_solve_noalloc): one
+// copy per GPU the library runs on, held from module load until the process
+// ends.  Host code never passes `scratch` itself to a kernel (on the host it
+// is only a stand-in symbol): it uses the device address that
+// hz_handle_create obtains with hipGetSymbolAddress, with the handle's device
+// current, and keeps in the handle.
+constexpr size_t kScratchBytes = size_t(96) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 struct hz_handle {
     int device;
+    void* scratch_dev;     // device address of `scratch` on this handle's device
     std::vector<TuneEntry> tune;  // autotuned lanes per row, newest last
     hipStream_t cap;                 // stream the iteration graphs are captured on (never runs work)
     std::vector<GraphEntry> graphs;  // cached iteration graphs, newest last
@@ -494,14 +504,19 @@ int upload_map(hipStream_t s, const WorkMap& m, const SolveWs& w) {
 // done-counter between chunks of 8, 16, ..., 64 iterations.
 template <typename T>
 int iterate(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>& a, int L, int maxiter, bool fused,
-            bool poll_done = true) {
+            bool poll_done = true, bool graphs = true) {
     const dim3 G(m.G), B(kBlock);
     int launched = 0, poll = poll_done ? 8 : 64;
     while (launched < maxiter) {
         const int k_n = (maxiter - launched) < poll ? (maxiter - launched) : poll;
         const bool tail = launched + k_n == maxiter;
         const int family = (fused ? 1 : 2) + (sizeof(T) == 4 ? 10 : 0);
-        int rc = launch_chunk(h, s, chunk_key(family, L, k_n, tail, a), [&](hipStream_t q) {
+        auto chunk = [&](auto&& record) {
+            if (graphs) return launch_chunk(h, s, chunk_key(family, L, k_n, tail, a), record);
+            record(s);  // direct launches: no graph is captured or instantiated (nothing allocated)
+            return hipGetLastError() == hipSuccess ? int(HZ_OK) : int(HZ_ERR_HIP);
+        };
+        int rc = chunk([&](hipStream_t q) {
             with_lanes(L, [&]<int LL, int UU>() {
                 for (int k = 0; k < k_n; ++k) {
                     if (fused) {
@@ -546,6 +561,13 @@ __global__ void k_map_one(BlockMap* bm, SysMap* sm, int* ndone, int n, int G, in
     }
 }
 
+// x = 0 by a kernel (the allocation-free solve records no memset, so that a
+// caller may capture it in a graph).
+__global__ void k_zero_c128(int n, double2* x) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = double2{0.0, 0.0};
+}
+
 int write_map_one(hipStream_t s, int n, const WorkMap& m, const SolveWs& w) {
     const int groups = (m.G % hz::kXcd == 0) ? hz::kXcd : 1, K = m.G / groups;
     hipLaunchKernelGGL(k_map_one, dim3((m.G + 255) / 256), dim3(256), 0, s, w.bmap, w.smap, w.ndone, n, m.G, groups,
@@ -581,8 +603,9 @@ void launch_sys_resid(int L, const WorkMap& m, const hz::BicgArgs<T>& a, const c
 // in/out; infos[j] receives system j's result.  Returns the largest status.
 int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nnz, const int* rp, const int* ci,
                const double2* A, const double2* bd, double2* xd, double rtol, int maxiter, int flags, char* ws,
-               hz_solve_info* infos, hz_solve_info* info_dev = nullptr) {
+               hz_solve_info* infos, hz_solve_info* info_dev = nullptr, bool direct = false) {
     const bool async = info_dev != nullptr;  // one system; nothing waits for the stream
+    // direct (allocation-free solve): kernels only, no memset, no graph capture
     const int n = row_off[nsys] - row_off[0];
     const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
     const int L = pick_lanes(h, rp, ci, n, nnz);
@@ -609,7 +632,10 @@ int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nn
     // initial iterate (y = D x0 under Jacobi) and residual
     const double2* rsrc = bd;
     if (flags & HZ_X0_ZERO) {
-        HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
+        if (direct)
+            hipLaunchKernelGGL(k_zero_c128, grid1(n), dim3(kBlock), 0, s, n, xd);
+        else
+            HZ_HIP(hipMemsetAsync(xd, 0, 16 * size_t(n), s));
     } else {
         if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, dinv, xd, 1);
         launch_sys_resid<double>(L, m, a, Aop, xd, r, s);
@@ -619,7 +645,7 @@ int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nn
     hipLaunchKernelGGL(hz::k_fin_init<double>, dim3(nsys), dim3(kBlock), 0, s, a);
     HZ_HIP(hipGetLastError());
     if (async) {
-        rc = iterate<double>(h, s, m, a, L, maxiter, choose_fused(h, n), false);
+        rc = iterate<double>(h, s, m, a, L, maxiter, choose_fused(h, n), false, !direct);
         if (rc) return rc;
         hipLaunchKernelGGL(hz::k_zero_if<double>, dim3(m.G), dim3(kBlock), 0, s, a);
         if (jacobi) hipLaunchKernelGGL(hz::k_diag_apply<double>, grid1(n), dim3(kBlock), 0, s, n, dinv, xd, 0);
@@ -1984,6 +2010,7 @@ const char* hz_strerror(int code) {
         case HZ_ERR_INVALID: return "invalid argument or malformed CSR";
         case HZ_ERR_HIP: return "HIP runtime error";
         case HZ_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+        case HZ_ERR_TOO_LARGE: return "system too large for the static scratch of the allocation-free solve";
         default: return "unknown helmz status";
     }
 }
@@ -2002,7 +2029,8 @@ int hz_handle_create(hz_handle** out) {
         hipHostMalloc(reinterpret_cast<void**>(&h->hflag), sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&h->hsc), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&h->hsc2), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess ||
-        hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipGetSymbolAddress(&h->scratch_dev, HIP_SYMBOL(scratch)) != hipSuccess || h->scratch_dev == nullptr) {
         hz_handle_destroy(h);
         return HZ_ERR_HIP;
     }
@@ -2255,6 +2283,30 @@ int zbicgstab_solve_async(hz_handle* h, hz_stream stream, int n, int nnz, const 
     return solve_fp64(h, static_cast<hipStream_t>(stream), 1, row_off, nnz, rp, ci,
                       reinterpret_cast<const double2*>(vals), reinterpret_cast<const double2*>(b),
                       reinterpret_cast<double2*>(x), rtol, maxiter, f, static_cast<char*>(ws), &unused, info_dev);
+}
+
+size_t zbicgstab_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int zbicgstab_solve_noalloc(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci,
+                            const hz_c128* vals, const hz_c128* b, hz_c128* x, double rtol, int maxiter, int flags,
+                            hz_solve_info* info_dev) {
+    if (h == nullptr || info_dev == nullptr || misaligned(info_dev, 8)) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (!(rtol >= 0.0) || maxiter < 0 || n == 0) return HZ_ERR_INVALID;
+    if (b == nullptr || x == nullptr || misaligned(b, 16) || misaligned(x, 16) || misaligned(vals, 16))
+        return HZ_ERR_INVALID;
+    if (overlap(b, 16 * size_t(n), x, 16 * size_t(n))) return HZ_ERR_INVALID;
+    if (flags & (HZ_REORDER | HZ_VALIDATE | HZ_RELIABLE)) return HZ_ERR_INVALID;
+    const int f = flags | HZ_NO_REORDER;
+    if (single_ws_bytes(n, nnz, f) > kScratchBytes) return HZ_ERR_TOO_LARGE;
+    if (h->scratch_dev == nullptr) return HZ_ERR_HIP;
+    const int row_off[2] = {0, n};
+    hz_solve_info unused;
+    return solve_fp64(h, static_cast<hipStream_t>(stream), 1, row_off, nnz, rp, ci,
+                      reinterpret_cast<const double2*>(vals), reinterpret_cast<const double2*>(b),
+                      reinterpret_cast<double2*>(x), rtol, maxiter, f, static_cast<char*>(h->scratch_dev), &unused,
+                      info_dev, true);
 }
 
 size_t zbicgstabl_workspace_bytes(int n, int nnz, int ell, int flags) {
