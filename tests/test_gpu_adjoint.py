@@ -127,9 +127,12 @@ def test_autograd_matches_dense_reference(hz):
 def test_source_amplitude_gradient_full_cylinder(hz):
     """Gradients w.r.t. 50 source amplitudes on the full cylinder (1000 receivers) by one adjoint solve.
 
-    Reference by a different route: with x = A^{-1} b, b = sum_s a_s e_s, the
-    real-pair gradient is dL/da_s = 2 (A^{-1} e_s)^H g, g = (x - t) on the
-    receivers; each column A^{-1} e_s is a forward solve.
+    With x = A^{-1} b and b = sum_s a_s e_s, the real-pair gradient of the loss w.r.t. b is lambda, the
+    solution of A^H lambda = g with g = 2 (x - t) on the receivers, and dL/da_s = lambda at source s.  The
+    full system runs the gather-light iteration (more than 131,072 rows), which the small dense-LU tests do
+    not reach.  Checked against the oracle only: lambda's true residual through the oracle's explicit
+    conjugate transpose and product, and lambda from the oracle's own Jacobi-BiCGStab on A^H (its OpenMP
+    build, for time).
     """
     A, cfg = W.config_adjoint()
     rec, t, src, amps = cfg["receivers"], cfg["targets"], cfg["sources"], cfg["amps"]
@@ -137,24 +140,30 @@ def test_source_amplitude_gradient_full_cylinder(hz):
     opts = hz.SolveOptions(rtol=1e-11, symmetric=True, jacobi=True)
     a = dev(amps).requires_grad_(True)
     b = torch.zeros(A.n, dtype=torch.complex128, device="cuda:0").index_add(0, dev(src), a)
+    b.retain_grad()
     x = hz.helmholtz_solve(rp, ci, vals, b, opts)
     loss = ((x[dev(rec)] - dev(t)).abs() ** 2).sum()
     loss.backward()
     grad = a.grad.cpu().numpy()
-    xr = x.detach().cpu().numpy()[rec] - t
-    # A zero initial guess would make the shadow residual a unit vector, so rho and <rhat, v> would be
-    # single entries of r and v; those fall ~16 orders below the rounding noise of their terms during the
-    # solve and can round to exactly zero (a breakdown).  A small random start makes r0 and rhat dense.
-    x0 = 1e-3 * cn(np.random.default_rng(7), A.n)
-    for s in (0, 17, 49):
-        e = np.zeros(A.n, complex)
-        e[src[s]] = 1.0
-        y, info = hz.zbicgstab_solve(rp, ci, vals, dev(e), x=dev(x0), rtol=1e-11, flags=hz.PRECOND_JACOBI)
-        assert info["status"] == hz.OK, info
-        ref = 2.0 * np.vdot(y.cpu().numpy()[rec], xr)
-        assert abs(ref - grad[s]) <= 1e-6 * abs(grad).max(), (s, ref, grad[s])
+    lam = b.grad.cpu().numpy()
+    assert np.array_equal(grad, lam[src])  # index_add's backward gathers lambda at the sources
+    xh = x.detach().cpu().numpy()
+    g = np.zeros(A.n, complex)
+    g[rec] = 2.0 * (xh[rec] - t)
+    # (1) residual of A^H lambda = g: adjoint solve to 1e-11 (recursive); the true residual may exceed that by
+    # the rounding drift of ~1,200 FP64 iterations, far below 1e-12 here
+    AH = O.zcsr_conj_transpose(A)
+    rr = np.linalg.norm(g - O.zspmv(AH, lam)) / np.linalg.norm(g)
+    assert rr <= 1.1e-11, rr
+    # (2) the oracle's lambda: both solutions have relative residual <= 1e-11, so they differ by at most
+    # kappa(A) * 2e-11 relative; 1e-6 of the largest gradient leaves kappa up to ~5e4
+    lam_o, info_o = O.zbicgstab_omp(AH, g, tol=1e-11, maxiter=20000, jacobi=True)
+    assert info_o["status"] == O.OK, info_o
+    err = np.abs(lam_o[src] - grad)
+    assert err.max() <= 1e-6 * np.abs(grad).max(), (err.max(), np.abs(grad).max())
+    assert np.linalg.norm(lam_o - lam) <= 1e-6 * np.linalg.norm(lam_o)
     # the loss itself, recomputed on the host from the GPU solution
-    assert abs(loss.item() - _loss_np(x.detach().cpu().numpy(), rec, t)) <= 1e-12 * loss.item()
+    assert abs(loss.item() - _loss_np(xh, rec, t)) <= 1e-12 * loss.item()
 
 
 def _splu_loss(A_sp, b, rec, t):
