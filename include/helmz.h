@@ -146,15 +146,22 @@ int csr_cspmv(hz_handle *handle, hz_stream stream, int n, int nnz, const int *ro
 
 /*
  * *out = sum_i conj(x_i) y_i (Section 5, dot product; the first argument is
- * conjugated).  out is a device pointer; nothing is synchronised.  The sum
- * order is fixed for a given n, so repeated calls are bitwise identical.
+ * conjugated).  out is a device pointer; nothing is synchronised.  Block
+ * partials in the handle's buffer, then a one-block kernel adds them in
+ * index order, so the sum order is fixed for a given n and repeated calls
+ * are bitwise identical.  zdotc, dznrm2 and hz_stream_read share the
+ * handle's partials: calls on one handle must not overlap in time (one
+ * stream, or serialised streams).
  */
 int zdotc(hz_handle *handle, hz_stream stream, int n, const hz_c128 *x, const hz_c128 *y, hz_c128 *out);
 
-/* *out = ||x||_2 = sqrt(sum |x_i|^2) (Section 5, norm), device pointer. */
+/* *out = ||x||_2 = sqrt(sum |x_i|^2) (Section 5, norm), device pointer;
+ * partials and a finishing kernel as for zdotc. */
 int dznrm2(hz_handle *handle, hz_stream stream, int n, const hz_c128 *x, double *out);
 
-/* y <- alpha x + y (Section 5, complex axpy); alpha by value. */
+/* y <- alpha x + y (Section 5, complex axpy); alpha by value; x may equal
+ * y, other overlaps are invalid.  One streaming pass, four 16-byte loads of
+ * each vector in flight per thread. */
 int zaxpy(hz_handle *handle, hz_stream stream, int n, hz_c128 alpha, const hz_c128 *x, hz_c128 *y);
 
 /* Device workspace (bytes) that zbicgstab_solve needs for this n, nnz,
@@ -519,8 +526,8 @@ int csr_zpermute(hz_handle *handle, hz_stream stream, int n, int nnz, const int 
  * that the bandwidth-bound kernels above are compared against on the same
  * part).  hz_stream_read reads `bytes` bytes of buf (device, 16-byte aligned,
  * bytes a multiple of 16) as doubles, each thread keeping eight independent
- * 16-byte loads in flight, and writes their sum, in a fixed order, to *out
- * (device double).  hz_stream_copy copies `bytes` bytes from src to dst
+ * non-temporal 16-byte loads in flight (32 KiB chunks, a few per block), and
+ * writes their sum, in a fixed order, to *out (device double).  hz_stream_copy copies `bytes` bytes from src to dst
  * (device, 16-byte aligned, not overlapping) the same way.  Both enqueue on
  * the stream and return HZ_ERR_INVALID for bad pointers or sizes.  The read
  * uses the handle's partial-sum buffer: calls on one handle must not

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhelmz.so")
 SOURCES = ["helmz.hip"]
-HEADERS = ["hz_kernels.hpp", "hz_adjoint.hpp", "hz_reorder.hpp", "hz_multi.hpp", "hz_reliable.hpp", "hz_spmv.hpp", "hz_bicgstabl.hpp", "hz_tfqmr.hpp", "hz_formats.hpp", "hz_stream.hpp"]
+HEADERS = ["hz_kernels.hpp", "hz_adjoint.hpp", "hz_reorder.hpp", "hz_multi.hpp", "hz_reliable.hpp", "hz_spmv.hpp", "hz_bicgstabl.hpp", "hz_tfqmr.hpp", "hz_formats.hpp", "hz_stream.hpp", "hz_blas1.hpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

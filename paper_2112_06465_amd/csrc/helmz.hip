@@ -25,6 +25,7 @@
 #include "hz_tfqmr.hpp"
 #include "hz_formats.hpp"
 #include "hz_stream.hpp"
+#include "hz_blas1.hpp"
 
 using hz::cx;
 using hz::Geom;
@@ -190,7 +191,7 @@ int rule_lanes(int n, int64_t nnz) {
 int pick_lanes(const hz_handle* h, const int* rp, const int* ci, int n, int64_t nnz) {
     if (const char* env = std::getenv("HZ_SPMV_LANES")) {
         int v = std::atoi(env);
-        if (v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64) return v;
+        if (v == 1 || v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64) return v;
     }
     if (h != nullptr)
         for (auto it = h->tune.rbegin(); it != h->tune.rend(); ++it)
@@ -241,8 +242,10 @@ inline dim3 grid1(int64_t n) { return dim3(unsigned((n + kBlock - 1) / kBlock));
 constexpr int batch_for(int L) { return L >= 16 ? 1 : 2; }
 
 // Calls f.template operator()<L, U>() for the lane width chosen at run time.
+// L = 1 selects the block-tile form of the solver kernels' row loop (for_tiles).
 template <typename F> void with_lanes(int L, F&& f) {
     switch (L) {
+        case 1: f.template operator()<1, 1>(); break;
         case 2: f.template operator()<2, batch_for(2)>(); break;
         case 4: f.template operator()<4, batch_for(4)>(); break;
         case 8: f.template operator()<8, batch_for(8)>(); break;
@@ -278,6 +281,7 @@ void launch_sp(const SpPlan& p, int m, int nnz, const int* rp, const int* ci, co
     hz::SpArgs<T> a{m, nnz, Geom{1}, rp, ci, v, x, y};
     if (p.form == SP_TILE) {
         a.geo = geom_sp(m, hz::kTileRows);
+        if (a.geo.G >= hz::kSpMaxGrid) a.geo.G = hz::kSpTileGrid;
         hipLaunchKernelGGL((hz::k_spmv_tile<T>), dim3(a.geo.G), dim3(hz::kSpBlock), 0, s, a);
         return;
     }
@@ -1739,7 +1743,8 @@ void launch_grad_vals(int n, const int* rp, const int* ci, const double2* lam, c
                       hipStream_t s) {
     const Geom geo = geom_for(n, kBlock / L);
     with_lanes(L, [&]<int LL, int UU>() {
-        hipLaunchKernelGGL((hz::k_grad_vals<LL>), dim3(geo.G), dim3(kBlock), 0, s, n, geo, rp, ci, lam, x, gv);
+        constexpr int LG = LL == 1 ? 4 : LL;  // the tile form's lane count reads whole rows per lane group
+        hipLaunchKernelGGL((hz::k_grad_vals<LG>), dim3(geo.G), dim3(kBlock), 0, s, n, geo, rp, ci, lam, x, gv);
     });
 }
 
@@ -2093,13 +2098,14 @@ int hz_autotune_spmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* 
             rc = HZ_ERR_HIP;
         if (rc == HZ_OK && ms < best) best = ms;
     };
-    // the solver kernels' lane count, timed on their row product
-    constexpr int kCand[6] = {2, 4, 8, 16, 32, 64};
-    float best_ms[6];
+    // the solver kernels' lane count, timed on their row product (1 = block tiles)
+    constexpr int kNCand = 7;
+    constexpr int kCand[kNCand] = {1, 2, 4, 8, 16, 32, 64};
+    float best_ms[kNCand];
     for (float& b : best_ms) b = 1e30f;
     rc = HZ_OK;
     for (int round = 0; round < 2 && rc == HZ_OK; ++round)
-        for (int c = 0; c < 6 && rc == HZ_OK; ++c) {
+        for (int c = 0; c < kNCand && rc == HZ_OK; ++c) {
             const int L = kCand[c];
             const auto a = spmv_args<double>(n, geom_for(n, kBlock / L), rp, ci, A, xd, yd, nullptr, nullptr);
             time_it([&] { launch_spmv<double, hz::EPI_NONE>(L, a, s); }, best_ms[c]);
@@ -2122,9 +2128,9 @@ int hz_autotune_spmv(hz_handle* h, hz_stream stream, int n, int nnz, const int* 
     constexpr float kMargin = 0.97f;
     const int rule = rule_lanes(n, nnz);
     int bc = 0;
-    for (int c = 1; c < 6; ++c)
+    for (int c = 1; c < kNCand; ++c)
         if (best_ms[c] < best_ms[bc]) bc = c;
-    for (int c = 0; c < 6; ++c)
+    for (int c = 0; c < kNCand; ++c)
         if (kCand[c] == rule && best_ms[bc] >= kMargin * best_ms[c]) bc = c;
     SpPlan sp{SP_PIPE, rule};
     if (nnz > 0) {
@@ -2171,10 +2177,12 @@ int zdotc(hz_handle* h, hz_stream stream, int n, const hz_c128* x, const hz_c128
     if (n > 0 && (x == nullptr || y == nullptr)) return HZ_ERR_INVALID;
     if (misaligned(x, 16) || misaligned(y, 16) || misaligned(out, 16)) return HZ_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Geom geo = geom_for(n > 0 ? n : 1, kBlock);
-    hipLaunchKernelGGL(hz::k_dot_part<0>, dim3(geo.G), dim3(kBlock), 0, s, n, geo,
+    const hz::B1Shape sh = hz::b1_shape(n);
+    static_assert(2 * hz::kB1MaxGrid <= kParts * kMaxGrid, "partials of zdotc fit the handle's buffer");
+    hipLaunchKernelGGL(hz::k_zdot_s<0>, dim3(sh.G), dim3(hz::kB1Block), 0, s, int64_t(n), sh.per,
                        reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(y), h->part);
-    hipLaunchKernelGGL(hz::k_dot_fin<0>, dim3(1), dim3(kBlock), 0, s, h->part, geo.G, static_cast<void*>(out));
+    hipLaunchKernelGGL(hz::k_zdot_fin<0>, dim3(1), dim3(hz::kB1Block), 0, s, static_cast<const double*>(h->part), sh.G,
+                       static_cast<void*>(out));
     HZ_HIP(hipGetLastError());
     return HZ_OK;
 }
@@ -2184,10 +2192,11 @@ int dznrm2(hz_handle* h, hz_stream stream, int n, const hz_c128* x, double* out)
     if (n > 0 && x == nullptr) return HZ_ERR_INVALID;
     if (misaligned(x, 16) || misaligned(out, 8)) return HZ_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const Geom geo = geom_for(n > 0 ? n : 1, kBlock);
-    hipLaunchKernelGGL(hz::k_dot_part<1>, dim3(geo.G), dim3(kBlock), 0, s, n, geo,
-                       reinterpret_cast<const double2*>(x), nullptr, h->part);
-    hipLaunchKernelGGL(hz::k_dot_fin<1>, dim3(1), dim3(kBlock), 0, s, h->part, geo.G, static_cast<void*>(out));
+    const hz::B1Shape sh = hz::b1_shape(n);
+    hipLaunchKernelGGL(hz::k_zdot_s<1>, dim3(sh.G), dim3(hz::kB1Block), 0, s, int64_t(n), sh.per,
+                       reinterpret_cast<const double2*>(x), static_cast<const double2*>(nullptr), h->part);
+    hipLaunchKernelGGL(hz::k_zdot_fin<1>, dim3(1), dim3(hz::kB1Block), 0, s, static_cast<const double*>(h->part), sh.G,
+                       static_cast<void*>(out));
     HZ_HIP(hipGetLastError());
     return HZ_OK;
 }
@@ -2201,9 +2210,8 @@ int zaxpy(hz_handle* h, hz_stream stream, int n, hz_c128 alpha, const hz_c128* x
     double2 a;
     a.x = alpha.re;
     a.y = alpha.im;
-    int64_t blocks = (int64_t(n) + kBlock - 1) / kBlock;
-    if (blocks > 8 * kMaxGrid) blocks = 8 * kMaxGrid;
-    hipLaunchKernelGGL(hz::k_zaxpy, dim3(unsigned(blocks)), dim3(kBlock), 0, s, int64_t(n), a,
+    const hz::B1Shape sh = hz::b1_shape(n);
+    hipLaunchKernelGGL(hz::k_zaxpy_s, dim3(sh.G), dim3(hz::kB1Block), 0, s, int64_t(n), sh.per, a,
                        reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
     HZ_HIP(hipGetLastError());
     return HZ_OK;
@@ -2212,12 +2220,13 @@ int zaxpy(hz_handle* h, hz_stream stream, int n, hz_c128 alpha, const hz_c128* x
 int hz_stream_read(hz_handle* h, hz_stream stream, const void* buf, size_t bytes, double* out) {
     if (h == nullptr || out == nullptr || bytes % 16 != 0 || (bytes > 0 && buf == nullptr)) return HZ_ERR_INVALID;
     if (misaligned(buf, 16) || misaligned(out, 8)) return HZ_ERR_INVALID;
-    static_assert(hz::kStreamGrid <= kParts * kMaxGrid, "partials of the stream read fit the handle's buffer");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(hz::k_stream_read, dim3(hz::kStreamGrid), dim3(hz::kStreamBlock), 0, s,
-                       static_cast<const double2*>(buf), int64_t(bytes / 16), h->part);
+    const hz::StreamShape sh = hz::stream_shape(int64_t(bytes / 16));
+    static_assert(hz::kStreamMaxGrid <= kParts * kMaxGrid, "partials of the stream read fit the handle's buffer");
+    hipLaunchKernelGGL(hz::k_stream_read, dim3(sh.G), dim3(hz::kStreamBlock), 0, s, static_cast<const double2*>(buf),
+                       int64_t(bytes / 16), sh.per, h->part);
     hipLaunchKernelGGL(hz::k_stream_fin, dim3(1), dim3(hz::kStreamBlock), 0, s, static_cast<const double*>(h->part),
-                       hz::kStreamGrid, out);
+                       sh.G, out);
     HZ_HIP(hipGetLastError());
     return HZ_OK;
 }
@@ -2228,8 +2237,9 @@ int hz_stream_copy(hz_handle* h, hz_stream stream, const void* src, void* dst, s
     if (src == nullptr || dst == nullptr || misaligned(src, 16) || misaligned(dst, 16)) return HZ_ERR_INVALID;
     if (overlap(src, bytes, dst, bytes)) return HZ_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(hz::k_stream_copy, dim3(hz::kStreamGrid), dim3(hz::kStreamBlock), 0, s,
-                       static_cast<const double2*>(src), int64_t(bytes / 16), static_cast<double2*>(dst));
+    const hz::StreamShape sh = hz::stream_shape(int64_t(bytes / 16));
+    hipLaunchKernelGGL(hz::k_stream_copy, dim3(sh.G), dim3(hz::kStreamBlock), 0, s, static_cast<const double2*>(src),
+                       int64_t(bytes / 16), sh.per, static_cast<double2*>(dst));
     HZ_HIP(hipGetLastError());
     return HZ_OK;
 }

@@ -86,6 +86,43 @@ __device__ __forceinline__ bool zfinite(double2 a) { return __builtin_isfinite(a
 __device__ __forceinline__ bool zzero(double2 a) { return a.x == 0.0 && a.y == 0.0; }
 template <typename T> __device__ __forceinline__ cx<T> narrow(double2 a) { return mk<T>((T)a.x, (T)a.y); }
 
+// Streaming (non-temporal) loads of matrix arrays, for kernels whose every
+// load instruction covers whole cache lines of consecutive entries (the block
+// tiles of the standalone product): the data is read once, and on this part
+// such streaming loads sustain 5-10 % more HBM bandwidth than ordinary ones.
+// Row-split accesses (L lanes per row, a line shared by neighbouring rows) and
+// the solvers' products, whose matrix is re-read every iteration, measured
+// slower with them and use ordinary loads.  HZ_STREAM_MATRIX=0 at build time
+// makes these ordinary loads too.
+#ifndef HZ_STREAM_MATRIX
+#define HZ_STREAM_MATRIX 1
+#endif
+typedef double hz_d2v __attribute__((ext_vector_type(2)));
+typedef float hz_f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int ld_mat(const int* p) {
+#if HZ_STREAM_MATRIX
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+__device__ __forceinline__ double2 ld_mat(const double2* p) {
+#if HZ_STREAM_MATRIX
+    const hz_d2v v = __builtin_nontemporal_load(reinterpret_cast<const hz_d2v*>(p));
+    return mk<double>(v.x, v.y);
+#else
+    return *p;
+#endif
+}
+__device__ __forceinline__ float2 ld_mat(const float2* p) {
+#if HZ_STREAM_MATRIX
+    const hz_f2v v = __builtin_nontemporal_load(reinterpret_cast<const hz_f2v*>(p));
+    return mk<float>(v.x, v.y);
+#else
+    return *p;
+#endif
+}
+
 // ------------------------------------------------------------------ lane exchange (DPP / ds_swizzle)
 
 struct I2 {
@@ -286,6 +323,73 @@ __device__ __forceinline__ cx<T> row_partial(int beg, int end, int lane, const i
     return acc;
 }
 
+// Block-tile form of the row loop (the lane count L = 1 selects it): tiles
+// of kSolTileRows rows; the block loads a tile's entries [rp[r0], rp[r0 +
+// kSolTileRows]) contiguously (thread t takes entries e0 + t + k kBlock,
+// straight-line, clamped into the tile), multiplies them by the gathered
+// operand op(col), writes the products to LDS, and kSolTileLanes threads per
+// row sum the row out of LDS in entry order; epi(row, total) runs in the
+// first thread of each row.  Each load instruction reads kBlock consecutive
+// entries, whole cache lines, where the vector form reads a row's few
+// entries per lane group.  A tile with more than kSolTileCap entries is done
+// as vector rows.  The trip count is uniform across the block.
+constexpr int kSolTileLanes = 4;
+constexpr int kSolTileRows = kBlock / kSolTileLanes;
+constexpr int kSolTilePer = 4;
+constexpr int kSolTileCap = kBlock * kSolTilePer;
+
+template <typename T, typename Op, typename Epi>
+__device__ __forceinline__ void for_tiles(const Rows& rw, const int* __restrict__ rp, const int* __restrict__ ci,
+                                          const cx<T>* __restrict__ vals, Op op, Epi epi) {
+    constexpr int L = kSolTileLanes;
+    __shared__ cx<T> prod[kSolTileCap];
+    const int t = threadIdx.x, g = t / L, lane = t % L;
+    const int64_t first = rw.x0 + (int64_t)rw.k * kSolTileRows, step = (int64_t)rw.K * kSolTileRows;
+    const int64_t r1 = rw.x1;
+    for (int64_t r0 = first; r0 < r1; r0 += step) {
+        const int64_t re = r0 + kSolTileRows < r1 ? r0 + kSolTileRows : r1;
+        const int e0 = rp[r0], e1 = rp[re];
+        const int64_t row = r0 + g;
+        const int b = rp[row < re ? row : re], e = rp[row + 1 < re ? row + 1 : re];
+        cx<T> acc = mk<T>(T(0), T(0));
+        if (e1 > e0 && e1 - e0 <= kSolTileCap) {  // (a tile of empty rows loads nothing: block-uniform)
+            const int last = e1 - 1;
+            int c[kSolTilePer];
+            cx<T> v[kSolTilePer], o[kSolTilePer];
+#pragma unroll
+            for (int k = 0; k < kSolTilePer; ++k) {
+                const int p = e0 + t + k * kBlock;
+                c[k] = ci[p < last ? p : last];
+            }
+#pragma unroll
+            for (int k = 0; k < kSolTilePer; ++k) {
+                const int p = e0 + t + k * kBlock;
+                v[k] = vals[p < last ? p : last];
+            }
+#pragma unroll
+            for (int k = 0; k < kSolTilePer; ++k) o[k] = op(c[k]);
+#pragma unroll
+            for (int k = 0; k < kSolTilePer; ++k) {
+                const bool ok = e0 + t + k * kBlock < e1;
+                const cx<T> pr = cmul<T>(v[k], o[k]);
+                prod[t + k * kBlock] = mk<T>(ok ? pr.x : T(0), ok ? pr.y : T(0));
+            }
+            __syncthreads();
+            for (int q = b - e0 + lane; q < e - e0; q += L) {
+                const cx<T> pv = prod[q];
+                acc.x += pv.x;
+                acc.y += pv.y;
+            }
+            __syncthreads();
+        } else if (e1 > e0 && row < re) {
+            acc = row_partial<T, L, 1>(b, e, lane, ci, vals, op);
+        }
+        acc.x = group_sum<L>(acc.x);
+        acc.y = group_sum<L>(acc.y);
+        if (row < re && lane == 0) epi(row, acc);
+    }
+}
+
 // Row loop of a block over its tiles of RPS = kBlock/L rows (g = thread / L
 // picks the row of the tile).  With
 // PF the next step's row_ptr pair is loaded before the current row's product,
@@ -296,6 +400,10 @@ __device__ __forceinline__ cx<T> row_partial(int beg, int end, int lane, const i
 template <typename T, int L, int U, bool PF = true, typename Op, typename Epi>
 __device__ __forceinline__ void for_rows(const Rows& rw, const int* __restrict__ rp, const int* __restrict__ ci,
                                          const cx<T>* __restrict__ vals, Op op, Epi epi) {
+    if constexpr (L == 1) {
+        for_tiles<T>(rw, rp, ci, vals, op, epi);
+        return;
+    }
     constexpr int RPS = kBlock / L;
     const int g = threadIdx.x / L, lane = threadIdx.x % L;
     const int64_t first = rw.x0 + (int64_t)rw.k * RPS, step = (int64_t)rw.K * RPS, r1 = rw.x1;

@@ -17,7 +17,12 @@
 //   loaded by the whole block contiguously (thread t takes entries e0 + t,
 //   e0 + t + 256, ...), multiplied by the gathered x and written to LDS; then
 //   kTileLanes threads per row sum the row's products out of LDS.  A tile
-//   with more than kTileCap entries is done as vector rows instead.
+//   with more than kTileCap entries is done as vector rows instead.  Its
+//   matrix loads are straight-line (clamped into the tile, masked after) and
+//   streaming (ld_mat): each instruction reads 256 consecutive entries, whole
+//   cache lines.  Up to kSpMaxGrid tiles, every tile gets a block; beyond,
+//   kSpTileGrid blocks loop over the tiles (fewer concurrent streams measured
+//   faster from HBM: 80 against 83 us on a 409 MB product).
 //
 // Row ownership is that of the other kernels (XCD groups, tiles dealt out
 // within a group), with the form's own tile height.  Summation order is fixed
@@ -34,6 +39,7 @@ constexpr int kTileRows = 64;                     // rows per tile of the block 
 constexpr int kTileLanes = kSpBlock / kTileRows;  // threads per row in its reduction
 constexpr int kTilePer = 4;                       // entries per thread per tile
 constexpr int kTileCap = kSpBlock * kTilePer;     // entries per tile held in LDS
+constexpr int kSpTileGrid = 1024;                 // blocks of the tile form beyond kSpMaxGrid tiles
 
 template <typename T> struct SpArgs {
     int n;    // rows
@@ -128,27 +134,41 @@ __global__ __launch_bounds__(kSpBlock) void k_spmv_tile(const SpArgs<T> a) {
     const int* __restrict__ ci = a.col_idx;
     const cx<T>* __restrict__ vals = a.vals;
     const cx<T>* __restrict__ x = a.x;
+    const int nnz = a.nnz;
     for (int64_t r0 = first; r0 < r1; r0 += step) {  // uniform across the block
         const int64_t re = r0 + kTileRows < r1 ? r0 + kTileRows : r1;
-        const int64_t e0 = rp[r0], e1 = rp[re];
+        const int e0 = rp[r0], e1 = rp[re];
         const int64_t row = r0 + g;
-        int b = 0, e = 0;
-        if (row < re) {
-            b = rp[row];
-            e = rp[row + 1];
-        }
+        const int b = rp[row < re ? row : re], e = rp[row + 1 < re ? row + 1 : re];
         cx<T> acc = mk<T>(T(0), T(0));
         if (e1 - e0 <= kTileCap) {
+            // straight-line streaming loads: entry e0 + t + k kSpBlock, clamped into the tile
+            const int last = e1 > e0 ? e1 - 1 : (e0 < nnz ? e0 : nnz - 1);
+            int c[kTilePer];
+            cx<T> v[kTilePer], o[kTilePer];
 #pragma unroll
             for (int k = 0; k < kTilePer; ++k) {
-                const int64_t p = e0 + t + k * kSpBlock;
-                if (p < e1) prod[p - e0] = cmul<T>(vals[p], x[ci[p]]);
+                const int p = e0 + t + k * kSpBlock;
+                c[k] = ld_mat(ci + (p < last ? p : last));
+            }
+#pragma unroll
+            for (int k = 0; k < kTilePer; ++k) {
+                const int p = e0 + t + k * kSpBlock;
+                v[k] = ld_mat(vals + (p < last ? p : last));
+            }
+#pragma unroll
+            for (int k = 0; k < kTilePer; ++k) o[k] = x[c[k]];
+#pragma unroll
+            for (int k = 0; k < kTilePer; ++k) {
+                const bool ok = e0 + t + k * kSpBlock < e1;
+                const cx<T> pr = cmul<T>(v[k], o[k]);
+                prod[t + k * kSpBlock] = mk<T>(ok ? pr.x : T(0), ok ? pr.y : T(0));
             }
             __syncthreads();
-            for (int64_t q = b - e0 + lane; q < e - e0; q += L) {
-                const cx<T> v = prod[q];
-                acc.x += v.x;
-                acc.y += v.y;
+            for (int q = b - e0 + lane; q < e - e0; q += L) {
+                const cx<T> pv = prod[q];
+                acc.x += pv.x;
+                acc.y += pv.y;
             }
             __syncthreads();
         } else if (row < re) {
