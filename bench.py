@@ -257,6 +257,20 @@ def spmv_cabin(hz, torch, dev, cab, reps=20):
             loop.enqueue()
             res[label] = dict(rate(spmv_bytes(n, nnz), loop.us()), kernel=spmv_kernel_name(form, L))
         del reps_
+    # the caller's numbering through a plan (level-set renumbered copy, x gathered, y scattered back)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plans = [hz.csr_zspmv_plan(cab.rp, cab.ci, cab.vals)]
+    torch.cuda.synchronize()
+    res["plan_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+    plans.append(hz.csr_zspmv_plan(cab.rp, cab.ci, cab.vals.clone()))
+    ys = [torch.empty_like(cab.x) for _ in plans]
+    loop = ColdLoop(torch, lambda py: hz.csr_zspmv_planned(py[0], cab.x, py[1]), list(zip(plans, ys)), reps)
+    loop.enqueue()
+    res["given_numbering_planned"] = dict(rate(spmv_bytes(n, nnz), loop.us()),
+                                          kernels="hz::k_gather_perm<double> + hz::k_spmv_tile<double>")
+    del plans, ys
+    torch.cuda.empty_cache()
     tune = hz.autotune_spmv(cab.rp2, cab.ci2, cab.v2, cab.xp, details=True)
     res["autotuned_form"] = {"form": tune["form"], "lanes": tune["form_lanes"]}
     ell = [hz.csr_to_hyb(cab.rp2, cab.ci2, cab.v2, K="ell")]
@@ -305,7 +319,7 @@ def spmv_cylinder(hz, torch, dev, reps=30):
     return res
 
 
-def time_solves(hz, torch, dev, name, A, b_np, rp, ci, vals, tol, runs, maxiter=50000):
+def time_solves(hz, torch, dev, name, A, b_np, rp, ci, vals, tol, runs, maxiter=50000, maxcycles=3125):
     """Wall time of each named solve to tol (one warm-up, then one timed run); x checked on the host."""
     n, nnz = A.n, A.nnz
     b = torch.from_numpy(b_np).to(dev)
@@ -333,8 +347,8 @@ def time_solves(hz, torch, dev, name, A, b_np, rp, ci, vals, tol, runs, maxiter=
         "mixed_reliable": lambda: hz.zbicgstab_solve_mixed(rp, ci, vals, b, x=x, rtol=tol, maxiter=maxiter,
                                                            flags=flags | hz.RELIABLE, ws=ws("mixed")),
         # BiCGstab(8), the paper's second solver: iterations are cycles of 8 Bi-CG steps (16 products)
-        "bicgstab_l8": lambda: hz.zbicgstabl_solve(rp, ci, vals, b, x=x, ell=8, rtol=tol,
-                                                   maxcycles=max(1, maxiter // 16), flags=flags, ws=ws("l8")),
+        "bicgstab_l8": lambda: hz.zbicgstabl_solve(rp, ci, vals, b, x=x, ell=8, rtol=tol, maxcycles=maxcycles,
+                                                   flags=flags, ws=ws("l8")),
         # TFQMR, the paper's third solver: two products per iteration, stopped on the quasi-residual bound
         "tfqmr": lambda: hz.ztfqmr_solve(rp, ci, vals, b, x=x, rtol=tol, maxiter=maxiter, flags=flags,
                                          ws=ws("tfqmr")),
@@ -689,7 +703,12 @@ def profile(what, steps, cache_dir):
     if what.startswith("spmv-cabin"):
         cab = Cabin(hz, torch, dev, cache_dir)
         L = rule_lanes(cab.n, cab.nnz)
-        if what == "spmv-cabin-ell":
+        if what == "spmv-cabin-planned":
+            plans = [hz.csr_zspmv_plan(cab.rp, cab.ci, cab.vals), hz.csr_zspmv_plan(cab.rp, cab.ci, cab.vals.clone())]
+            ys = [torch.empty_like(cab.x) for _ in plans]
+            loop = ColdLoop(torch, lambda py: hz.csr_zspmv_planned(py[0], cab.x, py[1]), list(zip(plans, ys)), 30)
+            form = None
+        elif what == "spmv-cabin-ell":
             ell = [hz.csr_to_hyb(cab.rp2, cab.ci2, cab.v2, K="ell")]
             ell.append({k: (v.clone() if hasattr(v, "clone") else v) for k, v in ell[0].items()})
             ys = [torch.empty_like(cab.x) for _ in ell]
@@ -732,7 +751,7 @@ def main():
     ap.add_argument("--cache", default=None, help="directory to keep generated workloads in (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--profile", default=None,
-                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-ell | solve-cabin | "
+                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | "
                          "adjoint-cylinder | stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline step only (no secondary sections)")
@@ -866,7 +885,7 @@ def main():
             A1c, b1c, _ = W.config_cylinder(robin="caps")
             out["time_to_tol"].append(time_solves(hz, torch, dev, "cylinder, Robin on the end caps only", A1c, b1c,
                                                   up(A1c.row_ptr), up(A1c.col_idx), up(A1c.vals), 1e-8,
-                                                  ["fp64", "bicgstab_l8", "tfqmr"], maxiter=20000))
+                                                  ["fp64", "bicgstab_l8", "tfqmr"], maxiter=20000, maxcycles=4000))
             out["time_to_tol"].append(time_solves(hz, torch, dev, "cabin", cab.A, cab.b_np, cab.rp, cab.ci,
                                                   cab.vals, 1e-10, all_runs + ["fp64_caller_order"]))
         if not args.no_adjoint:

@@ -536,6 +536,31 @@ int csr_zpermute(hz_handle *handle, hz_stream stream, int n, int nnz, const int 
 int hz_stream_read(hz_handle *handle, hz_stream stream, const void *buf, size_t bytes, double *out);
 int hz_stream_copy(hz_handle *handle, hz_stream stream, const void *src, void *dst, size_t bytes);
 
+/*
+ * Product in the caller's numbering through a renumbered copy (Section 3.2
+ * CSR storage, Section 6 product; the renumbering is not the paper's, see
+ * csr_level_order).  A randomly numbered matrix makes nearly every gathered
+ * 16-byte x element fetch its own cache line; a plan keeps the level-set
+ * renumbered copy P A P^T so that repeated products stream it instead.
+ * csr_zspmv_plan builds the plan in caller-owned device memory `plan` of
+ * csr_zspmv_plan_bytes(n, nnz) bytes (256-byte aligned; it holds perm and
+ * its inverse (4 n each), P A P^T (20 nnz + 4 (n + 1)), room for P x (16 n)
+ * and the ordering scratch) and synchronises the stream.  The plan copies
+ * the values: after the caller changes vals it must be rebuilt.
+ * csr_zspmv_planned computes y = A x (caller's numbering) as x_p = P x
+ * (gathered once), then the block-tile product of P A P^T writing row k to
+ * y[perm[k]] (about 72 n bytes more than csr_zspmv moves, for gathers that
+ * stay in cache).  n and nnz must be those the plan was built with; x and y
+ * must not overlap each other or the plan.  Concurrent products on one plan
+ * race on its x_p.  Returns HZ_ERR_WORKSPACE for a missing, misaligned or
+ * small plan, HZ_ERR_INVALID for bad pointers or overlaps.
+ */
+size_t csr_zspmv_plan_bytes(int n, int nnz);
+int csr_zspmv_plan(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
+                   const hz_c128 *vals, void *plan, size_t plan_bytes);
+int csr_zspmv_planned(hz_handle *handle, hz_stream stream, int n, int nnz, const void *plan, size_t plan_bytes,
+                      const hz_c128 *x, hz_c128 *y);
+
 #ifdef __cplusplus
 }
 #endif

@@ -90,6 +90,9 @@ SIGNATURES = {
     "csr_zpermute": (I, [P, P, I, I, P, P, P, P, P, P, P, P, P, SZ]),
     "hz_stream_read": (I, [P, P, P, SZ, P]),
     "zbicgstab_noalloc_max_bytes": (SZ, []),
+    "csr_zspmv_plan_bytes": (SZ, [I, I]),
+    "csr_zspmv_plan": (I, [P, P, I, I, P, P, P, P, SZ]),
+    "csr_zspmv_planned": (I, [P, P, I, I, P, SZ, P, P]),
     "zbicgstab_solve_noalloc": (I, [P, P, I, I, P, P, P, P, P, D, I, I, P]),
     "hz_stream_copy": (I, [P, P, P, P, SZ]),
 }

@@ -150,6 +150,40 @@ def zdotc(x, y, out=None):
     return out
 
 
+def csr_zspmv_plan(row_ptr, col_idx, vals, plan=None):
+    """Plan for products in the caller's numbering through a level-set renumbered copy (csr_zspmv_plan).
+
+    Returns a dict (n, nnz, plan tensor) for ``csr_zspmv_planned``; rebuild it after vals change.
+    """
+    dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    need = int(load().csr_zspmv_plan_bytes(n, nnz))
+    if plan is None:
+        plan = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    _need(plan, "plan", torch.uint8, dev)
+    pp, pbytes = _aligned_ptr(plan, need)
+    rc = load().csr_zspmv_plan(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                               vals.data_ptr(), pp, pbytes)
+    _check("csr_zspmv_plan", rc)
+    return {"n": n, "nnz": nnz, "plan": plan}
+
+
+def csr_zspmv_planned(plan, x, y=None):
+    """y = A x (caller's numbering) with a plan from csr_zspmv_plan (csr_zspmv_planned)."""
+    p = plan["plan"]
+    dev, n, nnz = p.device, plan["n"], plan["nnz"]
+    _need(x, "x", torch.complex128, dev)
+    if x.numel() != n:
+        raise ValueError("x has the wrong length")
+    if y is None:
+        y = torch.empty_like(x)
+    _need(y, "y", torch.complex128, dev)
+    need = int(load().csr_zspmv_plan_bytes(n, nnz))
+    pp, pbytes = _aligned_ptr(p, need)
+    rc = load().csr_zspmv_planned(handle(dev), _stream(dev), n, nnz, pp, pbytes, x.data_ptr(), y.data_ptr())
+    _check("csr_zspmv_planned", rc)
+    return y
+
+
 def stream_read(buf, out=None):
     """Sum of a device buffer's doubles by the bandwidth-calibration read (hz_stream_read)."""
     dev = buf.device

@@ -2752,9 +2752,98 @@ int zbicgstab_adjoint_batched(hz_handle* h, hz_stream stream, int nsys, int n, i
     return rc;
 }
 
+// ------------------------------------------------------------------ planned product in the caller's numbering
+
+// A plan: the level-set permutation, its inverse, P A P^T and room for P x,
+// then the ordering scratch (used while the plan is built).
+struct SpPlanWs {
+    int* perm;
+    int* inv;
+    int* rp;
+    int* ci;
+    double2* vals;
+    double2* xp;
+    LevelWs lv;
+};
+
+static size_t spplan_layout(int n, int64_t nnz, char* base, SpPlanWs* out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const size_t nn = size_t(n > 0 ? n : 1), nz = size_t(nnz > 0 ? nnz : 1);
+    SpPlanWs w{};
+    w.perm = static_cast<int*>(take(sizeof(int) * nn));
+    w.inv = static_cast<int*>(take(sizeof(int) * nn));
+    w.rp = static_cast<int*>(take(sizeof(int) * (nn + 1)));
+    w.ci = static_cast<int*>(take(sizeof(int) * nz));
+    w.vals = static_cast<double2*>(take(sizeof(double2) * nz));
+    w.xp = static_cast<double2*>(take(sizeof(double2) * nn));
+    off += level_layout(n, base ? base + off : nullptr, &w.lv);
+    if (out) *out = w;
+    return off;
+}
+
 size_t csr_reorder_workspace_bytes(int n, int nnz) {
     if (n < 0 || nnz < 0) return 0;
     return level_layout(n, nullptr, nullptr);
+}
+
+size_t csr_zspmv_plan_bytes(int n, int nnz) {
+    if (n < 0 || nnz < 0) return 0;
+    return spplan_layout(n, nnz, nullptr, nullptr);
+}
+
+int csr_zspmv_plan(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, const hz_c128* vals,
+                   void* plan, size_t plan_bytes) {
+    if (h == nullptr) return HZ_ERR_INVALID;
+    int rc = check_csr_args(n, nnz, rp, ci, vals);
+    if (rc) return rc;
+    if (n == 0) return HZ_OK;
+    if (misaligned(vals, 16)) return HZ_ERR_INVALID;
+    SpPlanWs w;
+    const size_t need = spplan_layout(n, nnz, static_cast<char*>(plan), &w);
+    if (plan == nullptr || plan_bytes < need || misaligned(plan, kAlign)) return HZ_ERR_WORKSPACE;
+    if (overlap(plan, need, rp, 4 * (size_t(n) + 1)) || overlap(plan, need, ci, 4 * size_t(nnz)) ||
+        overlap(plan, need, vals, 16 * size_t(nnz)))
+        return HZ_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = level_order(h, s, n, rp, ci, w.lv, w.perm, w.inv, nullptr);
+    if (rc) return rc;
+    rc = permute_csr(s, n, nnz, rp, ci, reinterpret_cast<const double2*>(vals), w.perm, w.inv, w.lv, w.rp, w.ci,
+                     w.vals);
+    if (rc) return rc;
+    HZ_HIP(hipStreamSynchronize(s));
+    return HZ_OK;
+}
+
+int csr_zspmv_planned(hz_handle* h, hz_stream stream, int n, int nnz, const void* plan, size_t plan_bytes,
+                      const hz_c128* x, hz_c128* y) {
+    if (h == nullptr || n < 0 || nnz < 0) return HZ_ERR_INVALID;
+    if (n == 0) return HZ_OK;
+    if (x == nullptr || y == nullptr || misaligned(x, 16) || misaligned(y, 16)) return HZ_ERR_INVALID;
+    if (overlap(x, 16 * size_t(n), y, 16 * size_t(n))) return HZ_ERR_INVALID;
+    SpPlanWs w;
+    const size_t need = spplan_layout(n, nnz, static_cast<char*>(const_cast<void*>(plan)), &w);
+    if (plan == nullptr || plan_bytes < need || misaligned(plan, kAlign)) return HZ_ERR_WORKSPACE;
+    if (overlap(plan, need, x, 16 * size_t(n)) || overlap(plan, need, y, 16 * size_t(n))) return HZ_ERR_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (nnz == 0) {
+        hipLaunchKernelGGL(k_zero_c128, grid1(n), dim3(kBlock), 0, s, n, reinterpret_cast<double2*>(y));
+        HZ_HIP(hipGetLastError());
+        return HZ_OK;
+    }
+    // x into the plan's numbering, then the block-tile product writing row k to y[perm[k]]
+    hipLaunchKernelGGL(hz::k_gather_perm<double>, grid1(n), dim3(kBlock), 0, s, n, static_cast<const int*>(w.perm),
+                       reinterpret_cast<const double2*>(x), w.xp);
+    hz::SpArgs<double> a{n, nnz, geom_sp(n, hz::kTileRows), w.rp, w.ci, w.vals, w.xp, reinterpret_cast<double2*>(y),
+                         w.perm};
+    if (a.geo.G >= hz::kSpMaxGrid) a.geo.G = hz::kSpTileGrid;
+    hipLaunchKernelGGL((hz::k_spmv_tile<double>), dim3(a.geo.G), dim3(hz::kSpBlock), 0, s, a);
+    HZ_HIP(hipGetLastError());
+    return HZ_OK;
 }
 
 int csr_level_order(hz_handle* h, hz_stream stream, int n, int nnz, const int* rp, const int* ci, int* perm, int* inv,

@@ -50,6 +50,7 @@ template <typename T> struct SpArgs {
     const cx<T>* __restrict__ vals;
     const cx<T>* __restrict__ x;  // at least one element
     cx<T>* __restrict__ y;
+    const int* __restrict__ yperm = nullptr;  // tile form: row r's result goes to y[yperm[r]] when set
 };
 
 template <typename T, int L, int U>
@@ -176,7 +177,7 @@ __global__ __launch_bounds__(kSpBlock) void k_spmv_tile(const SpArgs<T> a) {
         }
         acc.x = group_sum<L>(acc.x);
         acc.y = group_sum<L>(acc.y);
-        if (row < re && lane == 0) a.y[row] = acc;
+        if (row < re && lane == 0) a.y[a.yperm != nullptr ? a.yperm[row] : row] = acc;
     }
 }
 

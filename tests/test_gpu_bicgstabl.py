@@ -90,6 +90,18 @@ def test_full_size_cylinder(hz):
     print(f"full cylinder l=8: cycles {info['iterations']} true relres {rr:.3e}")
 
 
+def test_full_size_cylinder_robin_on_the_caps_only(hz):
+    """The cylinder with Robin conditions on the end caps only: Jacobi-BiCGStab stagnates near 4e-4 there,
+    BiCGstab(8) reaches 1e-8 (the oracle's BiCGstab(8) needs about 2,100 cycles).  Checked with the oracle's
+    product."""
+    A, b, _ = W.config_cylinder(robin="caps")
+    x, info = solve(hz, A, b, ell=8, rtol=1e-8, maxcycles=4000, flags=hz.PRECOND_JACOBI | hz.X0_ZERO)
+    assert info["status"] == hz.OK, info
+    rr = true_relres(A, x, b)
+    assert rr <= 1e-8 * (1 + 1e-2)
+    print(f"caps-only cylinder: cycles {info['iterations']} true relres {rr:.3e}")
+
+
 def test_renumbered_scrambled_mesh(hz):
     A, b, _ = W.config_cube(14, seed=4)
     rng = np.random.default_rng(9)
