@@ -729,6 +729,35 @@ def profile(what, steps, cache_dir):
                                          flags=hz.PRECOND_JACOBI | hz.X0_ZERO)
             torch.cuda.synchronize()
             print(what, info, flush=True)
+    elif what in ("sweep-explicit", "sweep-kmb"):
+        # 200 iterations of the 64-frequency batch, every system still active (they need 1,249 or more)
+        import workloads as W
+
+        A, vals, rhs, ks, sw = W.config_freq_sweep(B=64)
+        n, nnz, B = A.n, A.nnz, 64
+        rp, ci = torch.from_numpy(A.row_ptr).to(dev), torch.from_numpy(A.col_idx).to(dev)
+        Bm = torch.from_numpy(np.ascontiguousarray(rhs.T)).to(dev)
+        X = torch.zeros_like(Bm)
+        flags = hz.PRECOND_JACOBI | hz.X0_ZERO
+        if what == "sweep-explicit":
+            V = torch.from_numpy(np.ascontiguousarray(vals.T)).to(dev)
+            ws = torch.empty(hz.zbicgstab_batched_workspace_bytes(B, n, nnz, flags) + 256, dtype=torch.uint8,
+                             device=dev)
+            run = lambda: hz.zbicgstab_solve_batched(rp, ci, V, Bm, x=X, rtol=1e-10, maxiter=200,  # noqa: E731
+                                                     flags=flags, ws=ws)
+        else:
+            Kd, Md, Bd = (torch.from_numpy(sw[k]).to(dev) for k in ("K", "M", "B"))
+            ws = torch.empty(hz.zbicgstab_sweep_workspace_bytes(B, n, nnz, flags) + 256, dtype=torch.uint8,
+                             device=dev)
+            run = lambda: hz.zbicgstab_solve_sweep(rp, ci, Kd, Md, Bd, ks, Bm, x=X, rtol=1e-10,  # noqa: E731
+                                                   maxiter=200, flags=flags, ws=ws)
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, infos = run()
+            torch.cuda.synchronize()
+            print(what, "ms per iteration", round((time.perf_counter() - t0) * 1e3 / 200, 4),
+                  "active", sum(i["status"] == 1 for i in infos), flush=True)
     elif what == "adjoint-cylinder":
         for _ in range(steps):
             print(what, json.dumps(adjoint_cylinder(hz, torch, dev)), flush=True)
@@ -751,7 +780,7 @@ def main():
     ap.add_argument("--cache", default=None, help="directory to keep generated workloads in (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--profile", default=None,
-                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | "
+                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | sweep-explicit | sweep-kmb | "
                          "adjoint-cylinder | stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline step only (no secondary sections)")
