@@ -2469,9 +2469,19 @@ int zbicgstab_solve_batched(hz_handle* h, hz_stream stream, int nsys, int n, int
                        static_cast<char*>(ws), infos);
 }
 
+// A sweep of more than kSweepGroup systems runs as groups of up to
+// kSweepGroup systems of neighbouring wavenumbers, one group after another:
+// each group's solve (BL = 16 lanes per row) and its b and x columns.
+size_t sweep_group_bytes(int n, int nnz, int flags) {
+    const size_t cols = align_up(sizeof(double2) * size_t(n > 0 ? n : 1) * hz::kSweepGroup);
+    return multi_layout(hz::kSweepGroup, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, true, nullptr, nullptr) +
+           2 * cols;
+}
+
 size_t zbicgstab_sweep_workspace_bytes(int nsys, int n, int nnz, int flags) {
     if (nsys < 1 || nsys > hz::kMultiMax || n < 0 || nnz < 0) return 0;
-    return multi_layout(nsys, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, true, nullptr, nullptr);
+    const size_t one = multi_layout(nsys, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, true, nullptr, nullptr);
+    return nsys > hz::kSweepGroup ? std::max(one, sweep_group_bytes(n, nnz, flags)) : one;
 }
 
 int zbicgstab_solve_sweep(hz_handle* h, hz_stream stream, int nsys, int n, int nnz, const int* rp, const int* ci,
@@ -2504,8 +2514,53 @@ int zbicgstab_solve_sweep(hz_handle* h, hz_stream stream, int nsys, int n, int n
     mv.M = M;
     mv.Bm = Bmat;
     mv.ks = ks;
-    return solve_multi(h, s, nsys, n, nnz, rp, ci, mv, reinterpret_cast<const double2*>(b),
-                       reinterpret_cast<double2*>(x), rtol, maxiter, flags, static_cast<char*>(ws), infos);
+    if (nsys <= hz::kSweepGroup)
+        return solve_multi(h, s, nsys, n, nnz, rp, ci, mv, reinterpret_cast<const double2*>(b),
+                           reinterpret_cast<double2*>(x), rtol, maxiter, flags, static_cast<char*>(ws), infos);
+    // Groups of up to kSweepGroup systems in order of wavenumber (ties by index), solved one after another:
+    // the systems of a group need similar iteration counts, so few lanes idle while a group finishes, and a
+    // group's gathered columns (16 systems x 16 bytes per row) stay in the XCD's L2.  Each system still runs
+    // its own BiCGStab; only the launch grouping and the partial-sum trees differ from one wide batch.
+    std::vector<int> order(nsys);
+    for (int j = 0; j < nsys; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [ks](int u, int v) { return ks[u] < ks[v]; });
+    char* base = static_cast<char*>(ws);
+    const size_t cols = align_up(sizeof(double2) * size_t(n) * hz::kSweepGroup);
+    double2* bg = reinterpret_cast<double2*>(base);
+    double2* xg = reinterpret_cast<double2*>(base + cols);
+    char* gws = base + 2 * cols;
+    const int ngroups = (nsys + hz::kSweepGroup - 1) / hz::kSweepGroup;
+    int worst = HZ_OK;
+    for (int g = 0; g < ngroups; ++g) {
+        // near-equal groups (sizes differ by at most one)
+        const int j0 = int(int64_t(nsys) * g / ngroups), j1 = int(int64_t(nsys) * (g + 1) / ngroups);
+        const int Bg = j1 - j0;
+        hz::GroupCols idx{};
+        double kg[hz::kSweepGroup];
+        for (int k = 0; k < Bg; ++k) {
+            idx.j[k] = order[j0 + k];
+            kg[k] = ks[order[j0 + k]];
+        }
+        const dim3 grid = grid1(int64_t(n) * Bg);
+        hipLaunchKernelGGL(hz::k_m_cols, grid, dim3(kBlock), 0, s, n, nsys, Bg, idx,
+                           reinterpret_cast<const double2*>(b), bg, 0);
+        if (!(flags & HZ_X0_ZERO))
+            hipLaunchKernelGGL(hz::k_m_cols, grid, dim3(kBlock), 0, s, n, nsys, Bg, idx,
+                               static_cast<const double2*>(reinterpret_cast<double2*>(x)), xg, 0);
+        HZ_HIP(hipGetLastError());
+        MultiVals mg = mv;
+        mg.ks = kg;
+        hz_solve_info gi[hz::kSweepGroup];
+        rc = solve_multi(h, s, Bg, n, nnz, rp, ci, mg, bg, xg, rtol, maxiter, flags, gws, gi);
+        if (rc < 0) return rc;
+        hipLaunchKernelGGL(hz::k_m_cols, grid, dim3(kBlock), 0, s, n, nsys, Bg, idx, static_cast<const double2*>(xg),
+                           reinterpret_cast<double2*>(x), 1);
+        HZ_HIP(hipGetLastError());
+        for (int k = 0; k < Bg; ++k) infos[order[j0 + k]] = gi[k];
+        worst = std::max(worst, rc);
+    }
+    HZ_HIP(hipStreamSynchronize(s));
+    return worst;
 }
 
 size_t zbicgstab_mixed_workspace_bytes(int n, int nnz, int flags) {

@@ -581,4 +581,22 @@ __global__ HZ_STREAM_BOUNDS void k_m_grad_vals(const MultiArgs a, const double2*
     }
 }
 
+// Columns of a system-minor [n][B] array for a group of Bg <= kSweepGroup
+// systems: gather (dir 0) dst[i*Bg + k] = src[i*B + idx[k]], or scatter
+// (dir 1) dst[i*B + idx[k]] = src[i*Bg + k].
+constexpr int kSweepGroup = 16;
+struct GroupCols {
+    int j[kSweepGroup];
+};
+__global__ __launch_bounds__(kBlock) void k_m_cols(int n, int B, int Bg, GroupCols idx, const double2* __restrict__ src,
+                                                   double2* __restrict__ dst, int dir) {
+    const int64_t f = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (f >= (int64_t)n * Bg) return;
+    const int64_t i = f / Bg;
+    const int k = (int)(f % Bg);
+    const int64_t w = i * B + idx.j[k];
+    if (dir == 0) dst[f] = src[w];
+    else dst[w] = src[f];
+}
+
 }  // namespace hz

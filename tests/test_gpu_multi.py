@@ -201,6 +201,33 @@ def test_sweep_initial_guess_and_invalid_wavenumber(hz):
     assert e.value.code == -1
 
 
+def test_sweep_of_more_than_16_systems_runs_in_groups(hz):
+    """More than 16 wavenumbers run as groups of neighbouring wavenumbers, one group after another: every member
+    meets the tolerance (oracle product), agrees with the explicit-value batch, uses its initial guess, and
+    permuting the systems permutes the results bitwise (the groups follow the sorted wavenumbers)."""
+    B = 20
+    A, vals, rhs, ks, info = W.config_freq_sweep(B=B, h=0.12, kmin=3.0, kmax=9.0, seed=8)
+    flags = hz.PRECOND_JACOBI
+    xs, infos = solve_sweep(hz, A, info, ks, rhs, 1e-10, flags)
+    xe, _ = solve_multi(hz, A, vals, rhs, 1e-10, flags)
+    for j in range(B):
+        Aj = A.with_vals(vals[j])
+        assert infos[j]["status"] == hz.OK, infos[j]
+        assert true_relres(Aj, xs[j], rhs[j]) <= 1e-10 * (1 + 1e-3)
+        assert np.linalg.norm(xs[j] - xe[j]) / np.linalg.norm(xe[j]) < 1e-7
+    perm = np.random.default_rng(3).permutation(B)
+    xp, ip = solve_sweep(hz, A, info, ks[perm], rhs[perm], 1e-10, flags)
+    for k, j in enumerate(perm):
+        assert np.array_equal(xp[k].view(np.float64), xs[j].view(np.float64))
+        assert ip[k]["iterations"] == infos[j]["iterations"]
+    # a warm start from a loose solve takes fewer iterations in every group
+    xa, _ = solve_sweep(hz, A, info, ks, rhs, 1e-4, flags)
+    xw, iw = solve_sweep(hz, A, info, ks, rhs, 1e-10, flags, x0=np.stack(xa))
+    for j in range(B):
+        assert iw[j]["status"] == hz.OK and iw[j]["iterations"] < infos[j]["iterations"]
+        assert true_relres(A.with_vals(vals[j]), xw[j], rhs[j]) <= 1e-10 * (1 + 1e-3)
+
+
 def test_full_size_cylinder_sweep_from_three_matrices(hz):
     """64 wavenumbers k ~ U[10, 40] on the cylinder (n=209,777) from K, M, B: Jacobi-BiCGStab to 1e-8 each."""
     A, vals, rhs, ks, info = W.config_freq_sweep(B=64)
