@@ -199,6 +199,23 @@ int pick_lanes(const hz_handle* h, const int* rp, const int* ci, int n, int64_t 
     return rule_lanes(n, nnz);
 }
 
+// The lane count of a one-system FP64 solve: pick_lanes, except that a
+// matrix whose values exceed half of the 256 MB Infinity Cache (so that every
+// product streams them from HBM) runs the block-tile row loop (L = 1) unless
+// HZ_SPMV_LANES or the autotuner decided for these arrays.  Measured on the
+// 291 MB cabin: 241 against 254 us per BiCGStab iteration, 490 against 556 ms
+// for TFQMR to 1e-10; on the 49 MB cylinder, which stays in the cache, vector
+// rows are faster (48 against 63 us), and complex64 products stay on rows.
+constexpr int64_t kTileSolveBytes = int64_t(128) << 20;
+int solve_lanes(const hz_handle* h, const int* rp, const int* ci, int n, int64_t nnz) {
+    bool decided = std::getenv("HZ_SPMV_LANES") != nullptr;
+    if (!decided && h != nullptr)
+        for (const TuneEntry& t : h->tune)
+            if (t.rp == rp && t.ci == ci && t.n == n && t.nnz == nnz) decided = true;
+    if (!decided && 16 * nnz > kTileSolveBytes) return 1;
+    return pick_lanes(h, rp, ci, n, nnz);
+}
+
 // The standalone product's plan: HZ_SPMV_FORM ("rows" / "tiles") and
 // HZ_SPMV_LANES if set, else the autotuned plan, else pipelined rows with the
 // lane rule.
@@ -612,7 +629,7 @@ int solve_fp64(hz_handle* h, hipStream_t s, int nsys, const int* row_off, int nn
     // direct (allocation-free solve): kernels only, no memset, no graph capture
     const int n = row_off[nsys] - row_off[0];
     const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
-    const int L = pick_lanes(h, rp, ci, n, nnz);
+    const int L = nsys == 1 ? solve_lanes(h, rp, ci, n, nnz) : pick_lanes(h, rp, ci, n, nnz);
     const WorkMap m = build_map(nsys, row_off, L);
     SolveWs w;
     ws_layout<double>(n, nnz, jacobi, nsys, m.G, ws, &w);
@@ -1034,7 +1051,7 @@ int solve_l(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const in
             const double2* bd, double2* xd, int ell, double rtol, int maxcycles, int flags, char* ws,
             hz_solve_info* info) {
     const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
-    const int L = pick_lanes(h, rp, ci, n, nnz);
+    const int L = solve_lanes(h, rp, ci, n, nnz);
     const int row_off[2] = {0, n};
     const WorkMap m = build_map(1, row_off, L);
     LWs w;
@@ -1215,7 +1232,7 @@ size_t qsolve_ws_bytes(int n, int64_t nnz, int flags) {
 int solve_q(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const int* ci, const double2* A,
             const double2* bd, double2* xd, double rtol, int maxiter, int flags, char* ws, hz_solve_info* info) {
     const bool jacobi = (flags & HZ_PRECOND_JACOBI) != 0;
-    const int L = pick_lanes(h, rp, ci, n, nnz);
+    const int L = solve_lanes(h, rp, ci, n, nnz);
     const int row_off[2] = {0, n};
     const WorkMap m = build_map(1, row_off, L);
     QWs w;

@@ -331,8 +331,9 @@ __device__ __forceinline__ cx<T> row_partial(int beg, int end, int lane, const i
 // row sum the row out of LDS in entry order; epi(row, total) runs in the
 // first thread of each row.  Each load instruction reads kBlock consecutive
 // entries, whole cache lines, where the vector form reads a row's few
-// entries per lane group.  A tile with more than kSolTileCap entries is done
-// as vector rows.  The trip count is uniform across the block.
+// entries per lane group, so its loads carry the streaming hint (ld_mat).  A
+// tile with more than kSolTileCap entries is done as vector rows.  The trip
+// count is uniform across the block.
 constexpr int kSolTileLanes = 4;
 constexpr int kSolTileRows = kBlock / kSolTileLanes;
 constexpr int kSolTilePer = 4;
@@ -359,12 +360,12 @@ __device__ __forceinline__ void for_tiles(const Rows& rw, const int* __restrict_
 #pragma unroll
             for (int k = 0; k < kSolTilePer; ++k) {
                 const int p = e0 + t + k * kBlock;
-                c[k] = ci[p < last ? p : last];
+                c[k] = ld_mat(ci + (p < last ? p : last));
             }
 #pragma unroll
             for (int k = 0; k < kSolTilePer; ++k) {
                 const int p = e0 + t + k * kBlock;
-                v[k] = vals[p < last ? p : last];
+                v[k] = ld_mat(vals + (p < last ? p : last));
             }
 #pragma unroll
             for (int k = 0; k < kSolTilePer; ++k) o[k] = op(c[k]);
