@@ -119,8 +119,9 @@ enum { HZ_SPMV_FORM_ROWS = 0, HZ_SPMV_FORM_TILES = 1 };
 
 /*
  * Autotuner of the launch shapes for one matrix.  Two choices are made:
- *  - the lanes per row L (2 ... 64, so 64/L rows per wavefront) of the
- *    solver kernels' fused row products, timed on that row product;
+ *  - the lanes per row L (2 ... 64, so 64/L rows per wavefront, or 1 for
+ *    the block-tile row loop) of the solver kernels' fused row products,
+ *    timed on that row product;
  *  - the form of the standalone product (csr_zspmv, csr_cspmv,
  *    csr_zspmv_rect): vector rows with each L, or block tiles.
  * Each candidate is timed on the caller's matrix and vectors (two rounds of
@@ -139,6 +140,18 @@ enum { HZ_SPMV_FORM_ROWS = 0, HZ_SPMV_FORM_TILES = 1 };
  */
 int hz_autotune_spmv(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,
                      const hz_c128 *vals, const hz_c128 *x, hz_c128 *y, int *lanes, int *form, int *form_lanes);
+
+/*
+ * Records launch shapes for one matrix without timing them, as if
+ * hz_autotune_spmv had chosen them (a tuning cache kept across processes
+ * calls this with the choice it stored for a matrix of the same shape):
+ * lanes is the solver kernels' lane count (1 for the block-tile row loop,
+ * or 2 ... 64), form HZ_SPMV_FORM_ROWS with form_lanes 2 ... 64, or
+ * HZ_SPMV_FORM_TILES with form_lanes 4.  Host-only; returns HZ_ERR_INVALID
+ * for other values.
+ */
+int hz_autotune_set(hz_handle *handle, int n, int nnz, const int *row_ptr, const int *col_idx, int lanes, int form,
+                    int form_lanes);
 
 /* Same product with complex64 values, vectors and arithmetic. */
 int csr_cspmv(hz_handle *handle, hz_stream stream, int n, int nnz, const int *row_ptr, const int *col_idx,

@@ -84,6 +84,7 @@ SIGNATURES = {
     "zbicgstab_solve_mixed": (I, [P, P, I, I, P, P, P, P, P, D, D, I, I, I, P, SZ, C.POINTER(HzInfo)]),
     "csr_reorder_workspace_bytes": (SZ, [I, I]),
     "hz_autotune_spmv": (I, [P, P, I, I, P, P, P, P, P, C.POINTER(I), C.POINTER(I), C.POINTER(I)]),
+    "hz_autotune_set": (I, [P, I, I, P, P, I, I, I]),
     "zbicgstab_adjoint_batched_workspace_bytes": (SZ, [I, I, I, I]),
     "zbicgstab_adjoint_batched": (I, [P, P, I, I, I, P, P, P, P, P, P, P, D, I, I, P, SZ, P]),
     "csr_level_order": (I, [P, P, I, I, P, P, P, P, P, P, SZ]),

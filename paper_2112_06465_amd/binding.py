@@ -96,14 +96,60 @@ def csr_zspmv(row_ptr, col_idx, vals, x, y=None):
     return y
 
 
-def autotune_spmv(row_ptr, col_idx, vals, x=None, details=False):
+def _tune_key(row_ptr, col_idx, n, nnz):
+    """Shape of a matrix for the tuning cache: device, n, nnz, longest row, default HYB width."""
+    mx, width = csr_row_stats(row_ptr)
+    name = torch.cuda.get_device_properties(row_ptr.device).name
+    return f"{name}|n={n}|nnz={nnz}|maxrow={mx}|hyb={width}"
+
+
+def _read_cache(path):
+    import json
+
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _write_cache(path, d):
+    import json
+    import os
+
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def autotune_spmv(row_ptr, col_idx, vals, x=None, details=False, cache=None):
     """Time the launch shapes on this matrix and keep the fastest for it (hz_autotune_spmv).
 
     Returns the solver kernels' lane count; with details=True a dict with
     that count ("lanes"), the standalone product's form ("form": "rows" or
-    "tiles") and its lane count ("form_lanes").
+    "tiles") and its lane count ("form_lanes").  With ``cache`` (a JSON file
+    path; default: the HZ_TUNE_CACHE environment variable) a choice stored
+    for a matrix of the same shape (device, n, nnz, longest row, default HYB
+    width) is recorded with hz_autotune_set instead of timing, and a new
+    choice is added to the file.
     """
+    import os
+
     dev, n, nnz = _csr(row_ptr, col_idx, vals, torch.complex128)
+    cache = cache if cache is not None else os.environ.get("HZ_TUNE_CACHE")
+    key = None
+    if cache:
+        key = _tune_key(row_ptr, col_idx, n, nnz)
+        hit = _read_cache(cache).get(key)
+        if hit is not None:
+            rc = load().hz_autotune_set(handle(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+                                        int(hit["lanes"]), 1 if hit["form"] == "tiles" else 0, int(hit["form_lanes"]))
+            _check("hz_autotune_set", rc)
+            out = {"lanes": int(hit["lanes"]), "form": hit["form"], "form_lanes": int(hit["form_lanes"]),
+                   "cached": True}
+            return out if details else out["lanes"]
     if x is None:
         g = torch.Generator(device="cpu").manual_seed(0)
         x = torch.randn(n, dtype=torch.complex128, generator=g).to(dev)
@@ -115,9 +161,12 @@ def autotune_spmv(row_ptr, col_idx, vals, x=None, details=False):
     rc = load().hz_autotune_spmv(handle(dev), _stream(dev), n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
                                  vals.data_ptr(), x.data_ptr(), y.data_ptr(), C.byref(L), C.byref(F), C.byref(FL))
     _check("hz_autotune_spmv", rc)
-    if details:
-        return {"lanes": int(L.value), "form": ("rows", "tiles")[F.value], "form_lanes": int(FL.value)}
-    return int(L.value)
+    out = {"lanes": int(L.value), "form": ("rows", "tiles")[F.value], "form_lanes": int(FL.value), "cached": False}
+    if key is not None:
+        d = _read_cache(cache)
+        d[key] = {k: out[k] for k in ("lanes", "form", "form_lanes")}
+        _write_cache(cache, d)
+    return out if details else out["lanes"]
 
 
 def csr_cspmv(row_ptr, col_idx, vals, x, y=None):

@@ -2075,6 +2075,25 @@ int hz_handle_destroy(hz_handle* h) {
     return HZ_OK;
 }
 
+int hz_autotune_set(hz_handle* h, int n, int nnz, const int* rp, const int* ci, int lanes, int form,
+                    int form_lanes) {
+    if (h == nullptr || n < 0 || nnz < 0) return HZ_ERR_INVALID;
+    if (n > 0 && (rp == nullptr || (nnz > 0 && ci == nullptr))) return HZ_ERR_INVALID;
+    auto lane_ok = [](int v) { return v == 2 || v == 4 || v == 8 || v == 16 || v == 32 || v == 64; };
+    if (!(lanes == 1 || lane_ok(lanes))) return HZ_ERR_INVALID;
+    if (form == SP_PIPE) {
+        if (!lane_ok(form_lanes)) return HZ_ERR_INVALID;
+    } else if (form == SP_TILE) {
+        if (form_lanes != hz::kTileLanes) return HZ_ERR_INVALID;
+    } else {
+        return HZ_ERR_INVALID;
+    }
+    for (auto it = h->tune.begin(); it != h->tune.end();)
+        it = (it->rp == rp && it->ci == ci && it->n == n && it->nnz == nnz) ? h->tune.erase(it) : it + 1;
+    h->tune.push_back(TuneEntry{rp, ci, n, nnz, lanes, SpPlan{form, form_lanes}});
+    return HZ_OK;
+}
+
 static int spmv_common_checks(hz_handle* h, int n, int nnz, const int* rp, const int* ci, const void* vals,
                               const void* x, void* y, size_t esz) {
     if (h == nullptr) return HZ_ERR_INVALID;

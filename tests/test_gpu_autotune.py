@@ -45,7 +45,7 @@ def test_tuned_lanes_are_used_bitwise_and_only_for_that_matrix(hz):
     os.environ.pop("HZ_SPMV_LANES", None)
     rule = hz.csr_zspmv(rp.clone(), ci.clone(), v, x).cpu().numpy()  # fresh index arrays: never tuned
     tune = hz.autotune_spmv(rp, ci, v, x, details=True)
-    assert tune["lanes"] in (2, 4, 8, 16, 32, 64) and tune["form_lanes"] in (2, 4, 8, 16, 32, 64)
+    assert tune["lanes"] in (1, 2, 4, 8, 16, 32, 64) and tune["form_lanes"] in (2, 4, 8, 16, 32, 64)
     assert tune["form"] in ("rows", "tiles")
     y = hz.csr_zspmv(rp, ci, v, x).cpu().numpy()
     yf = forced(hz, tune["form_lanes"], rp, ci, v, x, form=tune["form"])
@@ -86,3 +86,30 @@ def test_autotune_of_an_empty_matrix_and_return_forms(hz):
     tune = hz.autotune_spmv(rp, ci, v, dev(np.ones(3, complex)), details=True)
     assert tune["form"] == "rows"
     assert np.array_equal(hz.csr_zspmv(rp, ci, v, dev(np.ones(3, complex))).cpu().numpy(), np.zeros(3))
+
+
+def test_tuning_cache_records_and_reuses_choices(hz, tmp_path):
+    """A JSON tuning cache keyed by the matrix's shape: the first call times and stores, a call for other index
+    arrays of the same shape records the stored choice without timing, and that choice is the one used."""
+    import json
+
+    A, _, _ = W.config_cube(24, seed=3)
+    rp, ci, v = dev(A.row_ptr), dev(A.col_idx), dev(A.vals)
+    x = dev(np.random.default_rng(2).standard_normal(A.n) + 0j)
+    path = str(tmp_path / "tune.json")
+    t1 = hz.autotune_spmv(rp, ci, v, x, details=True, cache=path)
+    assert t1["cached"] is False
+    stored = json.load(open(path))
+    assert len(stored) == 1
+    (entry,) = stored.values()
+    assert entry == {k: t1[k] for k in ("lanes", "form", "form_lanes")}
+    rp2, ci2 = rp.clone(), ci.clone()
+    t2 = hz.autotune_spmv(rp2, ci2, v, x, details=True, cache=path)
+    assert t2["cached"] is True and {k: t2[k] for k in entry} == entry
+    y = hz.csr_zspmv(rp2, ci2, v, x).cpu().numpy()
+    yf = forced(hz, t2["form_lanes"], rp2, ci2, v, x, form=t2["form"])
+    assert np.array_equal(y.view(np.float64), yf.view(np.float64))
+    L = hz.load()
+    h = hz.handle(torch.device("cuda:0"))
+    for lanes, form, fl in ((3, 0, 8), (8, 0, 5), (8, 1, 8), (8, 2, 8)):
+        assert L.hz_autotune_set(h, A.n, A.nnz, rp2.data_ptr(), ci2.data_ptr(), lanes, form, fl) == -1
