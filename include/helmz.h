@@ -159,17 +159,22 @@ int csr_cspmv(hz_handle *handle, hz_stream stream, int n, int nnz, const int *ro
 
 /*
  * *out = sum_i conj(x_i) y_i (Section 5, dot product; the first argument is
- * conjugated).  out is a device pointer; nothing is synchronised.  Block
- * partials in the handle's buffer, then a one-block kernel adds them in
- * index order, so the sum order is fixed for a given n and repeated calls
- * are bitwise identical.  zdotc, dznrm2 and hz_stream_read share the
- * handle's partials: calls on one handle must not overlap in time (one
- * stream, or serialised streams).
+ * conjugated).  out is a device pointer; nothing is synchronised.  One
+ * launch: each block publishes its total in a slot of the handle (an
+ * agent-scope atomic store), the grid's last block waits for every slot and
+ * adds the totals in index order, so the sum order is fixed for a given n
+ * and repeated calls are bitwise identical.  The wait is bounded (2 s of the
+ * device clock, or HZ_B1_WAIT_TICKS ticks read at hz_handle_create; 0 gives
+ * up at once): a wait that gives up writes NaN and leaves the handle's
+ * reductions broken, every later zdotc and dznrm2 on it writing NaN, until
+ * the handle is destroyed.  zdotc and dznrm2 share the handle's slots and
+ * hz_stream_read its partials: calls on one handle must not overlap in time
+ * (one stream, or serialised streams).
  */
 int zdotc(hz_handle *handle, hz_stream stream, int n, const hz_c128 *x, const hz_c128 *y, hz_c128 *out);
 
 /* *out = ||x||_2 = sqrt(sum |x_i|^2) (Section 5, norm), device pointer;
- * partials and a finishing kernel as for zdotc. */
+ * one launch, slots and bounded wait as for zdotc. */
 int dznrm2(hz_handle *handle, hz_stream stream, int n, const hz_c128 *x, double *out);
 
 /* y <- alpha x + y (Section 5, complex axpy); alpha by value; x may equal

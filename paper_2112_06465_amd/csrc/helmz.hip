@@ -79,6 +79,7 @@ struct hz_handle {
     hipStream_t cap;                 // stream the iteration graphs are captured on (never runs work)
     std::vector<GraphEntry> graphs;  // cached iteration graphs, newest last
     double* part;          // kParts * kMaxGrid partials for standalone reductions
+    hz::B1Slots b1;        // zdotc / dznrm2 slots, armed at creation
     int* dflag;            // device word for CSR validation
     unsigned long long* dcount;  // device counter for the locality test
     unsigned long long* hcount;  // pinned host copy
@@ -2037,6 +2038,26 @@ const char* hz_strerror(int code) {
     }
 }
 
+// Slots of the one-launch reductions: 2 kB1MaxGrid words, then the broken
+// word; all armed (and synchronised) before the handle is returned.  The
+// last block waits at most 2 s of the device's wall clock for the others
+// (HZ_B1_WAIT_TICKS overrides the limit in ticks; 0 makes every wait give up
+// at once, the failure path, for tests).
+static int b1_arm(hz_handle* h) {
+    const size_t words = 2 * size_t(hz::kB1MaxGrid);
+    HZ_HIP(hipMalloc(reinterpret_cast<void**>(&h->b1.slot), words * sizeof(unsigned long long) + 256));
+    h->b1.broken = reinterpret_cast<unsigned*>(h->b1.slot + words);
+    int khz = 0;
+    HZ_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device));
+    h->b1.limit = (khz > 0 ? static_cast<unsigned long long>(khz) : 100000ull) * 2000ull;
+    if (const char* e = std::getenv("HZ_B1_WAIT_TICKS")) h->b1.limit = std::strtoull(e, nullptr, 10);
+    hipLaunchKernelGGL(hz::k_b1_arm, dim3((words + hz::kB1Block - 1) / hz::kB1Block), dim3(hz::kB1Block), 0, nullptr,
+                       h->b1);
+    HZ_HIP(hipGetLastError());
+    HZ_HIP(hipStreamSynchronize(nullptr));
+    return HZ_OK;
+}
+
 int hz_handle_create(hz_handle** out) {
     if (out == nullptr) return HZ_ERR_INVALID;
     *out = nullptr;
@@ -2052,7 +2073,8 @@ int hz_handle_create(hz_handle** out) {
         hipHostMalloc(reinterpret_cast<void**>(&h->hsc), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&h->hsc2), sizeof(SolverScal), hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
-        hipGetSymbolAddress(&h->scratch_dev, HIP_SYMBOL(scratch)) != hipSuccess || h->scratch_dev == nullptr) {
+        hipGetSymbolAddress(&h->scratch_dev, HIP_SYMBOL(scratch)) != hipSuccess || h->scratch_dev == nullptr ||
+        b1_arm(h) != HZ_OK) {
         hz_handle_destroy(h);
         return HZ_ERR_HIP;
     }
@@ -2063,6 +2085,7 @@ int hz_handle_create(hz_handle** out) {
 int hz_handle_destroy(hz_handle* h) {
     if (h == nullptr) return HZ_OK;
     if (h->part) (void)hipFree(h->part);
+    if (h->b1.slot) (void)hipFree(h->b1.slot);
     if (h->dflag) (void)hipFree(h->dflag);
     if (h->dcount) (void)hipFree(h->dcount);
     if (h->hcount) (void)hipHostFree(h->hcount);
@@ -2214,10 +2237,8 @@ int zdotc(hz_handle* h, hz_stream stream, int n, const hz_c128* x, const hz_c128
     if (misaligned(x, 16) || misaligned(y, 16) || misaligned(out, 16)) return HZ_ERR_INVALID;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const hz::B1Shape sh = hz::b1_shape(n);
-    static_assert(2 * hz::kB1MaxGrid <= kParts * kMaxGrid, "partials of zdotc fit the handle's buffer");
     hipLaunchKernelGGL(hz::k_zdot_s<0>, dim3(sh.G), dim3(hz::kB1Block), 0, s, int64_t(n), sh.per,
-                       reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(y), h->part);
-    hipLaunchKernelGGL(hz::k_zdot_fin<0>, dim3(1), dim3(hz::kB1Block), 0, s, static_cast<const double*>(h->part), sh.G,
+                       reinterpret_cast<const double2*>(x), reinterpret_cast<const double2*>(y), h->b1,
                        static_cast<void*>(out));
     HZ_HIP(hipGetLastError());
     return HZ_OK;
@@ -2230,8 +2251,7 @@ int dznrm2(hz_handle* h, hz_stream stream, int n, const hz_c128* x, double* out)
     hipStream_t s = static_cast<hipStream_t>(stream);
     const hz::B1Shape sh = hz::b1_shape(n);
     hipLaunchKernelGGL(hz::k_zdot_s<1>, dim3(sh.G), dim3(hz::kB1Block), 0, s, int64_t(n), sh.per,
-                       reinterpret_cast<const double2*>(x), static_cast<const double2*>(nullptr), h->part);
-    hipLaunchKernelGGL(hz::k_zdot_fin<1>, dim3(1), dim3(hz::kB1Block), 0, s, static_cast<const double*>(h->part), sh.G,
+                       reinterpret_cast<const double2*>(x), static_cast<const double2*>(nullptr), h->b1,
                        static_cast<void*>(out));
     HZ_HIP(hipGetLastError());
     return HZ_OK;

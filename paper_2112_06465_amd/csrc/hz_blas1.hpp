@@ -6,14 +6,33 @@
 // issuing its kB1U loads of a chunk straight-line and non-temporal (every
 // instruction reads 256 consecutive elements, whole cache lines) before using
 // any of them.  A ragged tail is handled by the last block with guarded
-// accesses.  A reduction writes one partial per block (per thread in element
-// order, a wave tree, then the block's waves in order) and a one-block kernel
-// adds the partials in index order.  (Finishing in the same launch, the last
-// block to take an integer ticket adding the partials, needs a device-scope
-// release fence in every block; on this multi-XCD part each such fence writes
-// back and invalidates the XCD's L2, and the one-launch dot product measured
-// 10x slower than two launches.)  No floating-point atomics: results are
-// bitwise reproducible.
+// accesses.
+//
+// A reduction finishes in the same launch without a memory fence.  Each block
+// sums its elements in a fixed order (per thread in element order, a wave
+// tree, then the block's waves in order) and publishes the total with one
+// agent-scope atomic store into a slot of its own, a 64-bit word that holds a
+// signalling-NaN marker while empty.  The last block of the grid reads every
+// slot with agent-scope atomic loads until none holds the marker, adds the
+// totals in index order, writes the result and puts the marker back.  Only the
+// coherence of each single word is relied on (a load of a word that was stored
+// once returns the stored value or an older one, never a mix), so no release
+// or acquire ordering between different words is needed.  (The alternative, a
+// ticket counter with a device-scope release fence in every block, writes back
+// the XCD's L2 on this multi-XCD part: that dot product measured 1.6 to 2.4
+// times slower than two launches, and two launches 1.3 times slower than the
+// slots in a captured graph.)  A computed total that is a NaN is stored as the
+// quiet NaN, so no total can equal the marker.  No floating-point atomics:
+// results are bitwise reproducible and equal to a sum of the same partials
+// by a separate finishing kernel.
+//
+// The last block's wait ends when all blocks have stored, which needs only
+// that they are scheduled; as a guard it also ends after `limit` ticks of the
+// constant-rate wall clock.  A wait that ends that way writes a NaN result and
+// sets the handle's broken word: every later reduction on the handle then
+// writes NaN without waiting (a late store could otherwise leave a stale total
+// in a slot), until the slots are armed again.  A limit of 0 takes that path
+// at once, so that it can be exercised without a stalled block.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -80,13 +99,38 @@ __global__ __launch_bounds__(kB1Block) void k_zaxpy_s(int64_t n, int per, double
   }
 }
 
-// Block partials of K components: part[k G + b].  MODE 0: conj(x_i) y_i
-// (K = 2); MODE 1: |x_i|^2 (K = 1).
+constexpr unsigned long long kB1SlotEmpty = 0x7ff4dead0000beefull;  // a signalling NaN no arithmetic yields
+
+__device__ __forceinline__ unsigned long long b1_slot_bits(double v) {
+    if (v != v) v = __builtin_nan("");
+    return static_cast<unsigned long long>(__double_as_longlong(v));
+}
+
+// Slots (2 kB1MaxGrid words) and the broken word of a handle.
+struct B1Slots {
+    unsigned long long* slot;
+    unsigned* broken;
+    unsigned long long limit;  // wall-clock ticks the last block waits at most; 0: give up at once
+};
+
+// Marks every slot empty and clears the broken word.
+__global__ __launch_bounds__(kB1Block) void k_b1_arm(B1Slots s) {
+    const int i = blockIdx.x * kB1Block + threadIdx.x;
+    if (i < 2 * kB1MaxGrid) s.slot[i] = kB1SlotEmpty;
+    if (i == 0) *s.broken = 0u;
+}
+
+// MODE 0: *out = sum conj(x_i) y_i (complex, K = 2 components); MODE 1:
+// *out = sqrt(sum |x_i|^2) (K = 1).  Block b's total of component k goes to
+// slot k G + b.
 template <int MODE>
 __global__ __launch_bounds__(kB1Block) void k_zdot_s(int64_t n, int per, const double2* __restrict__ x,
-                                                     const double2* __restrict__ y, double* __restrict__ part) {
+                                                     const double2* __restrict__ y, B1Slots sl, void* out) {
     constexpr int K = MODE == 0 ? 2 : 1;
     const int G = gridDim.x;
+    // a previous wait that timed out: no slot is trusted any more (read early, used at the end)
+    const unsigned broken = threadIdx.x == 0 ? __hip_atomic_load(sl.broken, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                             : 0u;
     double e[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) e[k] = 0.0;
@@ -121,6 +165,7 @@ __global__ __launch_bounds__(kB1Block) void k_zdot_s(int64_t n, int per, const d
         }
     }
     __shared__ double w[K][kB1Block / 64];
+    __shared__ unsigned skip;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         double v = e[k];
@@ -129,40 +174,58 @@ __global__ __launch_bounds__(kB1Block) void k_zdot_s(int64_t n, int per, const d
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        skip = broken;
+        if (!broken) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            double s = 0.0;
-            for (int q = 0; q < kB1Block / 64; ++q) s += w[k][q];
-            part[int64_t(k) * G + blockIdx.x] = s;
+            for (int k = 0; k < K; ++k) {
+                const double s = (w[k][0] + w[k][1]) + (w[k][2] + w[k][3]);
+                __hip_atomic_store(sl.slot + int64_t(k) * G + blockIdx.x, b1_slot_bits(s), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
-}
-
-// The total of G partials per component (one block), in a fixed order: each
-// thread sums partials i, i + kB1Block, ..., a wave tree combines the
-// threads, thread 0 adds the four wave totals.  MODE 0 writes the complex
-// sum, MODE 1 the square root of the sum.
-template <int MODE>
-__global__ __launch_bounds__(kB1Block) void k_zdot_fin(const double* __restrict__ part, int G, void* out) {
-    constexpr int K = MODE == 0 ? 2 : 1;
-    __shared__ double w[K][kB1Block / 64];
+    if (blockIdx.x != G - 1) return;
+    __syncthreads();  // `skip` and the reuse of w below
+    bool late = skip != 0u || sl.limit == 0;
+    const uint64_t t0 = wall_clock64();
+    double tot[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         double t = 0.0;
-        for (int i = threadIdx.x; i < G; i += kB1Block) t += part[int64_t(k) * G + i];
+        for (int i = threadIdx.x; i < G && !late; i += kB1Block) {
+            unsigned long long* p = sl.slot + int64_t(k) * G + i;
+            unsigned long long u = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while (u == kB1SlotEmpty) {
+                __builtin_amdgcn_s_sleep(1);
+                if (wall_clock64() - t0 > sl.limit) {
+                    late = true;
+                    break;
+                }
+                u = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (late) break;
+            t += __longlong_as_double(static_cast<long long>(u));
+            __hip_atomic_store(p, kB1SlotEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
-        if ((threadIdx.x & 63) == 0) w[k][threadIdx.x >> 6] = t;
+        tot[k] = t;
     }
+    const bool any_late = __syncthreads_or(late);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if ((threadIdx.x & 63) == 0) w[k][threadIdx.x >> 6] = tot[k];
     __syncthreads();
     if (threadIdx.x == 0) {
         double s[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) s[k] = (w[k][0] + w[k][1]) + (w[k][2] + w[k][3]);
+        for (int k = 0; k < K; ++k)
+            s[k] = any_late ? __builtin_nan("") : (w[k][0] + w[k][1]) + (w[k][2] + w[k][3]);
         if constexpr (MODE == 0) {
             static_cast<double2*>(out)[0] = mk<double>(s[0], s[1]);
         } else {
             static_cast<double*>(out)[0] = __builtin_sqrt(s[0]);
         }
+        if (any_late) __hip_atomic_store(sl.broken, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
