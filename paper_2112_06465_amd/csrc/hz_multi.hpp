@@ -174,6 +174,76 @@ __device__ __forceinline__ double2 mrow(const MultiArgs& a, int64_t i, int j, co
     return acc;
 }
 
+// K/M/B products stage a tile's column indices and K, M, Bm entries in LDS:
+// every lane of a row (one per system) needs the same ones, and loading them
+// per lane costs one 64-lane load instruction per entry and kind for BL times
+// fewer distinct values.  Tiles with more entries than kMTileCap read them
+// per lane as mrow does.
+constexpr int kMTileCap = 1536;
+
+// Row i of A(k_j) times X for lane j, entries [b, e) of the staged tile; the
+// same operations in the same order as mrow<U, VS_KMB>, so the results are
+// bitwise equal.
+template <int U>
+__device__ __forceinline__ double2 mrow_lds(const int* cs, const double* ks, const double* ms, const double* bs, int b,
+                                            int e, int j, size_t B, const double2* __restrict__ X, double2 k) {
+    double2 acc = mk<double>(0.0, 0.0);
+    int p = b;
+    for (; p + U <= e; p += U) {
+        int c[U];
+        double2 xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = cs[p + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = X[(size_t)c[u] * B + j];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double2 av = mk<double>(__builtin_fma(-k.y, ms[p + u], ks[p + u]), k.x * bs[p + u]);
+            acc = cfma<double>(av, xv[u], acc);
+        }
+    }
+    for (; p < e; ++p) {
+        const double2 av = mk<double>(__builtin_fma(-k.y, ms[p], ks[p]), k.x * bs[p]);
+        acc = cfma<double>(av, X[(size_t)cs[p] * B + j], acc);
+    }
+    return acc;
+}
+
+// f(i, acc) for every row i of the block on lane j when `on`, acc = row i of
+// A(k_j) times X.  The block walks its rows in tiles of kBlock / BL
+// consecutive rows (the rows and order of HZ_MROWS); a tile's entries are
+// loaded once, contiguously by the whole block, into LDS.
+template <int BL, int U, typename F>
+__device__ __forceinline__ void m_kmb_tiles(const MultiArgs& a, const RowRange& rr, bool on,
+                                            const double2* __restrict__ X, double2 k, F&& f) {
+    constexpr int S = kBlock / BL;
+    __shared__ int cs[kMTileCap];
+    __shared__ double ks[kMTileCap], ms[kMTileCap], bs[kMTileCap];
+    const int g = threadIdx.x / BL, j = threadIdx.x % BL;
+    const int* __restrict__ rp = a.row_ptr;
+    for (int64_t r0 = rr.rw.x0 + (int64_t)rr.rw.k * S; r0 < rr.rw.x1; r0 += (int64_t)rr.rw.K * S) {  // uniform
+        const int64_t re = r0 + S < rr.rw.x1 ? r0 + S : rr.rw.x1;
+        const int e0 = rp[r0], ne = rp[re] - e0;
+        const bool staged = ne <= kMTileCap;
+        if (staged) {
+            for (int q = threadIdx.x; q < ne; q += kBlock) {
+                cs[q] = a.col_idx[e0 + q];
+                ks[q] = a.K[e0 + q];
+                ms[q] = a.M[e0 + q];
+                bs[q] = a.Bm[e0 + q];
+            }
+            __syncthreads();
+        }
+        const int64_t i = r0 + g;
+        if (on && i < re) {
+            const double2 acc = staged ? mrow_lds<U>(cs, ks, ms, bs, rp[i] - e0, rp[i + 1] - e0, j, (size_t)a.B, X, k)
+                                       : mrow<2, VS_KMB>(a, i, j, X, k);
+            f(i, acc);
+        }
+        if (staged) __syncthreads();  // the tile's entries have been read
+    }
+}
+
 #define HZ_MULTI_ROWS                                       \
     constexpr int S = kBlock / BL;                          \
     const RowRange rr = rows_of_block(a.n, a.geo);          \
@@ -305,17 +375,20 @@ __global__ HZ_STREAM_BOUNDS void k_m_A1(const MultiArgs a) {
     if (all_done(a)) return;
     HZ_MULTI_ROWS;
     double e[2] = {0.0, 0.0};
-    if (j < a.B && !a.sc[j].done && !a.sc[j].pending) {
+    const bool on = j < a.B && !a.sc[j].done && !a.sc[j].pending;
+    auto row = [&](int64_t i, double2 acc) {
+        const size_t q = (size_t)i * Bz + j;
+        a.v[q] = acc;
+        const double2 w = a.rh[q];
+        const double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
+        e[0] = c.x;
+        e[1] = c.y;
+    };
+    if constexpr (VS == VS_KMB) {
+        m_kmb_tiles<BL, U>(a, rr, on, a.q, j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0), row);
+    } else if (on) {
         const double2 k = mwave<VS>(a, j);
-        HZ_MROWS(i) {
-            const double2 acc = mrow<U, VS>(a, i, j, a.q, k);
-            const size_t q = (size_t)i * Bz + j;
-            a.v[q] = acc;
-            const double2 w = a.rh[q];
-            const double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
-            e[0] = c.x;
-            e[1] = c.y;
-        }
+        HZ_MROWS(i) row(i, mrow<U, VS>(a, i, j, a.q, k));
     }
     mstore<BL, 2>(mregion<BL>(a, kPartA), a.geo.G, rr.lb, e);
 }
@@ -364,19 +437,22 @@ __global__ HZ_STREAM_BOUNDS void k_m_B1(const MultiArgs a) {
     if (all_done(a)) return;
     HZ_MULTI_ROWS;
     double e[3] = {0.0, 0.0, 0.0};
-    if (j < a.B && !a.sc[j].done) {
+    const bool on = j < a.B && !a.sc[j].done;
+    auto row = [&](int64_t i, double2 acc) {
+        const size_t q = (size_t)i * Bz + j;
+        a.t[q] = acc;
+        const double2 sv = a.s[q];
+        const double2 c = cdotacc(acc.x, acc.y, sv.x, sv.y, mk<double>(e[0], e[1]));
+        e[0] = c.x;
+        e[1] = c.y;
+        e[2] = __builtin_fma(acc.x, acc.x, e[2]);
+        e[2] = __builtin_fma(acc.y, acc.y, e[2]);
+    };
+    if constexpr (VS == VS_KMB) {
+        m_kmb_tiles<BL, U>(a, rr, on, a.u, j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0), row);
+    } else if (on) {
         const double2 k = mwave<VS>(a, j);
-        HZ_MROWS(i) {
-            const double2 acc = mrow<U, VS>(a, i, j, a.u, k);
-            const size_t q = (size_t)i * Bz + j;
-            a.t[q] = acc;
-            const double2 sv = a.s[q];
-            const double2 c = cdotacc(acc.x, acc.y, sv.x, sv.y, mk<double>(e[0], e[1]));
-            e[0] = c.x;
-            e[1] = c.y;
-            e[2] = __builtin_fma(acc.x, acc.x, e[2]);
-            e[2] = __builtin_fma(acc.y, acc.y, e[2]);
-        }
+        HZ_MROWS(i) row(i, mrow<U, VS>(a, i, j, a.u, k));
     }
     mstore<BL, 3>(mregion<BL>(a, kPartB + 1), a.geo.G, rr.lb, e);
 }
@@ -466,16 +542,19 @@ __global__ HZ_STREAM_BOUNDS void k_m_resid(const MultiArgs a, const double2* __r
     a2.vals = vals;
     double e[1] = {0.0};
     const double2 k = j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0);
-    if (j < a.B)
-        HZ_MROWS(i) {
-            const double2 acc = mrow<U, VS>(a2, i, j, xin, k);
-            const size_t q = (size_t)i * Bz + j;
-            const double2 bv = a.b[q];
-            const double2 d = mk<double>(bv.x - acc.x, bv.y - acc.y);
-            y[q] = d;
-            e[0] = __builtin_fma(d.x, d.x, e[0]);
-            e[0] = __builtin_fma(d.y, d.y, e[0]);
-        }
+    auto row = [&](int64_t i, double2 acc) {
+        const size_t q = (size_t)i * Bz + j;
+        const double2 bv = a.b[q];
+        const double2 d = mk<double>(bv.x - acc.x, bv.y - acc.y);
+        y[q] = d;
+        e[0] = __builtin_fma(d.x, d.x, e[0]);
+        e[0] = __builtin_fma(d.y, d.y, e[0]);
+    };
+    if constexpr (VS == VS_KMB) {
+        m_kmb_tiles<BL, U>(a2, rr, j < a.B, xin, k, row);
+    } else if (j < a.B) {
+        HZ_MROWS(i) row(i, mrow<U, VS>(a2, i, j, xin, k));
+    }
     mstore<BL, 1>(mregion<BL>(a, kPartI), a.geo.G, rr.lb, e);
 }
 

@@ -238,3 +238,44 @@ def test_full_size_cylinder_sweep_from_three_matrices(hz):
         assert true_relres(A.with_vals(vals[j]), xs[j], rhs[j]) <= 1e-8 * (1 + 1e-3)
         its.append(infos[j]["iterations"])
     print(f"K/M/B sweep B=64 n={A.n}: iterations min {min(its)} max {max(its)}")
+
+
+def long_row_kmb(n=3000, long_rows=(100, 2000), width=1600, seed=9):
+    """K, M, B on one pattern with two rows of `width` entries: the 64-row tiles holding them exceed the
+    1,536 entries that the K/M/B products stage in LDS, so those tiles take the per-lane path."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    offs = [-7, -1, 1, 7]
+    K = sp.diags([np.full(n, 10.0)] + [np.full(n - abs(o), -0.1) for o in offs], [0] + offs, format="lil")
+    for r in long_rows:
+        for c in rng.choice(n, size=width, replace=False):
+            if c != r:
+                K[r, c] = K[r, c] + 1e-4
+    K = K.tocsr()
+    K.sort_indices()
+    rows = np.repeat(np.arange(n), np.diff(K.indptr))
+    diag = rows == K.indices
+    M = np.where(diag, 0.1, 0.0)
+    Bv = np.where(diag, 0.05, 0.0)
+    A = CSR(K.indptr.astype(np.int32), K.indices.astype(np.int32), K.data.astype(np.complex128))
+    return A, {"K": K.data.copy(), "M": M, "B": Bv}
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_sweep_with_tiles_too_long_to_stage(hz, jacobi):
+    A, info = long_row_kmb()
+    assert np.diff(A.row_ptr).max() >= 1536
+    B = 16
+    ks = np.linspace(1.0, 2.0, B)
+    vals = np.stack([info["K"] - k * k * info["M"] + 1j * k * info["B"] for k in ks])
+    rng = np.random.default_rng(10)
+    rhs = rng.standard_normal((B, A.n)) + 1j * rng.standard_normal((B, A.n))
+    flags = hz.PRECOND_JACOBI if jacobi else hz.PRECOND_NONE
+    xs, infos = solve_sweep(hz, A, info, ks, rhs, 1e-10, flags)
+    xe, _ = solve_multi(hz, A, vals, rhs, 1e-10, flags)
+    for j in range(B):
+        Aj = A.with_vals(vals[j])
+        assert infos[j]["status"] == hz.OK, infos[j]
+        assert true_relres(Aj, xs[j], rhs[j]) <= 1e-10 * (1 + 1e-3)
+        assert np.linalg.norm(xs[j] - xe[j]) / np.linalg.norm(xe[j]) < 1e-8
