@@ -1460,7 +1460,8 @@ struct MultiVals {
 // [kParts][G][BL], the done counter, six [n][B] vectors (r, rhat, p, v, s,
 // t) and, under Jacobi, D^{-1} [n][B] plus either the column-scaled values
 // [nnz][B] (explicit values) or the scaled gather vectors q = D^{-1} p and
-// u = D^{-1} s [n][B] (a sweep); a sweep also keeps its wavenumbers [B].
+// u = D^{-1} s [n][B] and the rows' diagonal triples [n][4] (a sweep); a
+// sweep also keeps its wavenumbers [B].
 struct MultiWs {
     SolverScal* sc;
     double* part;
@@ -1470,6 +1471,7 @@ struct MultiWs {
     double2* ahat;
     double2* q;
     double2* u;
+    double* kd;
     double* kw;
 };
 
@@ -1492,6 +1494,7 @@ size_t multi_layout(int B, int n, int64_t nnz, bool jacobi, bool kmb, char* base
     w.ahat = (jacobi && !kmb) ? static_cast<double2*>(take(sizeof(double2) * zb)) : nullptr;
     w.q = (jacobi && kmb) ? static_cast<double2*>(take(sizeof(double2) * nb)) : nullptr;
     w.u = (jacobi && kmb) ? static_cast<double2*>(take(sizeof(double2) * nb)) : nullptr;
+    w.kd = (jacobi && kmb) ? static_cast<double*>(take(sizeof(double) * 4 * size_t(n > 0 ? n : 1))) : nullptr;
     w.kw = kmb ? static_cast<double*>(take(sizeof(double) * size_t(B))) : nullptr;
     if (out) *out = w;
     return off;
@@ -1580,7 +1583,9 @@ int solve_multi(hz_handle* h, hipStream_t s, int B, int n, int nnz, const int* r
         if (kmb) {
             hipLaunchKernelGGL(hz::k_m_jacobi_kmb, grid1(nB), dim3(kBlock), 0, s, n, B, rp, ci, mv.K, mv.M, mv.Bm,
                                static_cast<const double*>(w.kw), w.dinv, w.sc);
-            a.dinv = w.dinv;
+            // P and S rebuild D^{-1} from the diagonal triples (24 bytes a row for all systems, not 16 B per system)
+            hipLaunchKernelGGL(hz::k_m_diag_kmb, grid1(n), dim3(kBlock), 0, s, n, rp, ci, mv.K, mv.M, mv.Bm, w.kd);
+            a.kd = w.kd;
             a.q = w.q;
             a.u = w.u;
         } else {

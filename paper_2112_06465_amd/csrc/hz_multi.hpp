@@ -52,6 +52,7 @@ struct MultiArgs {
     const double* __restrict__ Bm;
     const double* __restrict__ kw;
     const double2* dinv;  // non-null: the products act on q = D^{-1} p and u = D^{-1} s ([n][B])
+    const double* kd;     // VS_KMB with Jacobi, instead of dinv: row i's diagonal K, M, Bm at kd[4 i .. 4 i + 2]
     const double2* b;     // [n][B]
     double2* r;
     double2* rh;
@@ -244,6 +245,16 @@ __device__ __forceinline__ void m_kmb_tiles(const MultiArgs& a, const RowRange& 
     }
 }
 
+// 1 / (K_ii - k^2 M_ii + i k Bm_ii) from the row's diagonal triple, with the
+// operations of k_m_jacobi_kmb (bitwise the value it stores in dinv).
+__device__ __forceinline__ double2 m_dinv_kmb(const double* __restrict__ kd, int64_t i, double kj) {
+    const double2 km = reinterpret_cast<const double2*>(kd)[2 * i];
+    const double bd = kd[4 * i + 2];
+    const double2 d = mk<double>(__builtin_fma(-kj * kj, km.y, km.x), kj * bd);
+    const double q = d.x * d.x + d.y * d.y;
+    return mk<double>(d.x / q, -d.y / q);
+}
+
 #define HZ_MULTI_ROWS                                       \
     constexpr int S = kBlock / BL;                          \
     const RowRange rr = rows_of_block(a.n, a.geo);          \
@@ -354,18 +365,20 @@ __global__ HZ_STREAM_BOUNDS void k_m_P(const MultiArgs a) {
         sc->beta = beta;
         sc->cur = it;
     }
+    const double kj = a.kd ? a.kw[j] : 0.0;
     HZ_MROWS(i) {
         const size_t q = (size_t)i * Bz + j;
         const double2 rv = a.r[q];
-        if (it == 1) {
-            a.p[q] = rv;
-        } else {
+        double2 pn = rv;
+        if (it != 1) {
             const double2 pv = a.p[q], vv = a.v[q];
             const double2 d = mk<double>(pv.x - __builtin_fma(om.x, vv.x, -om.y * vv.y),
                                          pv.y - __builtin_fma(om.x, vv.y, om.y * vv.x));
-            a.p[q] = cfma<double>(beta, d, rv);
+            pn = cfma<double>(beta, d, rv);
         }
-        if (a.dinv) a.q[q] = cmul<double>(a.dinv[q], a.p[q]);
+        a.p[q] = pn;
+        if (a.kd) a.q[q] = cmul<double>(m_dinv_kmb(a.kd, i, kj), pn);
+        else if (a.dinv) a.q[q] = cmul<double>(a.dinv[q], pn);
     }
 }
 
@@ -419,11 +432,13 @@ __global__ HZ_STREAM_BOUNDS void k_m_S(const MultiArgs a) {
     }
     if (go) {
         const double2 nal = mk<double>(-alpha.x, -alpha.y);
+        const double kj = a.kd ? a.kw[j] : 0.0;
         HZ_MROWS(i) {
             const size_t q = (size_t)i * Bz + j;
             const double2 sv = cfma<double>(nal, a.v[q], a.r[q]);
             a.s[q] = sv;
-            if (a.dinv) a.u[q] = cmul<double>(a.dinv[q], sv);
+            if (a.kd) a.u[q] = cmul<double>(m_dinv_kmb(a.kd, i, kj), sv);
+            else if (a.dinv) a.u[q] = cmul<double>(a.dinv[q], sv);
             e[0] = __builtin_fma(sv.x, sv.x, e[0]);
             e[0] = __builtin_fma(sv.y, sv.y, e[0]);
         }
@@ -619,6 +634,20 @@ __global__ __launch_bounds__(kBlock) void k_m_jacobi_kmb(int n, int B, const int
     }
     const double q = d.x * d.x + d.y * d.y;
     dinv[f] = mk<double>(d.x / q, -d.y / q);
+}
+
+// kd[4 i .. 4 i + 3] = (K_ii, M_ii, Bm_ii, 0): the last diagonal entry of row i
+// (the one k_m_jacobi_kmb uses), zeros if the row has none.
+__global__ __launch_bounds__(kBlock) void k_m_diag_kmb(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                       const double* __restrict__ K, const double* __restrict__ M,
+                                                       const double* __restrict__ Bm, double* __restrict__ kd) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double k = 0.0, m = 0.0, b = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (ci[p] == i) k = K[p], m = M[p], b = Bm[p];
+    reinterpret_cast<double2*>(kd)[2 * i] = mk<double>(k, m);
+    reinterpret_cast<double2*>(kd)[2 * i + 1] = mk<double>(b, 0.0);
 }
 
 // out[p*B + j] = vals[p*B + j] * dinv[col_p*B + j]   (A_j D_j^{-1})
