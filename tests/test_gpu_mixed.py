@@ -145,3 +145,20 @@ def test_reliable_updates_cylinder_full_size(hz):
     rr = true_relres(A, x.cpu().numpy(), b)
     print(f"reliable cylinder: updates={info['outer_steps']} iterations={info['iterations']} relres={rr:.2e}")
     assert rr <= 1e-10 * (1 + 1e-3)
+
+
+@pytest.mark.parametrize("reliable", [False, True])
+def test_mixed_full_size_cabin(hz, reliable):
+    """The full cabin (1.24 M rows, random numbering, renumbered inside the call) to the FP64 tolerance."""
+    A, b, _ = W.config_cabin()
+    rp, ci, v = dev_csr(A)
+    flags = hz.PRECOND_JACOBI | hz.X0_ZERO | (hz.RELIABLE if reliable else 0)
+    if reliable:
+        x, info = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-10, maxiter=50000, flags=flags)
+    else:
+        x, info = hz.zbicgstab_solve_mixed(rp, ci, v, dev(b), rtol=1e-10, inner_rtol=1e-4, maxiter=50000, flags=flags)
+    assert info["status"] == hz.OK, info
+    assert info["renumbered"] == 1
+    rr = true_relres(A, x.cpu().numpy(), b)
+    print(f"mixed cabin (reliable={reliable}): outer={info['outer_steps']} inner={info['iterations']} relres={rr:.2e}")
+    assert rr <= 1e-10 * (1 + 1e-3)
