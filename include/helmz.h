@@ -378,8 +378,12 @@ size_t zbicgstab_batched_workspace_bytes(int nsys, int n, int nnz, int flags);
 
 /*
  * Solve nsys systems A_j x_j = b_j that share one sparsity pattern (a
- * frequency sweep K - k_j^2 M + i k_j B on one mesh) in one launch sequence;
- * batching is an extension of Section 7's solve.  1 <= nsys <= 256 and
+ * frequency sweep K - k_j^2 M + i k_j B on one mesh); batching is an
+ * extension of Section 7's solve.  Up to 16 systems run in one launch
+ * sequence; more run as near-equal groups of up to 16, one group after
+ * another, in order of a diagonal key (the sum of Re A_j(i,i) over up to
+ * 1,024 evenly spaced rows; ties by index), so that in a sweep a group holds
+ * neighbouring wavenumbers with similar iteration counts.  1 <= nsys <= 256 and
  * n * nsys < 2^31.  Layout is system-minor: vals[p * nsys + j] is entry p
  * of system j (nnz * nsys values), b[i * nsys + j] and x[i * nsys + j]
  * element i of system j.  Every system runs its own preconditioned BiCGStab

@@ -2498,8 +2498,38 @@ int zbicgstab_solve_varbatch(hz_handle* h, hz_stream stream, int nsys, const int
                       static_cast<char*>(ws), infos);
 }
 
+// A batch of more than kSweepGroup systems runs as groups of up to
+// kSweepGroup systems of neighbouring diagonal keys (k_m_diag_key), one
+// group after another: the group's b, x and value columns, the keys, and
+// the group's solve (BL = 16 lanes per row).
+struct BatchGroupWs {
+    double2* bg;
+    double2* xg;
+    double2* vg;
+    double* key;
+    char* solve;
+};
+
+static size_t batch_group_layout(int n, int nnz, int flags, char* base, BatchGroupWs* out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    BatchGroupWs w{};
+    w.bg = reinterpret_cast<double2*>(take(sizeof(double2) * size_t(n > 0 ? n : 1) * hz::kSweepGroup));
+    w.xg = reinterpret_cast<double2*>(take(sizeof(double2) * size_t(n > 0 ? n : 1) * hz::kSweepGroup));
+    w.vg = reinterpret_cast<double2*>(take(sizeof(double2) * size_t(nnz > 0 ? nnz : 1) * hz::kSweepGroup));
+    w.key = reinterpret_cast<double*>(take(sizeof(double) * hz::kMultiMax));
+    w.solve = take(multi_layout(hz::kSweepGroup, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, false, nullptr, nullptr));
+    if (out) *out = w;
+    return off;
+}
+
 size_t zbicgstab_batched_workspace_bytes(int nsys, int n, int nnz, int flags) {
     if (nsys < 1 || nsys > hz::kMultiMax || n < 0 || nnz < 0) return 0;
+    if (nsys > hz::kSweepGroup) return batch_group_layout(n, nnz, flags, nullptr, nullptr);
     return multi_layout(nsys, n, nnz, (flags & HZ_PRECOND_JACOBI) != 0, false, nullptr, nullptr);
 }
 
@@ -2526,8 +2556,56 @@ int zbicgstab_solve_batched(hz_handle* h, hz_stream stream, int nsys, int n, int
     }
     MultiVals mv;
     mv.vals = reinterpret_cast<const double2*>(vals);
-    return solve_multi(h, s, nsys, n, nnz, rp, ci, mv, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x), rtol, maxiter, flags,
-                       static_cast<char*>(ws), infos);
+    if (nsys <= hz::kSweepGroup)
+        return solve_multi(h, s, nsys, n, nnz, rp, ci, mv, reinterpret_cast<const double2*>(b),
+                           reinterpret_cast<double2*>(x), rtol, maxiter, flags, static_cast<char*>(ws), infos);
+    // Groups of up to kSweepGroup systems in order of their diagonal keys (ties by index): in a frequency sweep
+    // that is the order of the wavenumbers, and neighbours need similar iteration counts, so few lanes idle
+    // while a group finishes; a group of 16 systems' values (16 nnz * 16 bytes) is read per product instead
+    // of all systems' values for as long as the slowest system runs.  Each system still runs its own BiCGStab.
+    BatchGroupWs w;
+    batch_group_layout(n, nnz, flags, static_cast<char*>(ws), &w);
+    hipLaunchKernelGGL(hz::k_m_diag_key, dim3(nsys), dim3(kBlock), 0, s, n, nsys, rp, ci,
+                       reinterpret_cast<const double2*>(vals), w.key);
+    HZ_HIP(hipGetLastError());
+    std::vector<double> key(nsys);
+    HZ_HIP(hipMemcpyAsync(key.data(), w.key, sizeof(double) * size_t(nsys), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    for (double& k : key)
+        if (!(k == k)) k = HUGE_VAL;  // a NaN key sorts last
+    std::vector<int> order(nsys);
+    for (int j = 0; j < nsys; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&key](int u, int v) { return key[u] < key[v]; });
+    const int ngroups = (nsys + hz::kSweepGroup - 1) / hz::kSweepGroup;
+    int worst = HZ_OK;
+    for (int g = 0; g < ngroups; ++g) {
+        const int j0 = int(int64_t(nsys) * g / ngroups), j1 = int(int64_t(nsys) * (g + 1) / ngroups);
+        const int Bg = j1 - j0;
+        hz::GroupCols idx{};
+        for (int k = 0; k < Bg; ++k) idx.j[k] = order[j0 + k];
+        const dim3 grid = grid1(int64_t(n) * Bg);
+        hipLaunchKernelGGL(hz::k_m_cols, grid, dim3(kBlock), 0, s, n, nsys, Bg, idx,
+                           reinterpret_cast<const double2*>(b), w.bg, 0);
+        if (!(flags & HZ_X0_ZERO))
+            hipLaunchKernelGGL(hz::k_m_cols, grid, dim3(kBlock), 0, s, n, nsys, Bg, idx,
+                               static_cast<const double2*>(reinterpret_cast<double2*>(x)), w.xg, 0);
+        if (nnz > 0)  // the group's value columns: entries play the part of rows
+            hipLaunchKernelGGL(hz::k_m_cols, grid1(int64_t(nnz) * Bg), dim3(kBlock), 0, s, nnz, nsys, Bg, idx,
+                               reinterpret_cast<const double2*>(vals), w.vg, 0);
+        HZ_HIP(hipGetLastError());
+        MultiVals mg;
+        mg.vals = w.vg;
+        hz_solve_info gi[hz::kSweepGroup];
+        rc = solve_multi(h, s, Bg, n, nnz, rp, ci, mg, w.bg, w.xg, rtol, maxiter, flags & ~HZ_VALIDATE, w.solve, gi);
+        if (rc < 0) return rc;
+        hipLaunchKernelGGL(hz::k_m_cols, grid, dim3(kBlock), 0, s, n, nsys, Bg, idx, static_cast<const double2*>(w.xg),
+                           reinterpret_cast<double2*>(x), 1);
+        HZ_HIP(hipGetLastError());
+        for (int k = 0; k < Bg; ++k) infos[order[j0 + k]] = gi[k];
+        worst = std::max(worst, rc);
+    }
+    HZ_HIP(hipStreamSynchronize(s));
+    return worst;
 }
 
 // A sweep of more than kSweepGroup systems runs as groups of up to

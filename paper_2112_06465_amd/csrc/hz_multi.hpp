@@ -693,6 +693,32 @@ __global__ HZ_STREAM_BOUNDS void k_m_grad_vals(const MultiArgs a, const double2*
 // systems: gather (dir 0) dst[i*Bg + k] = src[i*B + idx[k]], or scatter
 // (dir 1) dst[i*B + idx[k]] = src[i*Bg + k].
 constexpr int kSweepGroup = 16;
+// Ordering key of system j for grouping a batch: the sum of Re(A_j(i, i))
+// over up to kBlock evenly spaced rows i (duplicates of a diagonal entry
+// all count; a row without one adds nothing), in a fixed order.  For a
+// frequency sweep K - k^2 M + i k B it decreases with k.  One block per
+// system.
+__global__ __launch_bounds__(kBlock) void k_m_diag_key(int n, int B, const int* __restrict__ rp,
+                                                       const int* __restrict__ ci, const double2* __restrict__ vals,
+                                                       double* __restrict__ key) {
+    __shared__ double red[kBlock];
+    const int j = blockIdx.x, t = threadIdx.x;
+    const int m = n < kBlock ? n : kBlock;
+    double v = 0.0;
+    if (t < m) {
+        const int i = (int)((int64_t)t * n / m);
+        for (int p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] == i) v += vals[(size_t)p * B + j].x;
+    }
+    red[t] = v;
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w /= 2) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) key[j] = red[0];
+}
+
 struct GroupCols {
     int j[kSweepGroup];
 };

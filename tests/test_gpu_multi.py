@@ -279,3 +279,34 @@ def test_sweep_with_tiles_too_long_to_stage(hz, jacobi):
         assert infos[j]["status"] == hz.OK, infos[j]
         assert true_relres(Aj, xs[j], rhs[j]) <= 1e-10 * (1 + 1e-3)
         assert np.linalg.norm(xs[j] - xe[j]) / np.linalg.norm(xe[j]) < 1e-8
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_batch_of_more_than_16_systems_runs_in_groups_by_diagonal(hz, jacobi):
+    """More than 16 explicit value sets run as groups of up to 16 in order of the mean real diagonal (for a sweep,
+    the wavenumbers): every member meets the tolerance (oracle product) and agrees with its single-system solve,
+    an initial guess is used, and permuting the systems permutes the results bitwise (the groups follow the keys,
+    not the positions)."""
+    B = 24
+    A, vals, rhs, ks, _ = W.config_freq_sweep(B=B, h=0.12, kmin=3.0, kmax=9.0, seed=11)
+    flags = hz.PRECOND_JACOBI if jacobi else hz.PRECOND_NONE
+    xs, infos = solve_multi(hz, A, vals, rhs, 1e-10, flags)
+    for j in range(B):
+        Aj = A.with_vals(vals[j])
+        assert infos[j]["status"] == hz.OK, (j, infos[j])
+        assert true_relres(Aj, xs[j], rhs[j]) <= 1e-10 * (1 + 1e-3)
+    for j in (0, 7, 23):
+        x1, i1 = hz.zbicgstab_solve(dev(A.row_ptr), dev(A.col_idx), dev(vals[j]), dev(rhs[j]), rtol=1e-10,
+                                    flags=flags | hz.X0_ZERO)
+        x1 = x1.cpu().numpy()
+        assert np.linalg.norm(xs[j] - x1) / np.linalg.norm(x1) < 1e-7
+    perm = np.random.default_rng(12).permutation(B)
+    xp, ip = solve_multi(hz, A, vals[perm], rhs[perm], 1e-10, flags)
+    for k, j in enumerate(perm):
+        assert np.array_equal(xp[k].view(np.float64), xs[j].view(np.float64))
+        assert ip[k] == infos[j]
+    xa, _ = solve_multi(hz, A, vals, rhs, 1e-4, flags)
+    xw, iw = solve_multi(hz, A, vals, rhs, 1e-10, flags, x0=np.stack(xa))
+    for j in range(B):
+        assert iw[j]["status"] == hz.OK and iw[j]["iterations"] < infos[j]["iterations"]
+        assert true_relres(A.with_vals(vals[j]), xw[j], rhs[j]) <= 1e-10 * (1 + 1e-3)
