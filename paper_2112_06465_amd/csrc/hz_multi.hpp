@@ -175,51 +175,60 @@ __device__ __forceinline__ double2 mrow(const MultiArgs& a, int64_t i, int j, co
     return acc;
 }
 
-// K/M/B products stage a tile's column indices and K, M, Bm entries in LDS:
-// every lane of a row (one per system) needs the same ones, and loading them
-// per lane costs one 64-lane load instruction per entry and kind for BL times
-// fewer distinct values.  Tiles with more entries than kMTileCap read them
-// per lane as mrow does.
+// The products stage a tile's column indices (and, for K/M/B, its K, M, Bm
+// entries) in LDS: every lane of a row (one per system) needs the same ones,
+// and loading them per lane costs one 64-lane load instruction per entry and
+// kind for BL times fewer distinct values.  Explicit values differ per system
+// and are still loaded per lane.  Tiles with more entries than kMTileCap read
+// everything per lane as mrow does.
 constexpr int kMTileCap = 1536;
 
-// Row i of A(k_j) times X for lane j, entries [b, e) of the staged tile; the
-// same operations in the same order as mrow<U, VS_KMB>, so the results are
-// bitwise equal.
-template <int U>
-__device__ __forceinline__ double2 mrow_lds(const int* cs, const double* ks, const double* ms, const double* bs, int b,
-                                            int e, int j, size_t B, const double2* __restrict__ X, double2 k) {
+// Row i of A_j times X for lane j, entries [b, e) of the staged tile (tile
+// offsets; the tile starts at entry e0); the same operations in the same
+// order as mrow<U, VS>, so the results are bitwise equal.
+template <int U, int VS>
+__device__ __forceinline__ double2 mrow_lds(const MultiArgs& a, int e0, const int* cs, const double* ks,
+                                            const double* ms, const double* bs, int b, int e, int j, size_t B,
+                                            const double2* __restrict__ X, double2 k) {
+    auto val = [&](int p) {
+        if constexpr (VS == VS_KMB) {
+            return mk<double>(__builtin_fma(-k.y, ms[p], ks[p]), k.x * bs[p]);
+        } else {
+            return a.vals[(size_t)(e0 + p) * B + j];
+        }
+    };
     double2 acc = mk<double>(0.0, 0.0);
     int p = b;
     for (; p + U <= e; p += U) {
         int c[U];
-        double2 xv[U];
+        double2 xv[U], av[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) c[u] = cs[p + u];
+        if constexpr (VS != VS_KMB) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) av[u] = val(p + u);
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) xv[u] = X[(size_t)c[u] * B + j];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double2 av = mk<double>(__builtin_fma(-k.y, ms[p + u], ks[p + u]), k.x * bs[p + u]);
-            acc = cfma<double>(av, xv[u], acc);
-        }
+        for (int u = 0; u < U; ++u) acc = cfma<double>(VS == VS_KMB ? val(p + u) : av[u], xv[u], acc);
     }
-    for (; p < e; ++p) {
-        const double2 av = mk<double>(__builtin_fma(-k.y, ms[p], ks[p]), k.x * bs[p]);
-        acc = cfma<double>(av, X[(size_t)cs[p] * B + j], acc);
-    }
+    for (; p < e; ++p) acc = cfma<double>(val(p), X[(size_t)cs[p] * B + j], acc);
     return acc;
 }
 
 // f(i, acc) for every row i of the block on lane j when `on`, acc = row i of
-// A(k_j) times X.  The block walks its rows in tiles of kBlock / BL
-// consecutive rows (the rows and order of HZ_MROWS); a tile's entries are
-// loaded once, contiguously by the whole block, into LDS.
-template <int BL, int U, typename F>
-__device__ __forceinline__ void m_kmb_tiles(const MultiArgs& a, const RowRange& rr, bool on,
-                                            const double2* __restrict__ X, double2 k, F&& f) {
+// A_j times X.  The block walks its rows in tiles of kBlock / BL consecutive
+// rows (the rows and order of HZ_MROWS); a tile's shared entries are loaded
+// once, contiguously by the whole block, into LDS.
+template <int BL, int U, int VS, typename F>
+__device__ __forceinline__ void m_tiles(const MultiArgs& a, const RowRange& rr, bool on, const double2* __restrict__ X,
+                                        double2 k, F&& f) {
     constexpr int S = kBlock / BL;
+    constexpr bool kmb = VS == VS_KMB;
+    constexpr int KC = kmb ? kMTileCap : 1;  // K, M, Bm staged only for K/M/B
     __shared__ int cs[kMTileCap];
-    __shared__ double ks[kMTileCap], ms[kMTileCap], bs[kMTileCap];
+    __shared__ double ks[KC], ms[KC], bs[KC];
     const int g = threadIdx.x / BL, j = threadIdx.x % BL;
     const int* __restrict__ rp = a.row_ptr;
     for (int64_t r0 = rr.rw.x0 + (int64_t)rr.rw.k * S; r0 < rr.rw.x1; r0 += (int64_t)rr.rw.K * S) {  // uniform
@@ -229,16 +238,19 @@ __device__ __forceinline__ void m_kmb_tiles(const MultiArgs& a, const RowRange& 
         if (staged) {
             for (int q = threadIdx.x; q < ne; q += kBlock) {
                 cs[q] = a.col_idx[e0 + q];
-                ks[q] = a.K[e0 + q];
-                ms[q] = a.M[e0 + q];
-                bs[q] = a.Bm[e0 + q];
+                if constexpr (kmb) {
+                    ks[q] = a.K[e0 + q];
+                    ms[q] = a.M[e0 + q];
+                    bs[q] = a.Bm[e0 + q];
+                }
             }
             __syncthreads();
         }
         const int64_t i = r0 + g;
         if (on && i < re) {
-            const double2 acc = staged ? mrow_lds<U>(cs, ks, ms, bs, rp[i] - e0, rp[i + 1] - e0, j, (size_t)a.B, X, k)
-                                       : mrow<2, VS_KMB>(a, i, j, X, k);
+            const double2 acc =
+                staged ? mrow_lds<U, VS>(a, e0, cs, ks, ms, bs, rp[i] - e0, rp[i + 1] - e0, j, (size_t)a.B, X, k)
+                       : mrow<2, VS>(a, i, j, X, k);
             f(i, acc);
         }
         if (staged) __syncthreads();  // the tile's entries have been read
@@ -397,12 +409,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_A1(const MultiArgs a) {
         e[0] = c.x;
         e[1] = c.y;
     };
-    if constexpr (VS == VS_KMB) {
-        m_kmb_tiles<BL, U>(a, rr, on, a.q, j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0), row);
-    } else if (on) {
-        const double2 k = mwave<VS>(a, j);
-        HZ_MROWS(i) row(i, mrow<U, VS>(a, i, j, a.q, k));
-    }
+    m_tiles<BL, U, VS>(a, rr, on, a.q, j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0), row);
     mstore<BL, 2>(mregion<BL>(a, kPartA), a.geo.G, rr.lb, e);
 }
 
@@ -463,12 +470,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_B1(const MultiArgs a) {
         e[2] = __builtin_fma(acc.x, acc.x, e[2]);
         e[2] = __builtin_fma(acc.y, acc.y, e[2]);
     };
-    if constexpr (VS == VS_KMB) {
-        m_kmb_tiles<BL, U>(a, rr, on, a.u, j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0), row);
-    } else if (on) {
-        const double2 k = mwave<VS>(a, j);
-        HZ_MROWS(i) row(i, mrow<U, VS>(a, i, j, a.u, k));
-    }
+    m_tiles<BL, U, VS>(a, rr, on, a.u, j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0), row);
     mstore<BL, 3>(mregion<BL>(a, kPartB + 1), a.geo.G, rr.lb, e);
 }
 
@@ -565,11 +567,7 @@ __global__ HZ_STREAM_BOUNDS void k_m_resid(const MultiArgs a, const double2* __r
         e[0] = __builtin_fma(d.x, d.x, e[0]);
         e[0] = __builtin_fma(d.y, d.y, e[0]);
     };
-    if constexpr (VS == VS_KMB) {
-        m_kmb_tiles<BL, U>(a2, rr, j < a.B, xin, k, row);
-    } else if (j < a.B) {
-        HZ_MROWS(i) row(i, mrow<U, VS>(a2, i, j, xin, k));
-    }
+    m_tiles<BL, U, VS>(a2, rr, j < a.B, xin, k, row);
     mstore<BL, 1>(mregion<BL>(a, kPartI), a.geo.G, rr.lb, e);
 }
 
