@@ -194,7 +194,7 @@ __device__ __forceinline__ double2 mrow_lds(const MultiArgs& a, int e0, const in
         if constexpr (VS == VS_KMB) {
             return mk<double>(__builtin_fma(-k.y, ms[p], ks[p]), k.x * bs[p]);
         } else {
-            return a.vals[(size_t)(e0 + p) * B + j];
+            return ld_mat(a.vals + (size_t)(e0 + p) * B + j);
         }
     };
     double2 acc = mk<double>(0.0, 0.0);
