@@ -217,13 +217,16 @@ __device__ __forceinline__ double2 mrow_lds(const MultiArgs& a, int e0, const in
     return acc;
 }
 
-// f(i, acc) for every row i of the block on lane j when `on`, acc = row i of
-// A_j times X.  The block walks its rows in tiles of kBlock / BL consecutive
-// rows (the rows and order of HZ_MROWS); a tile's shared entries are loaded
-// once, contiguously by the whole block, into LDS.
-template <int BL, int U, int VS, typename F>
+// f(i, acc, w) for every row i of the block on lane j when `on`, acc = row i
+// of A_j times X and w = pre(i), an operand of the epilogue.  The block walks
+// its rows in tiles of kBlock / BL consecutive rows (the rows and order of
+// HZ_MROWS); a tile's shared entries are loaded once, contiguously by the
+// whole block, into LDS.  The row's bounds are loaded with the tile's (before
+// the staging) and w before the row's gathers, so neither load adds a wait
+// of its own after the barrier.
+template <int BL, int U, int VS, typename P, typename F>
 __device__ __forceinline__ void m_tiles(const MultiArgs& a, const RowRange& rr, bool on, const double2* __restrict__ X,
-                                        double2 k, F&& f) {
+                                        double2 k, P&& pre, F&& f) {
     constexpr int S = kBlock / BL;
     constexpr bool kmb = VS == VS_KMB;
     constexpr int KC = kmb ? kMTileCap : 1;  // K, M, Bm staged only for K/M/B
@@ -233,7 +236,9 @@ __device__ __forceinline__ void m_tiles(const MultiArgs& a, const RowRange& rr, 
     const int* __restrict__ rp = a.row_ptr;
     for (int64_t r0 = rr.rw.x0 + (int64_t)rr.rw.k * S; r0 < rr.rw.x1; r0 += (int64_t)rr.rw.K * S) {  // uniform
         const int64_t re = r0 + S < rr.rw.x1 ? r0 + S : rr.rw.x1;
+        const int64_t i = r0 + g, ic = i < re ? i : re - 1;  // ic: an in-bounds row of the tile
         const int e0 = rp[r0], ne = rp[re] - e0;
+        const int rb = rp[ic], rend = rp[ic + 1];
         const bool staged = ne <= kMTileCap;
         if (staged) {
             for (int q = threadIdx.x; q < ne; q += kBlock) {
@@ -246,12 +251,11 @@ __device__ __forceinline__ void m_tiles(const MultiArgs& a, const RowRange& rr, 
             }
             __syncthreads();
         }
-        const int64_t i = r0 + g;
         if (on && i < re) {
-            const double2 acc =
-                staged ? mrow_lds<U, VS>(a, e0, cs, ks, ms, bs, rp[i] - e0, rp[i + 1] - e0, j, (size_t)a.B, X, k)
-                       : mrow<2, VS>(a, i, j, X, k);
-            f(i, acc);
+            const double2 w = pre(i);
+            const double2 acc = staged ? mrow_lds<U, VS>(a, e0, cs, ks, ms, bs, rb - e0, rend - e0, j, (size_t)a.B, X, k)
+                                       : mrow<2, VS>(a, i, j, X, k);
+            f(i, acc, w);
         }
         if (staged) __syncthreads();  // the tile's entries have been read
     }
@@ -401,15 +405,14 @@ __global__ HZ_STREAM_BOUNDS void k_m_A1(const MultiArgs a) {
     HZ_MULTI_ROWS;
     double e[2] = {0.0, 0.0};
     const bool on = j < a.B && !a.sc[j].done && !a.sc[j].pending;
-    auto row = [&](int64_t i, double2 acc) {
-        const size_t q = (size_t)i * Bz + j;
-        a.v[q] = acc;
-        const double2 w = a.rh[q];
+    auto pre = [&](int64_t i) { return a.rh[(size_t)i * Bz + j]; };
+    auto row = [&](int64_t i, double2 acc, double2 w) {
+        a.v[(size_t)i * Bz + j] = acc;
         const double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
         e[0] = c.x;
         e[1] = c.y;
     };
-    m_tiles<BL, U, VS>(a, rr, on, a.q, j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0), row);
+    m_tiles<BL, U, VS>(a, rr, on, a.q, j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0), pre, row);
     mstore<BL, 2>(mregion<BL>(a, kPartA), a.geo.G, rr.lb, e);
 }
 
@@ -460,17 +463,16 @@ __global__ HZ_STREAM_BOUNDS void k_m_B1(const MultiArgs a) {
     HZ_MULTI_ROWS;
     double e[3] = {0.0, 0.0, 0.0};
     const bool on = j < a.B && !a.sc[j].done;
-    auto row = [&](int64_t i, double2 acc) {
-        const size_t q = (size_t)i * Bz + j;
-        a.t[q] = acc;
-        const double2 sv = a.s[q];
+    auto pre = [&](int64_t i) { return a.s[(size_t)i * Bz + j]; };
+    auto row = [&](int64_t i, double2 acc, double2 sv) {
+        a.t[(size_t)i * Bz + j] = acc;
         const double2 c = cdotacc(acc.x, acc.y, sv.x, sv.y, mk<double>(e[0], e[1]));
         e[0] = c.x;
         e[1] = c.y;
         e[2] = __builtin_fma(acc.x, acc.x, e[2]);
         e[2] = __builtin_fma(acc.y, acc.y, e[2]);
     };
-    m_tiles<BL, U, VS>(a, rr, on, a.u, j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0), row);
+    m_tiles<BL, U, VS>(a, rr, on, a.u, j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0), pre, row);
     mstore<BL, 3>(mregion<BL>(a, kPartB + 1), a.geo.G, rr.lb, e);
 }
 
@@ -559,15 +561,14 @@ __global__ HZ_STREAM_BOUNDS void k_m_resid(const MultiArgs a, const double2* __r
     a2.vals = vals;
     double e[1] = {0.0};
     const double2 k = j < a.B ? mwave<VS>(a, j) : mk<double>(0.0, 0.0);
-    auto row = [&](int64_t i, double2 acc) {
-        const size_t q = (size_t)i * Bz + j;
-        const double2 bv = a.b[q];
+    auto pre = [&](int64_t i) { return a.b[(size_t)i * Bz + j]; };
+    auto row = [&](int64_t i, double2 acc, double2 bv) {
         const double2 d = mk<double>(bv.x - acc.x, bv.y - acc.y);
-        y[q] = d;
+        y[(size_t)i * Bz + j] = d;
         e[0] = __builtin_fma(d.x, d.x, e[0]);
         e[0] = __builtin_fma(d.y, d.y, e[0]);
     };
-    m_tiles<BL, U, VS>(a2, rr, j < a.B, xin, k, row);
+    m_tiles<BL, U, VS>(a2, rr, j < a.B, xin, k, pre, row);
     mstore<BL, 1>(mregion<BL>(a, kPartI), a.geo.G, rr.lb, e);
 }
 

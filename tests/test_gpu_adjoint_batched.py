@@ -36,13 +36,13 @@ def small_sweep(B, nonsym=False, seed=0):
     A, vals, rhs, ks, _ = W.config_freq_sweep(B=B, h=0.2, kmin=3.0, kmax=6.0, seed=seed)
     if nonsym:  # break A = A^T: perturb the strictly upper entries of every system
         upper = A.col_idx > A.row_of_entry()
-        vals = vals + 0.05j * upper[None, :] * (1 + np.arange(B))[:, None]
+        vals = vals + 0.05j * upper[None, :] * (1 + np.arange(B) % 5)[:, None]  # the same five sizes for any B
     return A, vals, rhs
 
 
+@pytest.mark.parametrize("B", [5, 20, 70])  # one launch of 16, 64 and 256 lanes per row
 @pytest.mark.parametrize("nonsym", [False, True])
-def test_batched_adjoint_matches_dense_and_oracle_gradients(hz, nonsym):
-    B = 5
+def test_batched_adjoint_matches_dense_and_oracle_gradients(hz, nonsym, B):
     A, vals, rhs = small_sweep(B, nonsym=nonsym, seed=1)
     rng = np.random.default_rng(2)
     G = cn(rng, A.n, B)
@@ -54,8 +54,16 @@ def test_batched_adjoint_matches_dense_and_oracle_gradients(hz, nonsym):
     for j in range(B):
         Aj = A.with_vals(vals[j])
         assert infos[j]["status"] == hz.OK
-        ld = np.linalg.solve(O.to_dense(Aj).conj().T, G[:, j])
-        assert np.linalg.norm(lam[:, j] - ld) / np.linalg.norm(ld) < 1e-8
+        D = O.to_dense(Aj).conj().T
+        ld = np.linalg.solve(D, G[:, j])
+        g = np.linalg.norm(G[:, j])
+        # the solve's guarantee: the residual of A^H lambda = g (rtol 1e-12 on the recursive residual), above the
+        # rounding floor of forming D lambda in double precision (near a resonance ||lambda|| is large)
+        floor = 64 * np.finfo(float).eps * np.linalg.norm(D) * np.linalg.norm(lam[:, j])
+        assert np.linalg.norm(D @ lam[:, j] - G[:, j]) <= 1e-10 * g + floor
+        # the error against the dense solve, within the conditioning: kappa >= ||A||_F ||lambda|| / ||g|| / sqrt(n)
+        kest = np.linalg.norm(D) * np.linalg.norm(ld) / g / np.sqrt(A.n)
+        assert np.linalg.norm(lam[:, j] - ld) / np.linalg.norm(ld) < max(1e-8, 1e-10 * kest)
         go = O.zgrad_vals(Aj, lam[:, j], X[:, j])
         assert np.max(np.abs(gv[:, j] - go)) <= 1e-14 * np.max(np.abs(go))
 
