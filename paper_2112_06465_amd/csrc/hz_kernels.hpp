@@ -16,6 +16,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace hz {
@@ -339,9 +341,19 @@ constexpr int kSolTileRows = kBlock / kSolTileLanes;
 constexpr int kSolTilePer = 4;
 constexpr int kSolTileCap = kBlock * kSolTilePer;
 
-template <typename T, typename Op, typename Epi>
+// No epilogue operand: epi(row, total).  With a `pre` functor the epilogue is
+// epi(row, total, pre(row)).  The vector form issues that load before the
+// row's product, so that its latency overlaps the product's loads; the tile
+// form loads it at the epilogue (its kernels use all 64 VGPRs, and an early
+// load spilled: 241 -> 250 us per cabin iteration).
+struct NoPre {
+    __device__ int operator()(int64_t) const { return 0; }
+};
+
+template <typename T, typename Op, typename Epi, typename Pre = NoPre>
 __device__ __forceinline__ void for_tiles(const Rows& rw, const int* __restrict__ rp, const int* __restrict__ ci,
-                                          const cx<T>* __restrict__ vals, Op op, Epi epi) {
+                                          const cx<T>* __restrict__ vals, Op op, Epi epi, Pre pre = Pre{}) {
+    constexpr bool kPre = !std::is_same_v<Pre, NoPre>;
     constexpr int L = kSolTileLanes;
     __shared__ cx<T> prod[kSolTileCap];
     const int t = threadIdx.x, g = t / L, lane = t % L;
@@ -387,7 +399,13 @@ __device__ __forceinline__ void for_tiles(const Rows& rw, const int* __restrict_
         }
         acc.x = group_sum<L>(acc.x);
         acc.y = group_sum<L>(acc.y);
-        if (row < re && lane == 0) epi(row, acc);
+        if (row < re && lane == 0) {
+            if constexpr (kPre) {
+                epi(row, acc, pre(row));
+            } else {
+                epi(row, acc);
+            }
+        }
     }
 }
 
@@ -398,11 +416,12 @@ __device__ __forceinline__ void for_tiles(const Rows& rw, const int* __restrict_
 // kernels whose column functor gathers several vectors leave it off to stay
 // within 64 VGPRs).  epi(row, total) runs in lane 0 of each row's group after
 // the group sum.  The trip count is uniform across the block.
-template <typename T, int L, int U, bool PF = true, typename Op, typename Epi>
+template <typename T, int L, int U, bool PF = true, typename Op, typename Epi, typename Pre = NoPre>
 __device__ __forceinline__ void for_rows(const Rows& rw, const int* __restrict__ rp, const int* __restrict__ ci,
-                                         const cx<T>* __restrict__ vals, Op op, Epi epi) {
+                                         const cx<T>* __restrict__ vals, Op op, Epi epi, Pre pre = Pre{}) {
+    constexpr bool kPre = !std::is_same_v<Pre, NoPre>;
     if constexpr (L == 1) {
-        for_tiles<T>(rw, rp, ci, vals, op, epi);
+        for_tiles<T>(rw, rp, ci, vals, op, epi, pre);
         return;
     }
     constexpr int RPS = kBlock / L;
@@ -427,10 +446,20 @@ __device__ __forceinline__ void for_rows(const Rows& rw, const int* __restrict__
             end = rp[row + 1];
         }
         cx<T> acc = mk<T>(T(0), T(0));
-        if (ok) acc = row_partial<T, L, U>(beg, end, lane, ci, vals, op);
+        decltype(pre(row)) w{};
+        if (ok) {
+            if constexpr (kPre) w = pre(row);
+            acc = row_partial<T, L, U>(beg, end, lane, ci, vals, op);
+        }
         acc.x = group_sum<L>(acc.x);
         acc.y = group_sum<L>(acc.y);
-        if (ok && lane == 0) epi(row, acc);
+        if (ok && lane == 0) {
+            if constexpr (kPre) {
+                epi(row, acc, w);
+            } else {
+                epi(row, acc);
+            }
+        }
         row = nrow;
         if (PF) {
             beg = nbeg;
@@ -933,14 +962,17 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_A1(const BicgArgs<T> a) {
     const cx<T>* __restrict__ p = a.p[it & 1];
     cx<T>* __restrict__ v = a.v[it & 1];
     auto pcol = [p](int c) { return p[c]; };
+    const cx<T>* __restrict__ rh = a.rh;
     double e[2] = {0.0, 0.0};
-    for_rows<T, L, U>(q.rw, a.row_ptr, a.col_idx, a.vals, pcol, [&](int64_t row, cx<T> acc) {
-        v[row] = acc;
-        const cx<T> w = a.rh[row];
-        double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
-        e[0] = c.x;
-        e[1] = c.y;
-    });
+    for_rows<T, L, U>(
+        q.rw, a.row_ptr, a.col_idx, a.vals, pcol,
+        [&](int64_t row, cx<T> acc, cx<T> w) {
+            v[row] = acc;
+            double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+        },
+        [rh](int64_t row) { return rh[row]; });
     store_sys_partials<2>(a.part + kPartA * a.stride, a.stride, q.lb, e);
 }
 
@@ -970,15 +1002,17 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_B1(const BicgArgs<T> a) {
     const cx<T>* __restrict__ sv = a.s;
     auto scol = [sv](int c) { return sv[c]; };
     double e[3] = {0.0, 0.0, 0.0};
-    for_rows<T, L, U>(q.rw, a.row_ptr, a.col_idx, a.vals, scol, [&](int64_t row, cx<T> acc) {
-        const cx<T> s = sv[row];
-        a.t[row] = acc;
-        double2 c = cdotacc(acc.x, acc.y, s.x, s.y, mk<double>(e[0], e[1]));
-        e[0] = c.x;
-        e[1] = c.y;
-        e[2] = __builtin_fma((double)acc.x, (double)acc.x, e[2]);
-        e[2] = __builtin_fma((double)acc.y, (double)acc.y, e[2]);
-    });
+    for_rows<T, L, U>(
+        q.rw, a.row_ptr, a.col_idx, a.vals, scol,
+        [&](int64_t row, cx<T> acc, cx<T> s) {
+            a.t[row] = acc;
+            double2 c = cdotacc(acc.x, acc.y, s.x, s.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+            e[2] = __builtin_fma((double)acc.x, (double)acc.x, e[2]);
+            e[2] = __builtin_fma((double)acc.y, (double)acc.y, e[2]);
+        },
+        [sv](int64_t row) { return sv[row]; });
     store_sys_partials<3>(a.part + (kPartB + 1) * a.stride, a.stride, q.lb, e);
 }
 
