@@ -253,7 +253,7 @@ __device__ __forceinline__ void m_tiles(const MultiArgs& a, const RowRange& rr, 
         }
         if (on && i < re) {
             const double2 w = pre(i);
-            const double2 acc = staged ? mrow_lds<U, VS>(a, e0, cs, ks, ms, bs, rb - e0, rend - e0, j, (size_t)a.B, X, k)
+            const double2 acc = staged ? mrow_lds<(kmb || U < 3 ? U : 3), VS>(a, e0, cs, ks, ms, bs, rb - e0, rend - e0, j, (size_t)a.B, X, k)
                                        : mrow<2, VS>(a, i, j, X, k);
             f(i, acc, w);
         }
