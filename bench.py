@@ -763,6 +763,24 @@ def profile(what, steps, cache_dir):
             print(what, json.dumps(adjoint_cylinder(hz, torch, dev)), flush=True)
     elif what == "stream":
         print(what, json.dumps(stream_ceiling(hz, torch, dev)), flush=True)
+    elif what == "blas1":
+        # zdotc, dznrm2 and zaxpy at n = 1.5e7 (HBM-bound) and 209,777 (launch-bound), 20 eager calls each per step
+        rng = np.random.default_rng(5)
+        for n in (15_000_000, 209_777):
+            x = torch.from_numpy(rng.standard_normal(2 * n).view(np.complex128)).to(dev)
+            y = torch.from_numpy(rng.standard_normal(2 * n).view(np.complex128)).to(dev)
+            d = torch.empty((), dtype=torch.complex128, device=dev)
+            nr = torch.empty((), dtype=torch.float64, device=dev)
+            for _ in range(steps):
+                for _ in range(20):
+                    hz.zdotc(x, y, out=d)
+                for _ in range(20):
+                    hz.dznrm2(x, out=nr)
+                for _ in range(20):
+                    hz.zaxpy(1e-3 + 0j, x, y)
+                torch.cuda.synchronize()
+            print(what, n, complex(d.cpu()), float(nr.cpu()), flush=True)
+            del x, y
     else:
         raise SystemExit(f"unknown profile target {what}")
 
@@ -781,7 +799,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--profile", default=None,
                     help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | sweep-explicit | sweep-kmb | "
-                         "adjoint-cylinder | stream")
+                         "adjoint-cylinder | stream | blas1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline step only (no secondary sections)")
     ap.add_argument("--no-time-to-tol", action="store_true")
