@@ -106,6 +106,37 @@ MUTANTS = {
         "tests/test_oracle_tfqmr_pins.py",
     ),
     "tfqmr_eta_without_c_squared": ("tfqmr.py", "eta = c * c * alpha", "eta = c * alpha", "tests/test_oracle_tfqmr_pins.py"),
+    # reliable updates (oracle/reliable.py), against their own pins
+    "reliable_update_drops_scale": (
+        "reliable.py",
+        "x = x + bn * (dinv.astype(np.complex128) * y.astype(np.complex128))",
+        "x = x + (dinv.astype(np.complex128) * y.astype(np.complex128))",
+        "tests/test_oracle_reliable_pins.py",
+    ),
+    "reliable_residual_not_replaced": (
+        "reliable.py",
+        "            r = (r64 / bn).astype(inner)\n            r_ref = float(np.linalg.norm(r.astype(np.complex128)))\n    if status",
+        "            r_ref = float(np.linalg.norm(r.astype(np.complex128)))\n    if status",
+        "tests/test_oracle_reliable_pins.py",
+    ),
+    "reliable_omega_conjugated": (
+        "reliable.py",
+        "omega = _dot(t, s) / tt",
+        "omega = _dot(s, t) / tt",
+        "tests/test_oracle_reliable_pins.py",
+    ),
+    "reliable_jacobi_not_inverted": (
+        "reliable.py",
+        "dinv = (1.0 / d).astype(inner)",
+        "dinv = d.astype(inner)",
+        "tests/test_oracle_reliable_pins.py",
+    ),
+    "reliable_y_drops_omega_term": (
+        "reliable.py",
+        "y = (y + c(alpha) * p + c(omega) * s).astype(inner)",
+        "y = (y + c(alpha) * p).astype(inner)",
+        "tests/test_oracle_reliable_pins.py",
+    ),
     # storage formats (oracle/formats.py), against their own pins
     "sell_sorted_ascending": (
         "formats.py",
