@@ -95,8 +95,10 @@ enum {
  * matrix, vectors and workspace) is replayed with one hipGraphLaunch on the
  * caller's stream; results are bitwise those of direct launches, which the
  * environment variable HZ_NO_GRAPH=1 selects.  Allocates device memory and
- * the capture stream once; returns HZ_ERR_HIP if that fails.  One handle per
- * device, used by one host thread at a time. */
+ * the capture stream once, and arms the slots of zdotc / dznrm2 with a kernel
+ * on the null stream that it waits for, so it must not be called while a
+ * stream of the device is being captured; returns HZ_ERR_HIP if any of this
+ * fails.  One handle per device, used by one host thread at a time. */
 int hz_handle_create(hz_handle **handle);
 int hz_handle_destroy(hz_handle *handle);
 

@@ -36,6 +36,9 @@ def handle(device: torch.device | int | None = None) -> int:
     with _hlock:
         h = _handles.get(idx)
         if h is None:
+            if torch.cuda.is_current_stream_capturing():
+                raise RuntimeError("the library handle is created (device memory, a synchronised set-up kernel) on first "
+                                   "use: call paper_2112_06465_amd.handle() before capturing a graph")
             with torch.cuda.device(idx):
                 hp = C.c_void_p()
                 rc = load().hz_handle_create(C.byref(hp))
