@@ -22,7 +22,14 @@
 //   streaming (ld_mat): each instruction reads 256 consecutive entries, whole
 //   cache lines.  Up to kSpMaxGrid tiles, every tile gets a block; beyond,
 //   kSpTileGrid blocks loop over the tiles (fewer concurrent streams measured
-//   faster from HBM: 80 against 83 us on a 409 MB product).
+//   faster from HBM: 80 against 83 us on a 409 MB product).  The
+//   results do not go to y tile by tile: a block keeps those of up to kHold
+//   tiles in LDS and writes them in one pass when the ring is full and at its
+//   end.  On this architecture one in-order counter tracks loads and stores,
+//   so a store issued at the end of a tile made the next tile's first wait for
+//   its loads also wait for the store to complete; with the ring a block's
+//   stores hold up its loads once per kHold tiles (on the cabin's 409 MB
+//   product, 19 tiles per block: 81 against 71-74 us).
 //
 // Row ownership is that of the other kernels (XCD groups, tiles dealt out
 // within a group), with the form's own tile height.  Summation order is fixed
@@ -40,6 +47,7 @@ constexpr int kTileLanes = kSpBlock / kTileRows;  // threads per row in its redu
 constexpr int kTilePer = 4;                       // entries per thread per tile
 constexpr int kTileCap = kSpBlock * kTilePer;     // entries per tile held in LDS
 constexpr int kSpTileGrid = 1024;                 // blocks of the tile form beyond kSpMaxGrid tiles
+constexpr int kHold = 20;                         // tiles whose results a block holds in LDS (20 KB)
 
 template <typename T> struct SpArgs {
     int n;    // rows
@@ -127,6 +135,7 @@ template <typename T>
 __global__ __launch_bounds__(kSpBlock) void k_spmv_tile(const SpArgs<T> a) {
     constexpr int L = kTileLanes;
     __shared__ cx<T> prod[kTileCap];
+    __shared__ cx<T> held[kHold * kTileRows];  // results of the block's last tiles, row-major by tile
     const RowRange rr = rows_of_block(a.n, a.geo);
     const int t = threadIdx.x, g = t / L, lane = t % L;
     const int64_t first = rr.rw.x0 + (int64_t)rr.rw.k * kTileRows, step = (int64_t)rr.rw.K * kTileRows;
@@ -136,7 +145,17 @@ __global__ __launch_bounds__(kSpBlock) void k_spmv_tile(const SpArgs<T> a) {
     const cx<T>* __restrict__ vals = a.vals;
     const cx<T>* __restrict__ x = a.x;
     const int nnz = a.nnz;
-    for (int64_t r0 = first; r0 < r1; r0 += step) {  // uniform across the block
+    // y for the `count` held tiles starting at the block's tile `base` (every thread; uniform)
+    auto flush = [&](int64_t base, int count) {
+        __syncthreads();  // the held results are written
+        for (int q = t; q < count * kTileRows; q += kSpBlock) {
+            const int64_t row = first + (base + q / kTileRows) * step + q % kTileRows;
+            if (row < r1) a.y[a.yperm != nullptr ? a.yperm[row] : row] = held[q];
+        }
+        __syncthreads();  // the ring may be refilled
+    };
+    int64_t tile = 0;                                             // the block's tile counter
+    for (int64_t r0 = first; r0 < r1; r0 += step, ++tile) {  // uniform across the block
         const int64_t re = r0 + kTileRows < r1 ? r0 + kTileRows : r1;
         const int e0 = rp[r0], e1 = rp[re];
         const int64_t row = r0 + g;
@@ -177,8 +196,11 @@ __global__ __launch_bounds__(kSpBlock) void k_spmv_tile(const SpArgs<T> a) {
         }
         acc.x = group_sum<L>(acc.x);
         acc.y = group_sum<L>(acc.y);
-        if (row < re && lane == 0) a.y[a.yperm != nullptr ? a.yperm[row] : row] = acc;
+        const int slot = (int)(tile % kHold);
+        if (lane == 0) held[slot * kTileRows + g] = acc;  // (rows past the range are skipped by the flush)
+        if (slot == kHold - 1) flush(tile - (kHold - 1), kHold);
     }
+    if (tile % kHold != 0) flush(tile - tile % kHold, (int)(tile % kHold));
 }
 
 }  // namespace hz
