@@ -77,26 +77,39 @@ __device__ __forceinline__ void st_nt(double2* p, double2 v) {
 
 // y = alpha x + y
 // (x may equal y: every element is read before it is written, by the same thread)
+// Whole chunks are software-pipelined: chunk j + 1's loads are issued before
+// chunk j's stores.  One in-order counter tracks loads and stores on this
+// architecture, so with the stores first the wait for the next chunk's loads
+// would also wait for them.
 __global__ __launch_bounds__(kB1Block) void k_zaxpy_s(int64_t n, int per, double2 alpha, const double2* x,
                                                       double2* y) {
-  for (int j = 0; j < per; ++j) {
-    const int64_t i0 = (int64_t(blockIdx.x) * per + j) * kB1Chunk + threadIdx.x;
-    if (i0 >= n) break;
-    if (i0 + (kB1U - 1) * kB1Block < n) {
-        double2 xv[kB1U], yv[kB1U];
+    const int64_t c0 = int64_t(blockIdx.x) * per;  // the block's first chunk
+    int64_t chunks = (n / kB1Chunk) - c0;           // whole chunks of this block
+    if (chunks > per) chunks = per;
+    if (chunks < 0) chunks = 0;
+    double2 xv[kB1U], yv[kB1U];
+    auto load = [&](int64_t c) {
+        const int64_t i0 = c * kB1Chunk + threadIdx.x;
 #pragma unroll
         for (int u = 0; u < kB1U; ++u) xv[u] = ld_nt(x + i0 + u * kB1Block);
 #pragma unroll
         for (int u = 0; u < kB1U; ++u) yv[u] = ld_nt(y + i0 + u * kB1Block);
+    };
+    if (chunks > 0) load(c0);
+    for (int64_t j = 0; j < chunks; ++j) {
+        const int64_t i0 = (c0 + j) * kB1Chunk + threadIdx.x;
+        double2 r[kB1U];
 #pragma unroll
-        for (int u = 0; u < kB1U; ++u) st_nt(y + i0 + u * kB1Block, cfma<double>(alpha, xv[u], yv[u]));
-    } else {
-        for (int u = 0; u < kB1U; ++u) {
-            const int64_t i = i0 + u * kB1Block;
-            if (i < n) y[i] = cfma<double>(alpha, x[i], y[i]);
-        }
+        for (int u = 0; u < kB1U; ++u) r[u] = cfma<double>(alpha, xv[u], yv[u]);
+        if (j + 1 < chunks) load(c0 + j + 1);
+#pragma unroll
+        for (int u = 0; u < kB1U; ++u) st_nt(y + i0 + u * kB1Block, r[u]);
     }
-  }
+    // the ragged tail past the last whole chunk, in the block that owns that chunk
+    const int64_t full = n / kB1Chunk;
+    if (full >= c0 && full < c0 + per) {
+        for (int64_t i = full * kB1Chunk + threadIdx.x; i < n; i += kB1Block) y[i] = cfma<double>(alpha, x[i], y[i]);
+    }
 }
 
 constexpr unsigned long long kB1SlotEmpty = 0x7ff4dead0000beefull;  // a signalling NaN no arithmetic yields
