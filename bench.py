@@ -51,10 +51,11 @@ CYL_REPLICAS = 6  # 6 x 68.5 MB > the 256 MB Infinity Cache
 CABIN_FORM = "tiles"  # the autotuner's pick on the renumbered cabin (block tiles)
 
 
-def spmv_kernel_name(form, L=8):
-    """Name of the standalone zSpMV kernel for a form ("rows" / "tiles") and lane count."""
+def spmv_kernel_name(form, L=8, n=None):
+    """Name of the standalone zSpMV kernel for a form ("rows" / "tiles") and lane count (tiles: one block per
+    64-row tile below 4,096 tiles, else 1,024 blocks looping over them)."""
     if form == "tiles":
-        return "hz::k_spmv_tile<double>"
+        return "hz::k_spmv_tile1<double>" if n is not None and -(-n // 64) < 4096 else "hz::k_spmv_tile<double>"
     U = 4 if L <= 4 else (2 if L == 8 else 1)
     return f"hz::k_spmv_pipe<double, {L}, {U}>"
 
@@ -285,7 +286,7 @@ def spmv_cabin(hz, torch, dev, cab, reps=20):
 
 
 def spmv_cylinder(hz, torch, dev, reps=30):
-    """Cold zSpMV of the cylinder (68.5 MB): 6 replicas; CSR rule rows, ELL and SELL-64-1."""
+    """Cold zSpMV of the cylinder (68.5 MB): 6 replicas; CSR rule rows, CSR block tiles, ELL and SELL-64-1."""
     import workloads as W
 
     A, _, _ = W.config_cylinder()
@@ -299,10 +300,11 @@ def spmv_cylinder(hz, torch, dev, reps=30):
            "algorithmic_bytes": spmv_bytes(n, nnz)}
     reps_ = [(rp, ci, vals, x, torch.empty_like(x))] + [
         (rp.clone(), ci.clone(), vals.clone(), x.clone(), torch.empty_like(x)) for _ in range(CYL_REPLICAS - 1)]
-    with PinnedForm("rows", L):
-        loop = ColdLoop(torch, lambda r: hz.csr_zspmv(*r), reps_, reps)
-        loop.enqueue()
-        res["csr_rows"] = dict(rate(spmv_bytes(n, nnz), loop.us()), kernel=spmv_kernel_name("rows", L))
+    for label, form, lanes in (("csr_rows", "rows", L), ("csr_tiles", "tiles", None)):
+        with PinnedForm(form, lanes):
+            loop = ColdLoop(torch, lambda r: hz.csr_zspmv(*r), reps_, reps)
+            loop.enqueue()
+            res[label] = dict(rate(spmv_bytes(n, nnz), loop.us()), kernel=spmv_kernel_name(form, L, n))
     del reps_
     for label, conv, prod, stored in (
         ("ell", lambda: hz.csr_to_hyb(rp.clone(), ci.clone(), vals.clone(), K="ell"), hz.hyb_zspmv,

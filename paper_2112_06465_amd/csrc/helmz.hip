@@ -299,8 +299,12 @@ void launch_sp(const SpPlan& p, int m, int nnz, const int* rp, const int* ci, co
     hz::SpArgs<T> a{m, nnz, Geom{1}, rp, ci, v, x, y};
     if (p.form == SP_TILE) {
         a.geo = geom_sp(m, hz::kTileRows);
-        if (a.geo.G >= hz::kSpMaxGrid) a.geo.G = hz::kSpTileGrid;
-        hipLaunchKernelGGL((hz::k_spmv_tile<T>), dim3(a.geo.G), dim3(hz::kSpBlock), 0, s, a);
+        if (a.geo.G >= hz::kSpMaxGrid) {  // blocks loop over the tiles: results through the LDS ring
+            a.geo.G = hz::kSpTileGrid;
+            hipLaunchKernelGGL((hz::k_spmv_tile<T>), dim3(a.geo.G), dim3(hz::kSpBlock), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((hz::k_spmv_tile1<T>), dim3(a.geo.G), dim3(hz::kSpBlock), 0, s, a);
+        }
         return;
     }
     auto go = [&]<int L>() {
@@ -3034,8 +3038,12 @@ int csr_zspmv_planned(hz_handle* h, hz_stream stream, int n, int nnz, const void
                        reinterpret_cast<const double2*>(x), w.xp);
     hz::SpArgs<double> a{n, nnz, geom_sp(n, hz::kTileRows), w.rp, w.ci, w.vals, w.xp, reinterpret_cast<double2*>(y),
                          w.perm};
-    if (a.geo.G >= hz::kSpMaxGrid) a.geo.G = hz::kSpTileGrid;
-    hipLaunchKernelGGL((hz::k_spmv_tile<double>), dim3(a.geo.G), dim3(hz::kSpBlock), 0, s, a);
+    if (a.geo.G >= hz::kSpMaxGrid) {
+        a.geo.G = hz::kSpTileGrid;
+        hipLaunchKernelGGL((hz::k_spmv_tile<double>), dim3(a.geo.G), dim3(hz::kSpBlock), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((hz::k_spmv_tile1<double>), dim3(a.geo.G), dim3(hz::kSpBlock), 0, s, a);
+    }
     HZ_HIP(hipGetLastError());
     return HZ_OK;
 }

@@ -29,7 +29,9 @@
 //   so a store issued at the end of a tile made the next tile's first wait for
 //   its loads also wait for the store to complete; with the ring a block's
 //   stores hold up its loads once per kHold tiles (on the cabin's 409 MB
-//   product, 19 tiles per block: 81 against 71-74 us).
+//   product, 19 tiles per block: 81 against 71-74 us).  With one tile per
+//   block (fewer than kSpMaxGrid tiles) k_spmv_tile1 stores directly and
+//   keeps the LDS, and with it the resident blocks, of the form without ring.
 //
 // Row ownership is that of the other kernels (XCD groups, tiles dealt out
 // within a group), with the form's own tile height.  Summation order is fixed
@@ -131,11 +133,15 @@ __global__ __launch_bounds__(kSpBlock) void k_spmv_pipe(const SpArgs<T> a) {
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kSpBlock) void k_spmv_tile(const SpArgs<T> a) {
+// The tile loop of a block.  HOLD > 1: results go through the LDS ring of
+// HOLD tiles (blocks looping over many tiles); HOLD = 1: each tile's results
+// are stored at once (one tile per block, where a ring would only cost LDS,
+// and so resident blocks).
+template <typename T, int HOLD>
+__device__ __forceinline__ void spmv_tiles(const SpArgs<T>& a) {
     constexpr int L = kTileLanes;
     __shared__ cx<T> prod[kTileCap];
-    __shared__ cx<T> held[kHold * kTileRows];  // results of the block's last tiles, row-major by tile
+    __shared__ cx<T> held[HOLD > 1 ? HOLD * kTileRows : 1];  // results of the block's last tiles, by tile
     const RowRange rr = rows_of_block(a.n, a.geo);
     const int t = threadIdx.x, g = t / L, lane = t % L;
     const int64_t first = rr.rw.x0 + (int64_t)rr.rw.k * kTileRows, step = (int64_t)rr.rw.K * kTileRows;
@@ -196,11 +202,27 @@ __global__ __launch_bounds__(kSpBlock) void k_spmv_tile(const SpArgs<T> a) {
         }
         acc.x = group_sum<L>(acc.x);
         acc.y = group_sum<L>(acc.y);
-        const int slot = (int)(tile % kHold);
-        if (lane == 0) held[slot * kTileRows + g] = acc;  // (rows past the range are skipped by the flush)
-        if (slot == kHold - 1) flush(tile - (kHold - 1), kHold);
+        if constexpr (HOLD > 1) {
+            const int slot = (int)(tile % HOLD);
+            if (lane == 0) held[slot * kTileRows + g] = acc;  // (rows past the range are skipped by the flush)
+            if (slot == HOLD - 1) flush(tile - (HOLD - 1), HOLD);
+        } else if (row < re && lane == 0) {
+            a.y[a.yperm != nullptr ? a.yperm[row] : row] = acc;
+        }
     }
-    if (tile % kHold != 0) flush(tile - tile % kHold, (int)(tile % kHold));
+    if constexpr (HOLD > 1) {
+        if (tile % HOLD != 0) flush(tile - tile % HOLD, (int)(tile % HOLD));
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSpBlock) void k_spmv_tile(const SpArgs<T> a) {
+    spmv_tiles<T, kHold>(a);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSpBlock) void k_spmv_tile1(const SpArgs<T> a) {
+    spmv_tiles<T, 1>(a);
 }
 
 }  // namespace hz

@@ -118,6 +118,26 @@ def test_spmv_both_forms_ragged(hz, form, maxlen, monkeypatch):
     assert np.array_equal(y.view(np.float64), y2.view(np.float64))
 
 
+def test_spmv_tiles_with_blocks_looping_over_tiles(hz, monkeypatch):
+    """The tile form above 4,096 tiles, where 1,024 blocks loop over the tiles
+    and hold their results in LDS for several tiles before storing them: a
+    tile count that is no multiple of the hold depth, a ragged last tile,
+    empty rows and rows too long for the LDS buffer among the short ones."""
+    monkeypatch.setenv("HZ_SPMV_FORM", "tiles")
+    n = 64 * 4133 + 29
+    rng = np.random.default_rng(41)
+    lens = rng.integers(0, 13, n)
+    lens[[3, 64 * 2000, n - 1]] = 0
+    lens[[70, 64 * 3001 + 5]] = [600, 900]
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.cumsum(lens, out=rp[1:])
+    ci = rng.integers(0, n, rp[-1]).astype(np.int32)
+    A = CSR(rp, ci, cn(rng, ci.size))
+    x = cn(np.random.default_rng(42), n)
+    y = check_spmv(hz, A, x)
+    assert np.all(y[[3, 64 * 2000, n - 1]] == 0)
+
+
 @pytest.mark.parametrize("form", ["rows", "tiles"])
 def test_spmv_both_forms_complex64_and_rect(hz, form, monkeypatch):
     monkeypatch.setenv("HZ_SPMV_FORM", form)
