@@ -731,6 +731,16 @@ def profile(what, steps, cache_dir):
                                          flags=hz.PRECOND_JACOBI | hz.X0_ZERO)
             torch.cuda.synchronize()
             print(what, info, flush=True)
+    elif what == "solve-cylinder":
+        import workloads as W
+
+        A, b, _ = W.config_cylinder()
+        rp, ci, v, bd = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (A.row_ptr, A.col_idx, A.vals, b))
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            _, info = hz.zbicgstab_solve(rp, ci, v, bd, rtol=1e-10, maxiter=50000, flags=hz.PRECOND_JACOBI | hz.X0_ZERO)
+            torch.cuda.synchronize()
+            print(what, "ms", round(1e3 * (time.perf_counter() - t0), 2), info, flush=True)
     elif what in ("sweep-explicit", "sweep-kmb"):
         # 200 iterations of the 64-frequency batch, every system still active (they need 1,249 or more)
         import workloads as W
@@ -800,7 +810,8 @@ def main():
     ap.add_argument("--cache", default=None, help="directory to keep generated workloads in (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--profile", default=None,
-                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | sweep-explicit | sweep-kmb | "
+                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | solve-cylinder | "
+                         "sweep-explicit | sweep-kmb | "
                          "adjoint-cylinder | stream | blas1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="headline step only (no secondary sections)")

@@ -21,6 +21,7 @@
 #include "hz_multi.hpp"
 #include "hz_reliable.hpp"
 #include "hz_spmv.hpp"
+#include "hz_soltile.hpp"
 #include "hz_bicgstabl.hpp"
 #include "hz_tfqmr.hpp"
 #include "hz_formats.hpp"
@@ -460,10 +461,14 @@ struct SolveWs {
     void* ahat;
 };
 
+// Partial component stride of the BiCGStab workspace for a map of G blocks:
+// room for kSolSubs slots per block (the products' sub-blocks).
+int bicg_stride(int G) { return hz::kSolSubs * std::max(G, kMaxGrid); }
+
 template <typename T>
 size_t ws_layout(int n, int64_t nnz, bool jacobi, int nsys, int G, char* base, SolveWs* out) {
     const size_t vb = align_up(sizeof(cx<T>) * size_t(n > 0 ? n : 1));
-    const int stride = std::max(G, kMaxGrid);
+    const int stride = bicg_stride(G);
     size_t off = 0;
     auto take = [&](size_t bytes) -> void* {
         void* p = base ? base + off : nullptr;
@@ -493,7 +498,7 @@ hz::BicgArgs<T> bicg_args(const WorkMap& m, const int* rp, const int* ci, const 
                           const SolveWs& w) {
     hz::BicgArgs<T> a{};
     a.G = m.G;
-    a.stride = m.stride;
+    a.stride = bicg_stride(m.G);
     a.bmap = w.bmap;
     a.smap = w.smap;
     a.ndone = w.ndone;
@@ -528,10 +533,37 @@ int upload_map(hipStream_t s, const WorkMap& m, const SolveWs& w) {
 // initialised (k_fin_init ran).  Launches at most maxiter iterations, then
 // one more first kernel that concludes the last iteration; polls the
 // done-counter between chunks of 8, 16, ..., 64 iterations.
+// The gather-light products of a one-system solve on the block-tile row loop
+// (L = 1) run as sub-blocks with an LDS result ring (k_bicg_A1t, k_bicg_B1t);
+// the returned arguments carry their partial layout.
+template <typename T> bool sub_products(const WorkMap& m, int L, bool fused) { return L == 1 && m.nsys == 1 && !fused; }
+template <typename T> hz::BicgArgs<T> iteration_args(const WorkMap& m, hz::BicgArgs<T> a, int L, bool fused) {
+    a.pf = sub_products<T>(m, L, fused) ? hz::kSolSubs : 1;
+    return a;
+}
+
+// One gather-light iteration (P, A1, S, B1, C) on stream q.
+template <typename T, int LL, int UU>
+void enqueue_gather_light(hipStream_t q, const WorkMap& m, const hz::BicgArgs<T>& a, bool sub) {
+    const dim3 G(m.G), B(kBlock);
+    hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, q, a);
+    if (sub)
+        hipLaunchKernelGGL((hz::k_bicg_A1t<T>), dim3(hz::kSolSubs * m.G), dim3(hz::kSpBlock), 0, q, a);
+    else
+        hipLaunchKernelGGL((hz::k_bicg_A1<T, LL, UU>), G, B, 0, q, a);
+    hipLaunchKernelGGL((hz::k_bicg_S<T>), G, B, 0, q, a);
+    if (sub)
+        hipLaunchKernelGGL((hz::k_bicg_B1t<T>), dim3(hz::kSolSubs * m.G), dim3(hz::kSpBlock), 0, q, a);
+    else
+        hipLaunchKernelGGL((hz::k_bicg_B1<T, LL, UU>), G, B, 0, q, a);
+}
+
 template <typename T>
-int iterate(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>& a, int L, int maxiter, bool fused,
+int iterate(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>& a0, int L, int maxiter, bool fused,
             bool poll_done = true, bool graphs = true) {
     const dim3 G(m.G), B(kBlock);
+    const hz::BicgArgs<T> a = iteration_args(m, a0, L, fused);
+    const bool sub = sub_products<T>(m, L, fused);
     int launched = 0, poll = poll_done ? 8 : 64;
     while (launched < maxiter) {
         const int k_n = (maxiter - launched) < poll ? (maxiter - launched) : poll;
@@ -549,10 +581,7 @@ int iterate(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>
                         hipLaunchKernelGGL((hz::k_bicg_A<T, LL, UU>), G, B, 0, q, a);
                         hipLaunchKernelGGL((hz::k_bicg_B<T, LL, UU>), G, B, 0, q, a);
                     } else {
-                        hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, q, a);
-                        hipLaunchKernelGGL((hz::k_bicg_A1<T, LL, UU>), G, B, 0, q, a);
-                        hipLaunchKernelGGL((hz::k_bicg_S<T>), G, B, 0, q, a);
-                        hipLaunchKernelGGL((hz::k_bicg_B1<T, LL, UU>), G, B, 0, q, a);
+                        enqueue_gather_light<T, LL, UU>(q, m, a, sub);
                     }
                     hipLaunchKernelGGL((hz::k_bicg_C<T>), G, B, 0, q, a);
                 }
@@ -1796,7 +1825,7 @@ int solve_mixed(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, cons
     int rc = upload_map(s, m, mw.in);
     if (rc) return rc;
     const dim3 one(1), B(kBlock);
-    double* partI = mw.in.part + hz::kPartI * m.stride;
+    double* partI = mw.in.part + hz::kPartI * bicg_stride(m.G);  // the inner solve's region I
 
     hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.outer, 1, rtol, max_outer);
     hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.in.sc, 1, inner_rtol, maxiter);
@@ -1870,9 +1899,11 @@ int solve_mixed(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, cons
 
 // Enqueue k iterations of the single-system BiCGStab (no poll).
 template <typename T>
-int launch_iterations(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>& a, int L, int k,
+int launch_iterations(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::BicgArgs<T>& a0, int L, int k,
                       bool fused) {
     const dim3 G(m.G), B(kBlock);
+    const hz::BicgArgs<T> a = iteration_args(m, a0, L, fused);
+    const bool sub = sub_products<T>(m, L, fused);
     const int family = (fused ? 3 : 4) + (sizeof(T) == 4 ? 10 : 0);
     return launch_chunk(h, s, chunk_key(family, L, k, 0, a), [&](hipStream_t q) {
         with_lanes(L, [&]<int LL, int UU>() {
@@ -1881,10 +1912,7 @@ int launch_iterations(hz_handle* h, hipStream_t s, const WorkMap& m, const hz::B
                     hipLaunchKernelGGL((hz::k_bicg_A<T, LL, UU>), G, B, 0, q, a);
                     hipLaunchKernelGGL((hz::k_bicg_B<T, LL, UU>), G, B, 0, q, a);
                 } else {
-                    hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, q, a);
-                    hipLaunchKernelGGL((hz::k_bicg_A1<T, LL, UU>), G, B, 0, q, a);
-                    hipLaunchKernelGGL((hz::k_bicg_S<T>), G, B, 0, q, a);
-                    hipLaunchKernelGGL((hz::k_bicg_B1<T, LL, UU>), G, B, 0, q, a);
+                    enqueue_gather_light<T, LL, UU>(q, m, a, sub);
                 }
                 hipLaunchKernelGGL((hz::k_bicg_C<T>), G, B, 0, q, a);
             }
@@ -1914,7 +1942,7 @@ int solve_mixed_reliable(hz_handle* h, hipStream_t s, int n, int nnz, const int*
     int rc = upload_map(s, m, mw.in);
     if (rc) return rc;
     const dim3 one(1), B(kBlock);
-    double* partI = mw.in.part + hz::kPartI * m.stride;
+    double* partI = mw.in.part + hz::kPartI * bicg_stride(m.G);  // the inner solve's region I
     hipLaunchKernelGGL(hz::k_sc_init, one, dim3(64), 0, s, mw.outer, 1, rtol, max_updates);
     const double2* dinv64 = nullptr;
     if (jacobi) {

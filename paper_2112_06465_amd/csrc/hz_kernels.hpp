@@ -176,10 +176,11 @@ template <int L, typename T> __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
-// Block sum of K doubles; the result is valid in thread 0 only.  Waves are
-// combined in a fixed order.  Safe to call repeatedly in one kernel.
-template <int K> __device__ __forceinline__ void block_sum(double (&v)[K]) {
-    __shared__ double lds[kBlock / kWave][K];
+// Block sum of K doubles over a block of NT threads; the result is valid in
+// thread 0 only.  Waves are combined in a fixed order.  Safe to call
+// repeatedly in one kernel.
+template <int K, int NT = kBlock> __device__ __forceinline__ void block_sum(double (&v)[K]) {
+    __shared__ double lds[NT / kWave][K];
     const int wid = threadIdx.x / kWave, lane = threadIdx.x % kWave;
 #pragma unroll
     for (int k = 0; k < K; ++k) v[k] = group_sum<64>(v[k]);
@@ -193,7 +194,7 @@ template <int K> __device__ __forceinline__ void block_sum(double (&v)[K]) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             double s = lds[0][k];
-            for (int w = 1; w < kBlock / kWave; ++w) s += lds[w][k];
+            for (int w = 1; w < NT / kWave; ++w) s += lds[w][k];
             v[k] = s;
         }
     }
@@ -525,7 +526,8 @@ struct SysMap {
 
 template <typename T> struct BicgArgs {
     int G;       // blocks of every solver launch (a multiple of 8, or < 8)
-    int stride;  // partial component stride (>= G)
+    int stride;  // partial component stride (>= pf G)
+    int pf = 1;  // partial slots per block in regions A and B (kSolSubs when the products run as sub-blocks)
     const BlockMap* bmap;
     const SysMap* smap;
     int* ndone;  // systems finished so far
@@ -625,12 +627,19 @@ __device__ __forceinline__ void sys_sum(const double* __restrict__ part, int str
     for (int k = 0; k < K; ++k) out[k] = bc[k];
 }
 
+// Thread 0 writes the block's totals to slot pf lb of each component and
+// zeros to the pf - 1 slots after it (a region whose other components come
+// from a launch of pf times as many blocks).
 template <int K>
-__device__ __forceinline__ void store_sys_partials(double* __restrict__ part, int stride, int lb, double (&e)[K]) {
+__device__ __forceinline__ void store_sys_partials(double* __restrict__ part, int stride, int lb, double (&e)[K],
+                                                   int pf = 1) {
     block_sum<K>(e);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) part[k * stride + lb] = e[k];
+        for (int k = 0; k < K; ++k) {
+            part[k * stride + pf * lb] = e[k];
+            for (int f = 1; f < pf; ++f) part[k * stride + pf * lb + f] = 0.0;
+        }
     }
 }
 
@@ -825,7 +834,7 @@ __device__ __forceinline__ bool alpha_step(const BicgArgs<T>& a, const SysBlock&
     it = sc->cur;
     const double2 rho = sc->rho2[it & 1];  // written by the iteration's first kernel; read before the barriers
     double h[2];
-    sys_sum<2>(a.part + kPartA * a.stride, a.stride, q.gbeg, q.gcnt, h);
+    sys_sum<2>(a.part + kPartA * a.stride, a.stride, a.pf * q.gbeg, a.pf * q.gcnt, h);
     const double2 sigma = mk<double>(h[0], h[1]);
     if (!zfinite(sigma) || zzero(sigma)) {
         if (sys_leader(q)) finish(sc, a.ndone, zzero(sigma) ? ST_BREAKDOWN : ST_NONFINITE, it, zzero(sigma) ? BD_RHAT_V : BD_NONE);
@@ -872,7 +881,7 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_C(const BicgArgs<T> a) {
     const double bnorm = sc->bnorm, rtol = sc->rtol;  // read before the reduction's barriers
     const double2 alpha = sc->alpha;
     double h[4];
-    sys_sum<4>(a.part + kPartB * a.stride, a.stride, q.gbeg, q.gcnt, h);
+    sys_sum<4>(a.part + kPartB * a.stride, a.stride, a.pf * q.gbeg, a.pf * q.gcnt, h);
     const double rel = __builtin_sqrt(h[0]) / bnorm;
     const cx<T> al = narrow<T>(alpha);
     const cx<T>* __restrict__ p = a.p[it & 1];
@@ -991,7 +1000,7 @@ __global__ HZ_STREAM_BOUNDS void k_bicg_S(const BicgArgs<T> a) {
         e[0] = __builtin_fma((double)s.x, (double)s.x, e[0]);
         e[0] = __builtin_fma((double)s.y, (double)s.y, e[0]);
     }
-    store_sys_partials<1>(a.part + kPartB * a.stride, a.stride, q.lb, e);
+    store_sys_partials<1>(a.part + kPartB * a.stride, a.stride, q.lb, e, a.pf);
 }
 
 template <typename T, int L, int U>

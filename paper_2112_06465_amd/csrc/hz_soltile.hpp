@@ -1,0 +1,97 @@
+// The two row products of the gather-light BiCGStab iteration (Section 7:
+// v = A p with <rhat, v>, and t = A s with <t, s> and ||t||^2) in the
+// standalone product's tile form, for one large system.
+//
+// The solver's other kernels run 1024-thread blocks, at most kMaxGrid of
+// them, and under their 64-VGPR budget a product could not hold its results
+// back without spilling; its stores then sat in front of the next tile's
+// loads (one in-order counter tracks both).  These kernels run each logical
+// block of the solver's map as kSolSubs blocks of kSpBlock threads (half the
+// waves per CU, twice the registers per wave) through tile_loop with its LDS
+// ring: the epilogue operand of each row (rhat or s) is loaded with the
+// tile's matrix entries and the row's terms go into the block's dot products
+// as soon as the tile is summed, while the totals v (or t) are held for kHold
+// tiles and stored when the ring is flushed.  Sub-block j of logical block lb
+// takes 64-row tiles k' = kSolSubs k + j of its group's rows (K' = kSolSubs
+// K), and writes its partials to slot kSolSubs lb + j; the region's readers
+// sum kSolSubs slots per block (BicgArgs::pf), and the S kernel, which writes
+// the region's first component with the logical blocks, fills the extra
+// slots with zeros.  Sums are taken in a fixed order: results are bitwise
+// reproducible.
+#pragma once
+
+#include "hz_spmv.hpp"
+
+namespace hz {
+
+constexpr int kSolSubs = 2;  // product blocks per logical block of the solver's map
+
+struct SubBlock {
+    int ls, sys;
+    Rows rw;
+};
+template <typename T> __device__ __forceinline__ SubBlock sub_block(const BicgArgs<T>& a) {
+    SubBlock q;
+    q.ls = logical_block(blockIdx.x, kSolSubs * a.G);
+    const BlockMap m = a.bmap[q.ls / kSolSubs];
+    q.sys = m.sys;
+    q.rw.x0 = m.x0;
+    q.rw.x1 = m.x1;
+    q.rw.k = kSolSubs * m.k + q.ls % kSolSubs;
+    q.rw.K = kSolSubs * m.K;
+    return q;
+}
+
+template <int K>
+__device__ __forceinline__ void store_sub_partials(double* __restrict__ part, int stride, int ls, double (&e)[K]) {
+    block_sum<K, kSpBlock>(e);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) part[k * stride + ls] = e[k];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSpBlock) void k_bicg_A1t(const BicgArgs<T> a) {
+    const SubBlock q = sub_block(a);
+    if (q.sys < 0) return;
+    const SolverScal* sc = a.sc + q.sys;
+    if (sc->done || sc->pending) return;
+    const int it = sc->cur;
+    const cx<T>* __restrict__ p = a.p[it & 1];
+    cx<T>* __restrict__ v = a.v[it & 1];
+    const cx<T>* __restrict__ rh = a.rh;
+    double e[2] = {0.0, 0.0};
+    tile_loop<T, kHold>(
+        q.rw, a.row_ptr, a.col_idx, a.vals, [p](int c) { return p[c]; }, [rh](int64_t row) { return rh[row]; },
+        [&](int64_t, cx<T> acc, cx<T> w) {
+            const double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+        },
+        [v](int64_t row, cx<T> acc) { v[row] = acc; });
+    store_sub_partials<2>(a.part + kPartA * a.stride, a.stride, q.ls, e);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSpBlock) void k_bicg_B1t(const BicgArgs<T> a) {
+    const SubBlock q = sub_block(a);
+    if (q.sys < 0) return;
+    if (a.sc[q.sys].done) return;
+    const cx<T>* __restrict__ sv = a.s;
+    cx<T>* __restrict__ tv = a.t;
+    double e[3] = {0.0, 0.0, 0.0};
+    tile_loop<T, kHold>(
+        q.rw, a.row_ptr, a.col_idx, a.vals, [sv](int c) { return sv[c]; }, [sv](int64_t row) { return sv[row]; },
+        [&](int64_t, cx<T> acc, cx<T> s) {
+            const double2 c = cdotacc(acc.x, acc.y, s.x, s.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+            e[2] = __builtin_fma((double)acc.x, (double)acc.x, e[2]);
+            e[2] = __builtin_fma((double)acc.y, (double)acc.y, e[2]);
+        },
+        [tv](int64_t row, cx<T> acc) { tv[row] = acc; });
+    store_sub_partials<3>(a.part + (kPartB + 1) * a.stride, a.stride, q.ls, e);
+}
+
+}  // namespace hz

@@ -133,43 +133,46 @@ __global__ __launch_bounds__(kSpBlock) void k_spmv_pipe(const SpArgs<T> a) {
     }
 }
 
-// The tile loop of a block.  HOLD > 1: results go through the LDS ring of
-// HOLD tiles (blocks looping over many tiles); HOLD = 1: each tile's results
-// are stored at once (one tile per block, where a ring would only cost LDS,
-// and so resident blocks).
-template <typename T, int HOLD>
-__device__ __forceinline__ void spmv_tiles(const SpArgs<T>& a) {
+// The tile loop of a block over the 64-row tiles that `rw` describes (the
+// block is the rw.k-th of rw.K taking the tiles of [x0, x1) in turn).  op(col)
+// is the gathered operand.  Each row's total goes to tail(row, total,
+// pre(row)) as soon as the tile is summed (pre: an operand per row, loaded
+// with the tile's matrix entries; NoPre: no load) and to put(row, total),
+// which stores it.  HOLD > 1: put runs when an LDS ring of HOLD tiles' totals
+// is flushed (full, or at the end); HOLD = 1: at once (one tile per block,
+// where a ring would only cost LDS, and so resident blocks).  A flush issues
+// stores only, so its stores hold up the next tile's loads once per HOLD
+// tiles and the last flush leaves nothing to wait for.  A tile of empty rows
+// loads nothing; every branch is uniform across the block.
+template <typename T, int HOLD, typename Op, typename Pre, typename Tail, typename Put>
+__device__ __forceinline__ void tile_loop(const Rows& rw, const int* __restrict__ rp, const int* __restrict__ ci,
+                                          const cx<T>* __restrict__ vals, Op op, Pre pre, Tail tail, Put put) {
     constexpr int L = kTileLanes;
     __shared__ cx<T> prod[kTileCap];
-    __shared__ cx<T> held[HOLD > 1 ? HOLD * kTileRows : 1];  // results of the block's last tiles, by tile
-    const RowRange rr = rows_of_block(a.n, a.geo);
+    __shared__ cx<T> held[HOLD > 1 ? HOLD * kTileRows : 1];  // totals of the block's last tiles, by tile
     const int t = threadIdx.x, g = t / L, lane = t % L;
-    const int64_t first = rr.rw.x0 + (int64_t)rr.rw.k * kTileRows, step = (int64_t)rr.rw.K * kTileRows;
-    const int64_t r1 = rr.rw.x1;
-    const int* __restrict__ rp = a.row_ptr;
-    const int* __restrict__ ci = a.col_idx;
-    const cx<T>* __restrict__ vals = a.vals;
-    const cx<T>* __restrict__ x = a.x;
-    const int nnz = a.nnz;
-    // y for the `count` held tiles starting at the block's tile `base` (every thread; uniform)
+    const int64_t first = rw.x0 + (int64_t)rw.k * kTileRows, step = (int64_t)rw.K * kTileRows;
+    const int64_t r1 = rw.x1;
+    // the `count` held tiles starting at the block's tile `base` (every thread; uniform)
     auto flush = [&](int64_t base, int count) {
-        __syncthreads();  // the held results are written
+        __syncthreads();  // the held totals are written
         for (int q = t; q < count * kTileRows; q += kSpBlock) {
             const int64_t row = first + (base + q / kTileRows) * step + q % kTileRows;
-            if (row < r1) a.y[a.yperm != nullptr ? a.yperm[row] : row] = held[q];
+            if (row < r1) put(row, held[q]);
         }
         __syncthreads();  // the ring may be refilled
     };
-    int64_t tile = 0;                                             // the block's tile counter
+    int64_t tile = 0;                                        // the block's tile counter
     for (int64_t r0 = first; r0 < r1; r0 += step, ++tile) {  // uniform across the block
         const int64_t re = r0 + kTileRows < r1 ? r0 + kTileRows : r1;
         const int e0 = rp[r0], e1 = rp[re];
         const int64_t row = r0 + g;
         const int b = rp[row < re ? row : re], e = rp[row + 1 < re ? row + 1 : re];
+        const auto w = pre(row < re ? row : re - 1);
         cx<T> acc = mk<T>(T(0), T(0));
-        if (e1 - e0 <= kTileCap) {
+        if (e1 > e0 && e1 - e0 <= kTileCap) {
             // straight-line streaming loads: entry e0 + t + k kSpBlock, clamped into the tile
-            const int last = e1 > e0 ? e1 - 1 : (e0 < nnz ? e0 : nnz - 1);
+            const int last = e1 - 1;
             int c[kTilePer];
             cx<T> v[kTilePer], o[kTilePer];
 #pragma unroll
@@ -183,7 +186,7 @@ __device__ __forceinline__ void spmv_tiles(const SpArgs<T>& a) {
                 v[k] = ld_mat(vals + (p < last ? p : last));
             }
 #pragma unroll
-            for (int k = 0; k < kTilePer; ++k) o[k] = x[c[k]];
+            for (int k = 0; k < kTilePer; ++k) o[k] = op(c[k]);
 #pragma unroll
             for (int k = 0; k < kTilePer; ++k) {
                 const bool ok = e0 + t + k * kSpBlock < e1;
@@ -197,22 +200,38 @@ __device__ __forceinline__ void spmv_tiles(const SpArgs<T>& a) {
                 acc.y += pv.y;
             }
             __syncthreads();
-        } else if (row < re) {
-            acc = row_partial<T, L, 1>(b, e, lane, ci, vals, [x](int cc) { return x[cc]; });
+        } else if (e1 > e0 && row < re) {
+            acc = row_partial<T, L, 1>(b, e, lane, ci, vals, op);
         }
         acc.x = group_sum<L>(acc.x);
         acc.y = group_sum<L>(acc.y);
+        if (row < re && lane == 0) tail(row, acc, w);
         if constexpr (HOLD > 1) {
             const int slot = (int)(tile % HOLD);
             if (lane == 0) held[slot * kTileRows + g] = acc;  // (rows past the range are skipped by the flush)
             if (slot == HOLD - 1) flush(tile - (HOLD - 1), HOLD);
         } else if (row < re && lane == 0) {
-            a.y[a.yperm != nullptr ? a.yperm[row] : row] = acc;
+            put(row, acc);
         }
     }
     if constexpr (HOLD > 1) {
         if (tile % HOLD != 0) flush(tile - tile % HOLD, (int)(tile % HOLD));
     }
+}
+
+// No per-row work besides the store.
+struct NoTail {
+    template <typename A, typename W> __device__ void operator()(int64_t, A, W) const {}
+};
+
+template <typename T, int HOLD>
+__device__ __forceinline__ void spmv_tiles(const SpArgs<T>& a) {
+    const RowRange rr = rows_of_block(a.n, a.geo);
+    const cx<T>* __restrict__ x = a.x;
+    cx<T>* __restrict__ y = a.y;
+    const int* __restrict__ yperm = a.yperm;
+    tile_loop<T, HOLD>(rr.rw, a.row_ptr, a.col_idx, a.vals, [x](int c) { return x[c]; }, NoPre{}, NoTail{},
+                       [=](int64_t row, cx<T> acc) { y[yperm != nullptr ? yperm[row] : row] = acc; });
 }
 
 template <typename T>
