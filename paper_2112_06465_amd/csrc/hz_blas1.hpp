@@ -201,28 +201,37 @@ __global__ __launch_bounds__(kB1Block) void k_zdot_s(int64_t n, int per, const d
     __syncthreads();  // `skip` and the reuse of w below
     bool late = skip != 0u || sl.limit == 0;
     const uint64_t t0 = wall_clock64();
+    // slot i of every component is loaded at once (one round trip to L2 for all K), then each is
+    // waited for in turn; per component the slots are added in index order
     double tot[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double t = 0.0;
-        for (int i = threadIdx.x; i < G && !late; i += kB1Block) {
-            unsigned long long* p = sl.slot + int64_t(k) * G + i;
-            unsigned long long u = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            while (u == kB1SlotEmpty) {
+    for (int k = 0; k < K; ++k) tot[k] = 0.0;
+    for (int i = threadIdx.x; i < G && !late; i += kB1Block) {
+        unsigned long long u[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            u[k] = __hip_atomic_load(sl.slot + int64_t(k) * G + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            while (!late && u[k] == kB1SlotEmpty) {
                 __builtin_amdgcn_s_sleep(1);
                 if (wall_clock64() - t0 > sl.limit) {
                     late = true;
                     break;
                 }
-                u = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                u[k] = __hip_atomic_load(sl.slot + int64_t(k) * G + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            if (late) break;
-            t += __longlong_as_double(static_cast<long long>(u));
-            __hip_atomic_store(p, kB1SlotEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
-        tot[k] = t;
+        if (late) break;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            tot[k] += __longlong_as_double(static_cast<long long>(u[k]));
+            __hip_atomic_store(sl.slot + int64_t(k) * G + i, kB1SlotEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int off = 32; off > 0; off >>= 1) tot[k] += __shfl_down(tot[k], off, 64);
     const bool any_late = __syncthreads_or(late);
 #pragma unroll
     for (int k = 0; k < K; ++k)
