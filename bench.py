@@ -727,10 +727,11 @@ def profile(what, steps, cache_dir):
     elif what == "solve-cabin":
         cab = Cabin(hz, torch, dev, cache_dir)
         for _ in range(steps):
+            t0 = time.perf_counter()
             _, info = hz.zbicgstab_solve(cab.rp, cab.ci, cab.vals, cab.b, rtol=1e-10, maxiter=50000,
                                          flags=hz.PRECOND_JACOBI | hz.X0_ZERO)
             torch.cuda.synchronize()
-            print(what, info, flush=True)
+            print(what, "ms", round(1e3 * (time.perf_counter() - t0), 2), info, flush=True)
     elif what == "solve-cylinder":
         import workloads as W
 
