@@ -250,8 +250,8 @@ def spmv_cabin(hz, torch, dev, cab, reps=20):
            "analysis_ms": round(cab.analysis_ms, 3), "levels": cab.levels}
     L = rule_lanes(n, nnz)
     launch = lambda r: hz.csr_zspmv(*r)  # noqa: E731
-    for label, level, form in (("given_numbering", False, "rows"), ("level_sets_rows", True, "rows"),
-                               ("level_sets_tiles", True, "tiles")):
+    for label, level, form in (("given_numbering", False, "rows"), ("given_numbering_tiles", False, "tiles"),
+                               ("level_sets_rows", True, "rows"), ("level_sets_tiles", True, "tiles")):
         reps_ = cab.replicas(torch, level)
         with PinnedForm(form, L if form == "rows" else None):
             loop = ColdLoop(torch, launch, reps_, reps)
@@ -717,8 +717,9 @@ def profile(what, steps, cache_dir):
             loop = ColdLoop(torch, lambda e: hz.hyb_zspmv(e[0], cab.xp, e[1]), list(zip(ell, ys)), 30)
             form = None
         else:
-            level = what != "spmv-cabin-given"
-            form = {"spmv-cabin": CABIN_FORM, "spmv-cabin-rows": "rows", "spmv-cabin-given": "rows"}[what]
+            level = not what.startswith("spmv-cabin-given")
+            form = {"spmv-cabin": CABIN_FORM, "spmv-cabin-rows": "rows", "spmv-cabin-given": "rows",
+                    "spmv-cabin-given-tiles": "tiles"}[what]
             loop = ColdLoop(torch, lambda r: hz.csr_zspmv(*r), cab.replicas(torch, level), 30)
         for _ in range(steps):
             with PinnedForm(form or "rows", L if form == "rows" else None):
@@ -811,7 +812,7 @@ def main():
     ap.add_argument("--cache", default=None, help="directory to keep generated workloads in (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--profile", default=None,
-                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | solve-cylinder | "
+                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-given-tiles | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | solve-cylinder | "
                          "sweep-explicit | sweep-kmb | "
                          "adjoint-cylinder | stream | blas1")
     ap.add_argument("--no-cpu-baseline", action="store_true")

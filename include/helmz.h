@@ -128,12 +128,14 @@ enum { HZ_SPMV_FORM_ROWS = 0, HZ_SPMV_FORM_TILES = 1 };
  *    csr_zspmv_rect): vector rows with each L, or block tiles.
  * Each candidate is timed on the caller's matrix and vectors (two rounds of
  * 5 launches after 2 warm-up launches, HIP events on `stream`); the fastest
- * (the built-in rule's choice unless another is more than 3 % faster) are
+ * (the untuned choice unless another is more than 3 % faster) are
  * recorded in the handle for this (row_ptr, col_idx, n, nnz), and later
  * products and solves on the same handle with the same index arrays use
- * them (results change only by summation order).  Without tuning, both use
- * vector rows with the smallest power of two L not below half the mean row
- * length.  Writes the solver lane count to *lanes, and, where the pointers
+ * them (results change only by summation order).  Without tuning, the
+ * solver kernels use vector rows with the smallest power of two L not below
+ * half the mean row length (block tiles for a one-system FP64 solve whose
+ * values exceed 128 MiB), and the standalone product uses block tiles when
+ * the mean row length is at most 16 entries, else vector rows with that L.  Writes the solver lane count to *lanes, and, where the pointers
  * are not NULL, the standalone form to *form (HZ_SPMV_FORM_*) and its lane
  * count to *form_lanes (host memory).  y is overwritten with A x.
  * Synchronises the stream.  The environment variables HZ_SPMV_LANES (a lane
