@@ -733,6 +733,16 @@ def profile(what, steps, cache_dir):
                                          flags=hz.PRECOND_JACOBI | hz.X0_ZERO)
             torch.cuda.synchronize()
             print(what, "ms", round(1e3 * (time.perf_counter() - t0), 2), info, flush=True)
+    elif what == "solve-cabin-mixed":
+        cab = Cabin(hz, torch, dev, cache_dir)
+        for _ in range(steps):
+            for label, extra in (("restarted", 0), ("reliable", hz.RELIABLE)):
+                t0 = time.perf_counter()
+                _, info = hz.zbicgstab_solve_mixed(cab.rp, cab.ci, cab.vals, cab.b, rtol=1e-10, maxiter=50000,
+                                                   inner_rtol=None if extra else 1e-4,
+                                                   flags=hz.PRECOND_JACOBI | hz.X0_ZERO | extra)
+                torch.cuda.synchronize()
+                print(what, label, "ms", round(1e3 * (time.perf_counter() - t0), 2), info, flush=True)
     elif what == "solve-cylinder":
         import workloads as W
 
@@ -812,7 +822,7 @@ def main():
     ap.add_argument("--cache", default=None, help="directory to keep generated workloads in (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--profile", default=None,
-                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-given-tiles | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | solve-cylinder | "
+                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-given-tiles | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | solve-cabin-mixed | solve-cylinder | "
                          "sweep-explicit | sweep-kmb | "
                          "adjoint-cylinder | stream | blas1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
