@@ -1053,7 +1053,7 @@ size_t lws_layout(int n, int64_t nnz, int ell, bool jacobi, char* base, LWs* out
     };
     LWs w{};
     w.sc = static_cast<SolverScal*>(take(sizeof(SolverScal)));
-    w.part = static_cast<double*>(take(sizeof(double) * size_t(hz::kParts) * size_t(kMaxGrid)));
+    w.part = static_cast<double*>(take(sizeof(double) * size_t(hz::kParts) * size_t(bicg_stride(kMaxGrid))));
     w.bmap = static_cast<BlockMap*>(take(sizeof(BlockMap) * size_t(kMaxGrid)));
     w.smap = static_cast<SysMap*>(take(sizeof(SysMap)));
     w.ndone = static_cast<int*>(take(sizeof(int)));
@@ -1113,7 +1113,7 @@ int solve_l(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const in
     // the BiCGStab set-up and finishing kernels on the same map, scalars and partials
     hz::BicgArgs<double> ba{};
     ba.G = m.G;
-    ba.stride = m.stride;
+    ba.stride = bicg_stride(m.G);  // room for the sub-block products' slots (shared regions C and I)
     ba.bmap = w.bmap;
     ba.smap = w.smap;
     ba.ndone = w.ndone;
@@ -1147,7 +1147,9 @@ int solve_l(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const in
 
     hz::LArgs la{};
     la.G = m.G;
-    la.stride = m.stride;
+    la.stride = ba.stride;
+    const bool sub = L == 1;  // the tile row loop: AU and AR as sub-blocks with the LDS result ring
+    la.pf = sub ? hz::kSolSubs : 1;
     la.bmap = w.bmap;
     la.smap = w.smap;
     la.ndone = w.ndone;
@@ -1174,9 +1176,15 @@ int solve_l(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const in
                 hz::LArgs aj = la;
                 aj.j = j;
                 hipLaunchKernelGGL(hz::k_l_U, G, B, 0, q, aj);
-                hipLaunchKernelGGL((hz::k_l_AU<LL, UU>), G, B, 0, q, aj);
+                if (sub)
+                    hipLaunchKernelGGL(hz::k_l_AUt, dim3(hz::kSolSubs * m.G), dim3(hz::kSpBlock), 0, q, aj);
+                else
+                    hipLaunchKernelGGL((hz::k_l_AU<LL, UU>), G, B, 0, q, aj);
                 hipLaunchKernelGGL(hz::k_l_R, G, B, 0, q, aj);
-                hipLaunchKernelGGL((hz::k_l_AR<LL, UU>), G, B, 0, q, aj);
+                if (sub)
+                    hipLaunchKernelGGL(hz::k_l_ARt, dim3(hz::kSolSubs * m.G), dim3(hz::kSpBlock), 0, q, aj);
+                else
+                    hipLaunchKernelGGL((hz::k_l_AR<LL, UU>), G, B, 0, q, aj);
             }
         });
         with_ell(ell, [&]<int EL>() {

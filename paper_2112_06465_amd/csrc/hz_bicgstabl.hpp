@@ -24,6 +24,7 @@
 #pragma once
 
 #include "hz_kernels.hpp"
+#include "hz_soltile.hpp"
 
 namespace hz {
 
@@ -51,6 +52,7 @@ struct LArgs {
     SolverScal* sc;
     int n, ell, j;    // rows, l, the Bi-CG step of this launch
     int gG;           // blocks of the Gram launch
+    int pf = 1;       // partial slots per block that AU and AR write (kSolSubs when they run as sub-blocks)
 };
 
 __device__ __forceinline__ SysBlock lblock(const LArgs& a) {
@@ -90,7 +92,8 @@ __global__ HZ_STREAM_BOUNDS void k_l_U(const LArgs a) {
     const double2 alpha = sc->alpha, omega = sc->omega;
     const double2 rho_prev = s == 0 ? mk<double>(1.0, 0.0) : sc->rho2[(s + 1) & 1];
     double h[3];
-    sys_sum<3>(a.part + kPartC * a.stride, a.stride, q.gbeg, q.gcnt, h);
+    const int pf = a.j > 0 ? a.pf : 1;  // region C from AR (step j - 1), or from the update / set-up (j = 0)
+    sys_sum<3>(a.part + kPartC * a.stride, a.stride, pf * q.gbeg, pf * q.gcnt, h);
     const double2 rho1 = mk<double>(h[0], h[1]);
     double2 rho0 = rho_prev;
     if (a.j == 0) {  // a cycle starts: test the residual of the previous one
@@ -158,7 +161,7 @@ __global__ HZ_STREAM_BOUNDS void k_l_R(const LArgs a) {
     const int s = (it - 1) * a.ell + a.j;
     const double2 rho1 = sc->rho2[s & 1];
     double h[2];
-    sys_sum<2>(a.part + kPartA * a.stride, a.stride, q.gbeg, q.gcnt, h);
+    sys_sum<2>(a.part + kPartA * a.stride, a.stride, a.pf * q.gbeg, a.pf * q.gcnt, h);
     const double2 g = mk<double>(h[0], h[1]);
     int st = -1, why = BD_NONE;
     double2 alpha = mk<double>(0.0, 0.0);
@@ -198,6 +201,45 @@ __global__ HZ_STREAM_BOUNDS void k_l_AR(const LArgs a) {
                                e[1] = c.y;
                            });
     store_sys_partials<3>(a.part + kPartC * a.stride, a.stride, q.lb, e);
+}
+
+// AU and AR on a large system: the tile loop of the standalone product as
+// kSolSubs blocks of kSpBlock threads per block of the map (r~ loaded with the
+// tile, the product held in the LDS ring), one partial slot per sub-block.
+__global__ __launch_bounds__(kSpBlock) void k_l_AUt(const LArgs a) {
+    const SubBlock q = sub_block_of(a.bmap, a.G);
+    if (q.sys < 0 || a.sc[q.sys].done) return;
+    const double2* __restrict__ uj = a.u[a.j];
+    double2* __restrict__ un = a.u[a.j + 1];
+    const double2* __restrict__ rt = a.rt;
+    double e[2] = {0.0, 0.0};
+    tile_loop<double, kHold>(
+        q.rw, a.row_ptr, a.col_idx, a.vals, [uj](int c) { return uj[c]; }, [rt](int64_t row) { return rt[row]; },
+        [&](int64_t, double2 acc, double2 w) {
+            const double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+        },
+        [un](int64_t row, double2 acc) { un[row] = acc; });
+    store_sub_partials<2>(a.part + kPartA * a.stride, a.stride, q.ls, e);
+}
+
+__global__ __launch_bounds__(kSpBlock) void k_l_ARt(const LArgs a) {
+    const SubBlock q = sub_block_of(a.bmap, a.G);
+    if (q.sys < 0 || a.sc[q.sys].done) return;
+    const double2* __restrict__ rj = a.r[a.j];
+    double2* __restrict__ rn = a.r[a.j + 1];
+    const double2* __restrict__ rt = a.rt;
+    double e[3] = {0.0, 0.0, 0.0};  // the norm slot is unused before the cycle's end
+    tile_loop<double, kHold>(
+        q.rw, a.row_ptr, a.col_idx, a.vals, [rj](int c) { return rj[c]; }, [rt](int64_t row) { return rt[row]; },
+        [&](int64_t, double2 acc, double2 w) {
+            const double2 c = cdotacc(w.x, w.y, acc.x, acc.y, mk<double>(e[0], e[1]));
+            e[0] = c.x;
+            e[1] = c.y;
+        },
+        [rn](int64_t row, double2 acc) { rn[row] = acc; });
+    store_sub_partials<3>(a.part + kPartC * a.stride, a.stride, q.ls, e);
 }
 
 // Gram partials of <r_p, r_q>, 0 <= p <= q <= ELL, pair index in row-major

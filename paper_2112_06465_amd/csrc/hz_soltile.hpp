@@ -1,6 +1,7 @@
 // The two row products of the gather-light BiCGStab iteration (Section 7:
 // v = A p with <rhat, v>, and t = A s with <t, s> and ||t||^2) in the
-// standalone product's tile form, for one large system.
+// standalone product's tile form, for one large system (BiCGstab(l)'s two
+// products, with the same structure, are in hz_bicgstabl.hpp).
 //
 // The solver's other kernels run 1024-thread blocks, at most kMaxGrid of
 // them, and under their 64-VGPR budget a product could not hold its results
@@ -30,16 +31,20 @@ struct SubBlock {
     int ls, sys;
     Rows rw;
 };
-template <typename T> __device__ __forceinline__ SubBlock sub_block(const BicgArgs<T>& a) {
+// Sub-block of a launch of kSolSubs G blocks over the solver map `bmap` of G blocks.
+__device__ __forceinline__ SubBlock sub_block_of(const BlockMap* bmap, int G) {
     SubBlock q;
-    q.ls = logical_block(blockIdx.x, kSolSubs * a.G);
-    const BlockMap m = a.bmap[q.ls / kSolSubs];
+    q.ls = logical_block(blockIdx.x, kSolSubs * G);
+    const BlockMap m = bmap[q.ls / kSolSubs];
     q.sys = m.sys;
     q.rw.x0 = m.x0;
     q.rw.x1 = m.x1;
     q.rw.k = kSolSubs * m.k + q.ls % kSolSubs;
     q.rw.K = kSolSubs * m.K;
     return q;
+}
+template <typename T> __device__ __forceinline__ SubBlock sub_block(const BicgArgs<T>& a) {
+    return sub_block_of(a.bmap, a.G);
 }
 
 template <int K>

@@ -69,6 +69,24 @@ def test_iterates_follow_the_oracle(hz, ell, cycles, bound, jacobi):
     assert abs(info["relres_recursive"] - io["relres_recursive"]) <= 1e-6 * io["relres_recursive"] + 1e-14
 
 
+@pytest.mark.parametrize("ell,cycles,bound", [(1, 6, 1e-10), (4, 2, 1e-7), (8, 1, 1e-7)])
+def test_tile_products_follow_the_oracle(hz, ell, cycles, bound, monkeypatch):
+    """AU and AR on the tile row loop (lane code 1: two 256-thread blocks per block of the map, the products
+    held in an LDS ring, two partial slots per block) against the oracle, and a Jacobi solve to tolerance."""
+    monkeypatch.setenv("HZ_SPMV_LANES", "1")
+    A, b, _ = W.config_cylinder(h=0.1)
+    flags = hz.PRECOND_JACOBI | hz.X0_ZERO | hz.NO_REORDER
+    x, info = solve(hz, A, b, ell=ell, rtol=1e-30, maxcycles=cycles, flags=flags)
+    xo, io = bicgstab_l(A, b, ell=ell, tol=1e-30, maxcycles=cycles, jacobi=True)
+    assert info["status"] == hz.NOT_CONVERGED and info["iterations"] == cycles == io["iterations"]
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(f"tiles l={ell} after {cycles} cycles: rel diff {err:.2e}")
+    assert err <= bound
+    x, info = solve(hz, A, b, ell=ell, rtol=1e-10, flags=flags)
+    assert info["status"] == hz.OK, info
+    assert true_relres(A, x, b) <= 1e-10 * (1 + 1e-3)
+
+
 def test_jacobi_cylinder_converges_like_the_oracle(hz):
     A, b, _ = W.config_cylinder(h=0.08)
     flags = hz.PRECOND_JACOBI | hz.X0_ZERO

@@ -109,6 +109,24 @@ def test_large_banded_system_follows_the_oracle(hz, tile_products):
     assert np.linalg.norm(b - O.zspmv(A, x)) <= 1e-10 * (1 + 1e-3) * np.linalg.norm(b)
 
 
+def test_large_banded_system_bicgstab_l_follows_the_oracle(hz, tile_products):
+    """BiCGstab(2), whose AU and AR products take the same tile loop, on the 1.4 M-row system: two cycles
+    against the oracle's BiCGstab(l)."""
+    from oracle.bicgstabl import bicgstab_l
+
+    A = banded_dominant(1_400_017, seed=7)
+    b = cn(np.random.default_rng(4), A.n)
+    rp, ci, v = (dev(A.row_ptr), dev(A.col_idx), dev(A.vals))
+    x, info = hz.zbicgstabl_solve(rp, ci, v, dev(b), ell=2, rtol=1e-30, maxcycles=2,
+                                  flags=hz.PRECOND_JACOBI | hz.X0_ZERO | hz.NO_REORDER)
+    xo, io = bicgstab_l(A, b, ell=2, tol=1e-30, maxcycles=2, jacobi=True)
+    assert info["iterations"] == 2 == io["iterations"]
+    x = x.cpu().numpy()
+    err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    print(f"BiCGstab(2), 2 cycles: rel diff {err:.2e}")
+    assert err <= 1e-11
+
+
 def test_solves_to_tolerance_deterministic_and_graphs_equal_direct(hz, tile_products, monkeypatch):
     A, b, _ = W.config_cylinder(h=0.1, k=8.0, seed=2)
     flags = hz.PRECOND_JACOBI | hz.X0_ZERO | hz.NO_REORDER
