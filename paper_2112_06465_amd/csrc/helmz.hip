@@ -471,8 +471,8 @@ struct SolveWs {
 };
 
 // Partial component stride of the BiCGStab workspace for a map of G blocks:
-// room for kSolSubs slots per block (the products' sub-blocks).
-int bicg_stride(int G) { return hz::kSolSubs * std::max(G, kMaxGrid); }
+// room for the products' sub-blocks, sol_subs(G) G <= max(2 G, kSolSlots) slots.
+int bicg_stride(int G) { return std::max(2 * G, std::max(2 * kMaxGrid, hz::kSolSlots)); }
 
 template <typename T>
 size_t ws_layout(int n, int64_t nnz, bool jacobi, int nsys, int G, char* base, SolveWs* out) {
@@ -547,7 +547,7 @@ int upload_map(hipStream_t s, const WorkMap& m, const SolveWs& w) {
 // the returned arguments carry their partial layout.
 template <typename T> bool sub_products(const WorkMap& m, int L, bool fused) { return L == 1 && m.nsys == 1 && !fused; }
 template <typename T> hz::BicgArgs<T> iteration_args(const WorkMap& m, hz::BicgArgs<T> a, int L, bool fused) {
-    a.pf = sub_products<T>(m, L, fused) ? hz::kSolSubs : 1;
+    a.pf = sub_products<T>(m, L, fused) ? hz::sol_subs(m.G) : 1;
     return a;
 }
 
@@ -557,12 +557,12 @@ void enqueue_gather_light(hipStream_t q, const WorkMap& m, const hz::BicgArgs<T>
     const dim3 G(m.G), B(kBlock);
     hipLaunchKernelGGL((hz::k_bicg_P<T>), G, B, 0, q, a);
     if (sub)
-        hipLaunchKernelGGL((hz::k_bicg_A1t<T>), dim3(hz::kSolSubs * m.G), dim3(hz::kSpBlock), 0, q, a);
+        hipLaunchKernelGGL((hz::k_bicg_A1t<T>), dim3(a.pf * m.G), dim3(hz::kSpBlock), 0, q, a);
     else
         hipLaunchKernelGGL((hz::k_bicg_A1<T, LL, UU>), G, B, 0, q, a);
     hipLaunchKernelGGL((hz::k_bicg_S<T>), G, B, 0, q, a);
     if (sub)
-        hipLaunchKernelGGL((hz::k_bicg_B1t<T>), dim3(hz::kSolSubs * m.G), dim3(hz::kSpBlock), 0, q, a);
+        hipLaunchKernelGGL((hz::k_bicg_B1t<T>), dim3(a.pf * m.G), dim3(hz::kSpBlock), 0, q, a);
     else
         hipLaunchKernelGGL((hz::k_bicg_B1<T, LL, UU>), G, B, 0, q, a);
 }
@@ -1149,7 +1149,7 @@ int solve_l(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const in
     la.G = m.G;
     la.stride = ba.stride;
     const bool sub = L == 1;  // the tile row loop: AU and AR as sub-blocks with the LDS result ring
-    la.pf = sub ? hz::kSolSubs : 1;
+    la.pf = sub ? hz::sol_subs(m.G) : 1;
     la.bmap = w.bmap;
     la.smap = w.smap;
     la.ndone = w.ndone;
@@ -1177,12 +1177,12 @@ int solve_l(hz_handle* h, hipStream_t s, int n, int nnz, const int* rp, const in
                 aj.j = j;
                 hipLaunchKernelGGL(hz::k_l_U, G, B, 0, q, aj);
                 if (sub)
-                    hipLaunchKernelGGL(hz::k_l_AUt, dim3(hz::kSolSubs * m.G), dim3(hz::kSpBlock), 0, q, aj);
+                    hipLaunchKernelGGL(hz::k_l_AUt, dim3(aj.pf * m.G), dim3(hz::kSpBlock), 0, q, aj);
                 else
                     hipLaunchKernelGGL((hz::k_l_AU<LL, UU>), G, B, 0, q, aj);
                 hipLaunchKernelGGL(hz::k_l_R, G, B, 0, q, aj);
                 if (sub)
-                    hipLaunchKernelGGL(hz::k_l_ARt, dim3(hz::kSolSubs * m.G), dim3(hz::kSpBlock), 0, q, aj);
+                    hipLaunchKernelGGL(hz::k_l_ARt, dim3(aj.pf * m.G), dim3(hz::kSpBlock), 0, q, aj);
                 else
                     hipLaunchKernelGGL((hz::k_l_AR<LL, UU>), G, B, 0, q, aj);
             }

@@ -52,7 +52,7 @@ struct LArgs {
     SolverScal* sc;
     int n, ell, j;    // rows, l, the Bi-CG step of this launch
     int gG;           // blocks of the Gram launch
-    int pf = 1;       // partial slots per block that AU and AR write (kSolSubs when they run as sub-blocks)
+    int pf = 1;       // partial slots per block that AU and AR write (sol_subs(G) when they run as sub-blocks)
 };
 
 __device__ __forceinline__ SysBlock lblock(const LArgs& a) {
@@ -204,10 +204,10 @@ __global__ HZ_STREAM_BOUNDS void k_l_AR(const LArgs a) {
 }
 
 // AU and AR on a large system: the tile loop of the standalone product as
-// kSolSubs blocks of kSpBlock threads per block of the map (r~ loaded with the
+// pf = sol_subs(G) blocks of kSpBlock threads per block of the map (r~ loaded with the
 // tile, the product held in the LDS ring), one partial slot per sub-block.
 __global__ __launch_bounds__(kSpBlock) void k_l_AUt(const LArgs a) {
-    const SubBlock q = sub_block_of(a.bmap, a.G);
+    const SubBlock q = sub_block_of(a.bmap, a.G, a.pf);
     if (q.sys < 0 || a.sc[q.sys].done) return;
     const double2* __restrict__ uj = a.u[a.j];
     double2* __restrict__ un = a.u[a.j + 1];
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kSpBlock) void k_l_AUt(const LArgs a) {
 }
 
 __global__ __launch_bounds__(kSpBlock) void k_l_ARt(const LArgs a) {
-    const SubBlock q = sub_block_of(a.bmap, a.G);
+    const SubBlock q = sub_block_of(a.bmap, a.G, a.pf);
     if (q.sys < 0 || a.sc[q.sys].done) return;
     const double2* __restrict__ rj = a.r[a.j];
     double2* __restrict__ rn = a.r[a.j + 1];

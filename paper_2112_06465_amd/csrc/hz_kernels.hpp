@@ -527,7 +527,7 @@ struct SysMap {
 template <typename T> struct BicgArgs {
     int G;       // blocks of every solver launch (a multiple of 8, or < 8)
     int stride;  // partial component stride (>= pf G)
-    int pf = 1;  // partial slots per block in regions A and B (kSolSubs when the products run as sub-blocks)
+    int pf = 1;  // partial slots per block in regions A and B (sol_subs(G) when the products run as sub-blocks)
     const BlockMap* bmap;
     const SysMap* smap;
     int* ndone;  // systems finished so far

@@ -7,17 +7,16 @@
 // them, and under their 64-VGPR budget a product could not hold its results
 // back without spilling; its stores then sat in front of the next tile's
 // loads (one in-order counter tracks both).  These kernels run each logical
-// block of the solver's map as kSolSubs blocks of kSpBlock threads (half the
-// waves per CU, twice the registers per wave) through tile_loop with its LDS
-// ring: the epilogue operand of each row (rhat or s) is loaded with the
+// block of the solver's map as F = sol_subs(G) blocks of kSpBlock threads
+// (half the waves per CU at most, twice the registers per wave) through
+// tile_loop with its LDS ring: the epilogue operand of each row (rhat or s) is loaded with the
 // tile's matrix entries and the row's terms go into the block's dot products
 // as soon as the tile is summed, while the totals v (or t) are held for kHold
 // tiles and stored when the ring is flushed.  Sub-block j of logical block lb
-// takes 64-row tiles k' = kSolSubs k + j of its group's rows (K' = kSolSubs
-// K), and writes its partials to slot kSolSubs lb + j; the region's readers
-// sum kSolSubs slots per block (BicgArgs::pf), and the S kernel, which writes
-// the region's first component with the logical blocks, fills the extra
-// slots with zeros.  Sums are taken in a fixed order: results are bitwise
+// takes 64-row tiles k' = F k + j of its group's rows (K' = F K), and writes
+// its partials to slot F lb + j; the region's readers sum F slots per block
+// (BicgArgs::pf = F), and the S kernel, which writes the region's first
+// component with the logical blocks, fills the extra slots with zeros.  Sums are taken in a fixed order: results are bitwise
 // reproducible.
 #pragma once
 
@@ -25,26 +24,34 @@
 
 namespace hz {
 
-constexpr int kSolSubs = 2;  // product blocks per logical block of the solver's map
+constexpr int kSolSlots = 1024;  // partial slots per component that the sub-blocks of a launch may take
+
+// Product blocks per logical block of a map of G blocks: enough for about
+// kSolSlots blocks (four per CU, the residency that the tile loop's 36 KB of
+// LDS allows), at least 2 and at most 4, and F G <= max(2 G, kSolSlots).
+__host__ __device__ constexpr int sol_subs(int G) {
+    const int f = G > 0 ? kSolSlots / G : 4;
+    return f < 2 ? 2 : (f > 4 ? 4 : f);
+}
 
 struct SubBlock {
     int ls, sys;
     Rows rw;
 };
-// Sub-block of a launch of kSolSubs G blocks over the solver map `bmap` of G blocks.
-__device__ __forceinline__ SubBlock sub_block_of(const BlockMap* bmap, int G) {
+// Sub-block of a launch of F G blocks over the solver map `bmap` of G blocks.
+__device__ __forceinline__ SubBlock sub_block_of(const BlockMap* bmap, int G, int F) {
     SubBlock q;
-    q.ls = logical_block(blockIdx.x, kSolSubs * G);
-    const BlockMap m = bmap[q.ls / kSolSubs];
+    q.ls = logical_block(blockIdx.x, F * G);
+    const BlockMap m = bmap[q.ls / F];
     q.sys = m.sys;
     q.rw.x0 = m.x0;
     q.rw.x1 = m.x1;
-    q.rw.k = kSolSubs * m.k + q.ls % kSolSubs;
-    q.rw.K = kSolSubs * m.K;
+    q.rw.k = F * m.k + q.ls % F;
+    q.rw.K = F * m.K;
     return q;
 }
 template <typename T> __device__ __forceinline__ SubBlock sub_block(const BicgArgs<T>& a) {
-    return sub_block_of(a.bmap, a.G);
+    return sub_block_of(a.bmap, a.G, a.pf);
 }
 
 template <int K>
