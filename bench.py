@@ -733,6 +733,14 @@ def profile(what, steps, cache_dir):
                                          flags=hz.PRECOND_JACOBI | hz.X0_ZERO)
             torch.cuda.synchronize()
             print(what, "ms", round(1e3 * (time.perf_counter() - t0), 2), info, flush=True)
+    elif what == "solve-cabin-l8":
+        cab = Cabin(hz, torch, dev, cache_dir)
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            _, info = hz.zbicgstabl_solve(cab.rp, cab.ci, cab.vals, cab.b, ell=8, rtol=1e-10, maxcycles=5000,
+                                          flags=hz.PRECOND_JACOBI | hz.X0_ZERO)
+            torch.cuda.synchronize()
+            print(what, "ms", round(1e3 * (time.perf_counter() - t0), 2), info, flush=True)
     elif what == "solve-cabin-mixed":
         cab = Cabin(hz, torch, dev, cache_dir)
         for _ in range(steps):
@@ -822,7 +830,7 @@ def main():
     ap.add_argument("--cache", default=None, help="directory to keep generated workloads in (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--profile", default=None,
-                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-given-tiles | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | solve-cabin-mixed | solve-cylinder | "
+                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-given-tiles | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | solve-cabin-l8 | solve-cabin-mixed | solve-cylinder | "
                          "sweep-explicit | sweep-kmb | "
                          "adjoint-cylinder | stream | blas1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
