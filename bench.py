@@ -733,6 +733,22 @@ def profile(what, steps, cache_dir):
                                          flags=hz.PRECOND_JACOBI | hz.X0_ZERO)
             torch.cuda.synchronize()
             print(what, "ms", round(1e3 * (time.perf_counter() - t0), 2), info, flush=True)
+    elif what in ("spmv-cylinder", "spmv-cylinder-rows"):
+        import workloads as W
+
+        A, _, _ = W.config_cylinder()
+        n, nnz = A.n, A.nnz
+        rng = np.random.default_rng(3)
+        up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+        x = up(rng.standard_normal(n) + 1j * rng.standard_normal(n))
+        reps_ = [(up(A.row_ptr), up(A.col_idx), up(A.vals), x.clone(), torch.empty_like(x))
+                 for _ in range(CYL_REPLICAS)]
+        form = "tiles" if what == "spmv-cylinder" else "rows"
+        loop = ColdLoop(torch, lambda r: hz.csr_zspmv(*r), reps_, 30)
+        for _ in range(steps):
+            with PinnedForm(form, rule_lanes(n, nnz) if form == "rows" else None):
+                loop.enqueue()
+            print(what, "us per launch", round(loop.us(), 3), flush=True)
     elif what == "solve-cabin-l8":
         cab = Cabin(hz, torch, dev, cache_dir)
         for _ in range(steps):
@@ -830,7 +846,7 @@ def main():
     ap.add_argument("--cache", default=None, help="directory to keep generated workloads in (profiling runs)")
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--profile", default=None,
-                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-given-tiles | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | solve-cabin-l8 | solve-cabin-mixed | solve-cylinder | "
+                    help="spmv-cabin | spmv-cabin-rows | spmv-cabin-given | spmv-cabin-given-tiles | spmv-cabin-planned | spmv-cabin-ell | solve-cabin | solve-cabin-l8 | spmv-cylinder | spmv-cylinder-rows | solve-cabin-mixed | solve-cylinder | "
                          "sweep-explicit | sweep-kmb | "
                          "adjoint-cylinder | stream | blas1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
